@@ -1,0 +1,202 @@
+// Direct frequency-domain sum (Eq. inty_dft, Algorithm 1), the comparison path.
+//
+// A wavefront owns one pixel and 64 frequencies (one per lane) and a group of
+// particles.  Per chunk of 64 samples every lane evaluates one sample (arrival time
+// and E*kappa, the integrand of Eq. const_phase_drop) into LDS; then every lane
+// sweeps the 64 staged samples for its own frequency.  The phase w*(t_a - t0) is
+// formed in double and reduced to one revolution before sin/cos, so the float sin/cos
+// of the mixed mode never sees a large argument.  Partial sums of the wavefront go
+// to a double workspace with atomics; a final kernel forms S = (dt^2/2pi) sum_c |F_c|^2.
+#include "lw_internal.h"
+
+#include <algorithm>
+
+namespace lw {
+namespace {
+
+constexpr int kWavesPerBlock = 4;
+
+struct FdShape {
+    int64_t n_particles, n_samples, n_pix, n_omega;
+    int64_t n_wblocks, n_groups, parts_per_group;
+    double t_start, dt, t0, inv_cdt, cdt;
+    int fmask;
+};
+
+template <typename T, int GEOM>
+__global__ __launch_bounds__(256) void k_direct_fd(const double *__restrict__ r, const double *__restrict__ beta,
+                                                   const double *__restrict__ beta_dot,
+                                                   const double *__restrict__ charge, const double *__restrict__ x_det,
+                                                   const double *__restrict__ omega, double *__restrict__ acc,
+                                                   FdShape sh)
+{
+    __shared__ double s_ta[kWavesPerBlock][64];
+    __shared__ T s_ek[kWavesPerBlock][3][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+    const int64_t per_pix = sh.n_wblocks * sh.n_groups;
+    const int64_t m = wave / per_pix;
+    if (m >= sh.n_pix) return;  // whole wavefront idle; no block-level sync below
+    const int64_t rem = wave - m * per_pix;
+    const int64_t wb = rem / sh.n_groups, grp = rem - wb * sh.n_groups;
+    const int64_t w = wb * 64 + lane;
+    const bool w_ok = w < sh.n_omega;
+    const double nu = w_ok ? omega[w] / (2.0 * kPi) : 0.0;  // cycles per second
+    const int64_t k0 = grp * sh.parts_per_group, k1 = std::min(k0 + sh.parts_per_group, sh.n_particles);
+    PixGeo g = pix_geo(x_det, m, sh.inv_cdt);
+    const double *xm = x_det + 3 * m;
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;  // Re/Im of F_x, F_y, F_z
+    const int64_t ns = sh.n_samples;
+    for (int64_t k = k0; k < k1; ++k) {
+        const double q = charge ? charge[k] : -kQe;
+        for (int64_t i0 = 0; i0 < ns; i0 += 64) {
+            // stage: lane -> sample i0 + lane
+            {
+                const int64_t i = i0 + lane;
+                double ta = 0.0;
+                T ex = 0, ey = 0, ez = 0;
+                if (i < ns && g.ok) {
+                    const size_t s = (size_t)(k * ns + i) * 3;
+                    if (sample_usable(r + s, beta + s, beta_dot + s)) {
+                        double kap;
+                        lw_field<T, GEOM>(g, xm, r[s], r[s + 1], r[s + 2], beta[s], beta[s + 1], beta[s + 2],
+                                          beta_dot[s], beta_dot[s + 1], beta_dot[s + 2], q, sh.fmask, ex, ey, ez,
+                                          &kap);
+                        // arrival time relative to t0 (s): tau * dt_obs with dt_obs = cdt / c
+                        const double alpha = ((sh.t_start + (double)i * sh.dt) - sh.t0) / (sh.cdt / kC);
+                        ta = arrival_tau<GEOM>(g, alpha, r[s], r[s + 1], r[s + 2], sh.cdt) * (sh.cdt / kC);
+                        const T tk = (T)kap;
+                        ex *= tk;
+                        ey *= tk;
+                        ez *= tk;
+                        if (!(isfinite(ta) && isfinite((double)ex) && isfinite((double)ey) && isfinite((double)ez))) {
+                            ta = 0.0;
+                            ex = ey = ez = 0;
+                        }
+                    }
+                }
+                s_ta[wv][lane] = ta;
+                s_ek[wv][0][lane] = ex;
+                s_ek[wv][1][lane] = ey;
+                s_ek[wv][2][lane] = ez;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const int cnt = (int)std::min<int64_t>(64, ns - i0);
+            T b0 = 0, b1 = 0, b2 = 0, b3 = 0, b4 = 0, b5 = 0;
+            for (int j = 0; j < cnt; ++j) {
+                const double x = nu * s_ta[wv][j];
+                const double fr = x - floor(x);  // revolutions in [0, 1)
+                T c, sn;
+                if (sizeof(T) == 4) {
+                    const float f = (float)fr;
+                    c = (T)__builtin_amdgcn_cosf(f);
+                    sn = (T)__builtin_amdgcn_sinf(f);
+                } else {
+                    double sd, cd;
+                    sincospi(2.0 * fr, &sd, &cd);
+                    c = (T)cd;
+                    sn = (T)sd;
+                }
+                const T e0 = s_ek[wv][0][j], e1 = s_ek[wv][1][j], e2 = s_ek[wv][2][j];
+                b0 += e0 * c;
+                b1 += e0 * sn;
+                b2 += e1 * c;
+                b3 += e1 * sn;
+                b4 += e2 * c;
+                b5 += e2 * sn;
+            }
+            a0 += (double)b0;
+            a1 += (double)b1;
+            a2 += (double)b2;
+            a3 += (double)b3;
+            a4 += (double)b4;
+            a5 += (double)b5;
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (w_ok && k1 > k0) {
+        double *o = acc + ((size_t)m * sh.n_omega + w) * 6;
+        atomicAdd(o + 0, a0);
+        atomicAdd(o + 1, a1);
+        atomicAdd(o + 2, a2);
+        atomicAdd(o + 3, a3);
+        atomicAdd(o + 4, a4);
+        atomicAdd(o + 5, a5);
+    }
+}
+
+__global__ void k_fd_zero(double *__restrict__ p, int64_t n)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        p[j] = 0.0;
+}
+
+__global__ void k_fd_finish(const double *__restrict__ acc, double *__restrict__ S, int64_t n, double f)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const double *a = acc + 6 * j;
+        S[j] = f * (a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + a[3] * a[3] + a[4] * a[4] + a[5] * a[5]);
+    }
+}
+
+}  // namespace
+
+size_t direct_fd_ws_bytes(int64_t n_pix, int64_t n_omega)
+{
+    return (size_t)std::max<int64_t>(n_pix * n_omega, 1) * 6 * sizeof(double);
+}
+
+lw_status launch_direct_fd(const lw_traj_t *t, const lw_grid_t *gr, const double *omega, int64_t n_omega, int prec,
+                           int fmask, int geom, double *S, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    const int64_t n_pix = gr->n_pix;
+    const int64_t nS = n_pix * n_omega;
+    if (nS == 0) return LW_OK;
+    double *acc = (double *)ws;
+    k_fd_zero<<<(int)std::min<int64_t>((6 * nS + 255) / 256, 65536), 256, 0, s>>>(acc, 6 * nS);
+    FdShape sh;
+    sh.n_particles = t->n_particles;
+    sh.n_samples = t->n_samples;
+    sh.n_pix = n_pix;
+    sh.n_omega = n_omega;
+    sh.n_wblocks = (n_omega + 63) / 64;
+    const int64_t base = n_pix * sh.n_wblocks;
+    int64_t groups = std::max<int64_t>(1, (8192 + base - 1) / base);
+    groups = std::min<int64_t>(groups, std::max<int64_t>(t->n_particles, 1));
+    sh.parts_per_group = (std::max<int64_t>(t->n_particles, 1) + groups - 1) / groups;
+    sh.n_groups = (std::max<int64_t>(t->n_particles, 1) + sh.parts_per_group - 1) / sh.parts_per_group;
+    sh.t_start = t->t_start;
+    sh.dt = t->dt;
+    sh.t0 = gr->t0;
+    // any positive grid step gives the same arrival times; use dt (the grid of this call is irrelevant)
+    const double dts = t->dt;
+    sh.cdt = kC * dts;
+    sh.inv_cdt = 1.0 / sh.cdt;
+    sh.fmask = fmask;
+    if (t->n_particles > 0) {
+        const int64_t waves = base * sh.n_groups;
+        const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+        if (blocks > 0x7fffffff) return fail(LW_E_SHAPE, "lw_direct_fd: problem too large for one launch");
+        if (prec == LW_PREC_FP64) {
+            if (geom == LW_GEOM_EXACT)
+                k_direct_fd<double, LW_GEOM_EXACT><<<(unsigned)blocks, 256, 0, s>>>(
+                    t->r, t->beta, t->beta_dot, t->charge, gr->x_det, omega, acc, sh);
+            else
+                k_direct_fd<double, LW_GEOM_FARFIELD><<<(unsigned)blocks, 256, 0, s>>>(
+                    t->r, t->beta, t->beta_dot, t->charge, gr->x_det, omega, acc, sh);
+        } else {
+            if (geom == LW_GEOM_EXACT)
+                k_direct_fd<float, LW_GEOM_EXACT><<<(unsigned)blocks, 256, 0, s>>>(
+                    t->r, t->beta, t->beta_dot, t->charge, gr->x_det, omega, acc, sh);
+            else
+                k_direct_fd<float, LW_GEOM_FARFIELD><<<(unsigned)blocks, 256, 0, s>>>(
+                    t->r, t->beta, t->beta_dot, t->charge, gr->x_det, omega, acc, sh);
+        }
+    }
+    const double f = t->dt * t->dt / (2.0 * kPi);
+    k_fd_finish<<<(int)std::min<int64_t>((nS + 255) / 256, 65536), 256, 0, s>>>(acc, S, nS, f);
+    return check_launch("lw_direct_fd");
+}
+
+}  // namespace lw

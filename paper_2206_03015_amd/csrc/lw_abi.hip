@@ -1,0 +1,205 @@
+// extern "C" entry points of liblw.so: argument validation, workspace checks, dispatch.
+#include "lw_internal.h"
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+namespace lw {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+lw_status fail(lw_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+lw_status check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(LW_E_HIP, "%s: %s", what, hipGetErrorString(e));
+    g_err[0] = 0;
+    return LW_OK;
+}
+
+namespace {
+
+constexpr int64_t kMaxSamples = int64_t(1) << 31;
+
+bool finite_pos(double v) { return v > 0.0 && v < 1e300; }
+
+lw_status check_traj_samples(const lw_traj_t *t, const char *fn)
+{
+    if (!t) return fail(LW_E_ARG, "%s: traj is NULL", fn);
+    if (t->kind != LW_TRAJ_SAMPLES)
+        return fail(LW_E_UNSUPPORTED, "%s: traj->kind must be LW_TRAJ_SAMPLES", fn);
+    if (t->reserved != 0) return fail(LW_E_ARG, "%s: traj->reserved must be 0", fn);
+    if (t->n_particles < 0 || t->n_samples < 1 || t->n_samples >= kMaxSamples)
+        return fail(LW_E_SHAPE, "%s: need n_particles >= 0 and 1 <= n_samples < 2^31 (got %lld, %lld)", fn,
+                    (long long)t->n_particles, (long long)t->n_samples);
+    if (!finite_pos(t->dt) || !(t->t_start > -1e300 && t->t_start < 1e300))
+        return fail(LW_E_ARG, "%s: dt must be positive and finite, t_start finite", fn);
+    if (t->n_particles > 0) {
+        if (!t->r || !t->beta || !t->beta_dot) return fail(LW_E_ARG, "%s: r, beta, beta_dot must be non-NULL", fn);
+        if (!aligned(t->r, 8) || !aligned(t->beta, 8) || !aligned(t->beta_dot, 8) ||
+            (t->charge && !aligned(t->charge, 8)))
+            return fail(LW_E_ALIGN, "%s: trajectory arrays must be 8-byte aligned", fn);
+    }
+    return LW_OK;
+}
+
+lw_status check_grid(const lw_grid_t *g, const char *fn, bool need_grid)
+{
+    if (!g) return fail(LW_E_ARG, "%s: grid is NULL", fn);
+    if (g->n_pix < 0) return fail(LW_E_SHAPE, "%s: n_pix < 0", fn);
+    if (g->n_pix > 0 && !g->x_det) return fail(LW_E_ARG, "%s: x_det is NULL", fn);
+    if (g->x_det && !aligned(g->x_det, 8)) return fail(LW_E_ALIGN, "%s: x_det must be 8-byte aligned", fn);
+    if (!(g->t0 > -1e300 && g->t0 < 1e300)) return fail(LW_E_ARG, "%s: t0 must be finite", fn);
+    if (need_grid) {
+        if (!finite_pos(g->dt_obs)) return fail(LW_E_ARG, "%s: dt_obs must be positive and finite", fn);
+        if (g->n_obs < 1 || g->n_obs > (int64_t(1) << 40)) return fail(LW_E_SHAPE, "%s: n_obs out of range", fn);
+    }
+    return LW_OK;
+}
+
+bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+}  // namespace lw
+
+using namespace lw;
+
+extern "C" {
+
+const char *lw_last_error(void) { return g_err; }
+
+const char *lw_version(void) { return "liblw 0.1 (gfx950)"; }
+
+size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec)
+{
+    switch (which) {
+    case LW_WS_DEPOSIT:
+    case LW_WS_DEPOSIT_BWD:
+        return deposit_ws_bytes(n_a, n_b);
+    case LW_WS_FFT:
+    case LW_WS_FFT_BWD:
+        return fft_ws_bytes(n_a, n_b, prec);
+    case LW_WS_DIRECT_FD:
+        return direct_fd_ws_bytes(n_a, n_b);
+    default:
+        return 0;
+    }
+}
+
+lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom, void *E,
+                        int64_t *diag, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    const char *fn = "lw_deposit_td";
+    lw_status st = check_traj_samples(traj, fn);
+    if (st != LW_OK) return st;
+    if ((st = check_grid(grid, fn, true)) != LW_OK) return st;
+    if (prec != LW_PREC_FP64 && prec != LW_PREC_MIXED) return fail(LW_E_ARG, "%s: unknown prec %d", fn, prec);
+    if (field_mask <= 0 || (field_mask & ~(LW_FIELD_ACCEL | LW_FIELD_VELOCITY)))
+        return fail(LW_E_ARG, "%s: field_mask must be a non-empty combination of LW_FIELD_*", fn);
+    const bool acc = (geom & LW_ACCUMULATE) != 0;
+    const int g = geom & ~LW_ACCUMULATE;
+    if (g != LW_GEOM_EXACT && g != LW_GEOM_FARFIELD) return fail(LW_E_ARG, "%s: unknown geometry %d", fn, g);
+    if (grid->n_pix > 0 && !E) return fail(LW_E_ARG, "%s: E is NULL", fn);
+    if (E && !aligned(E, 16)) return fail(LW_E_ALIGN, "%s: E must be 16-byte aligned", fn);
+    if (diag && !aligned(diag, 8)) return fail(LW_E_ALIGN, "%s: diag must be 8-byte aligned", fn);
+    if (grid->n_pix > (int64_t(1) << 31) || traj->n_particles > (int64_t(1) << 40))
+        return fail(LW_E_SHAPE, "%s: too many pixels or particles", fn);
+    const size_t need = deposit_ws_bytes(traj->n_particles, traj->n_samples);
+    if (traj->n_particles > 0 && grid->n_pix > 0 && (!ws || ws_bytes < need))
+        return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes < %zu needed", fn, ws_bytes, need);
+    if (ws && !aligned(ws, 256)) return fail(LW_E_ALIGN, "%s: workspace must be 256-byte aligned", fn);
+    return launch_deposit(traj, grid, prec, field_mask, g, acc, E, diag, ws, ws_bytes, stream);
+}
+
+lw_status lw_spectrum_fft(const void *E, int64_t n_pix, int64_t n_obs, double dt_obs, int prec, void *S, void *ws,
+                          size_t ws_bytes, hipStream_t stream)
+{
+    const char *fn = "lw_spectrum_fft";
+    if (prec != LW_PREC_FP64 && prec != LW_PREC_MIXED) return fail(LW_E_ARG, "%s: unknown prec %d", fn, prec);
+    if (n_pix < 0) return fail(LW_E_SHAPE, "%s: n_pix < 0", fn);
+    if (!pow2(n_obs) || n_obs < 4 || n_obs > (int64_t(1) << 22))
+        return fail(LW_E_SHAPE, "%s: n_obs must be a power of two in [4, 2^22] (got %lld)", fn, (long long)n_obs);
+    if (!finite_pos(dt_obs)) return fail(LW_E_ARG, "%s: dt_obs must be positive and finite", fn);
+    if (n_pix > 0 && (!E || !S)) return fail(LW_E_ARG, "%s: E and S must be non-NULL", fn);
+    if ((E && !aligned(E, 16)) || (S && !aligned(S, 16)) || (ws && !aligned(ws, 256)))
+        return fail(LW_E_ALIGN, "%s: E, S must be 16-byte and ws 256-byte aligned", fn);
+    return launch_fft(E, n_pix, n_obs, dt_obs, prec, S, ws, ws_bytes, stream);
+}
+
+lw_status lw_direct_fd(const lw_traj_t *traj, const lw_grid_t *grid, const double *omega, int64_t n_omega, int prec,
+                       int field_mask, int geom, double *S, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    const char *fn = "lw_direct_fd";
+    lw_status st = check_traj_samples(traj, fn);
+    if (st != LW_OK) return st;
+    if ((st = check_grid(grid, fn, false)) != LW_OK) return st;
+    if (prec != LW_PREC_FP64 && prec != LW_PREC_MIXED) return fail(LW_E_ARG, "%s: unknown prec %d", fn, prec);
+    if (field_mask <= 0 || (field_mask & ~(LW_FIELD_ACCEL | LW_FIELD_VELOCITY)))
+        return fail(LW_E_ARG, "%s: field_mask must be a non-empty combination of LW_FIELD_*", fn);
+    if (geom != LW_GEOM_EXACT && geom != LW_GEOM_FARFIELD) return fail(LW_E_ARG, "%s: unknown geometry %d", fn, geom);
+    if (n_omega < 0) return fail(LW_E_SHAPE, "%s: n_omega < 0", fn);
+    if (n_omega > 0 && !omega) return fail(LW_E_ARG, "%s: omega is NULL", fn);
+    if (n_omega > 0 && grid->n_pix > 0 && !S) return fail(LW_E_ARG, "%s: S is NULL", fn);
+    if ((omega && !aligned(omega, 8)) || (S && !aligned(S, 8)) || (ws && !aligned(ws, 256)))
+        return fail(LW_E_ALIGN, "%s: misaligned pointer", fn);
+    const size_t need = direct_fd_ws_bytes(grid->n_pix, n_omega);
+    if (n_omega > 0 && grid->n_pix > 0 && (!ws || ws_bytes < need))
+        return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes < %zu needed", fn, ws_bytes, need);
+    return launch_direct_fd(traj, grid, omega, n_omega, prec, field_mask, geom, S, ws, ws_bytes, stream);
+}
+
+lw_status lw_trajectory_boris(const lw_traj_t *traj, double *r, double *beta, double *beta_dot, hipStream_t stream)
+{
+    const char *fn = "lw_trajectory_boris";
+    if (!traj) return fail(LW_E_ARG, "%s: traj is NULL", fn);
+    if (traj->kind != LW_TRAJ_BORIS) return fail(LW_E_ARG, "%s: traj->kind must be LW_TRAJ_BORIS", fn);
+    if (traj->n_particles < 0 || traj->n_samples < 1 || traj->n_samples >= (int64_t(1) << 31))
+        return fail(LW_E_SHAPE, "%s: bad sizes", fn);
+    if (!finite_pos(traj->dt)) return fail(LW_E_ARG, "%s: dt must be positive and finite", fn);
+    const lw_laser_t &L = traj->laser;
+    if (!finite_pos(L.lambda) || !(L.n_cycles > 0.0) || !(L.a0 >= 0.0 && L.a0 < 1e6) || !(L.w0 < 1e300))
+        return fail(LW_E_ARG, "%s: laser parameters out of range", fn);
+    if (traj->n_particles > 0 && (!traj->init || !r || !beta || !beta_dot))
+        return fail(LW_E_ARG, "%s: NULL array", fn);
+    if ((traj->init && !aligned(traj->init, 8)) || (r && !aligned(r, 8)) || (beta && !aligned(beta, 8)) ||
+        (beta_dot && !aligned(beta_dot, 8)))
+        return fail(LW_E_ALIGN, "%s: arrays must be 8-byte aligned", fn);
+    return launch_boris(traj, r, beta, beta_dot, stream);
+}
+
+lw_status lw_spectrum_fft_bwd(const void *, const void *, int64_t, int64_t, double, int, void *, void *, size_t,
+                              hipStream_t)
+{
+    return fail(LW_E_UNSUPPORTED, "lw_spectrum_fft_bwd: not built yet");
+}
+
+lw_status lw_deposit_td_bwd(const lw_traj_t *, const lw_grid_t *, int, int, int, const void *, double *, double *,
+                            double *, void *, size_t, hipStream_t)
+{
+    return fail(LW_E_UNSUPPORTED, "lw_deposit_td_bwd: not built yet");
+}
+
+lw_status lw_direct_fd_bwd(const lw_traj_t *, const lw_grid_t *, const double *, int64_t, int, int, int,
+                           const double *, double *, double *, double *, void *, size_t, hipStream_t)
+{
+    return fail(LW_E_UNSUPPORTED, "lw_direct_fd_bwd: not built yet");
+}
+
+}  // extern "C"

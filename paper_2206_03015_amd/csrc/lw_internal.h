@@ -1,0 +1,155 @@
+// Internal declarations of liblw.so (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/lw.h"
+
+namespace lw {
+
+// CODATA 2018 (SI)
+constexpr double kC = 299792458.0;
+constexpr double kQe = 1.602176634e-19;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kMe = 9.1093837015e-31;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kCoulomb = 1.0 / (4.0 * kPi * kEps0);
+
+// error reporting (thread-local message, see lw_last_error)
+void set_error(const char *fmt, ...);
+lw_status fail(lw_status st, const char *fmt, ...);
+lw_status check_launch(const char *what);
+
+inline bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+// ---------------------------------------------------------------------------------------------
+// Pixel geometry, shared by the arrival-time and field evaluations.
+struct PixGeo {
+    double nx, ny, nz;  // unit direction x_m / |x_m|
+    double D;           // |x_m|
+    double sx, sy, sz;  // n / (c dt_obs): arrival shift per metre, in grid units
+    bool ok;
+};
+
+__device__ __forceinline__ PixGeo pix_geo(const double *x_det, int64_t m, double inv_cdt)
+{
+    PixGeo g;
+    double x = x_det[3 * m], y = x_det[3 * m + 1], z = x_det[3 * m + 2];
+    double D = sqrt(x * x + y * y + z * z);
+    g.ok = (D > 0.0) && isfinite(D);
+    if (!g.ok) D = 1.0, x = 0.0, y = 0.0, z = 1.0;
+    g.nx = x / D;
+    g.ny = y / D;
+    g.nz = z / D;
+    g.D = D;
+    g.sx = g.nx * inv_cdt;
+    g.sy = g.ny * inv_cdt;
+    g.sz = g.nz * inv_cdt;
+    return g;
+}
+
+// Arrival time in grid units, tau = alpha_i - n.r/(c dt_obs) [+ exact-geometry correction],
+// alpha_i = (t_i - t0)/dt_obs.  The exact correction uses
+// |x - r| - |x| = -n.r + |r_perp|^2 / (|x - r| + |x| - n.r),  r_perp = r - (n.r) n,
+// which has no cancellation.  Written with explicit fma so that every caller that
+// evaluates the same (pixel, sample) gets the same bits.
+template <int GEOM>
+__device__ __forceinline__ double arrival_tau(const PixGeo &g, double alpha, double rx, double ry, double rz,
+                                              double cdt)
+{
+    double tau = fma(-g.sz, rz, alpha);
+    tau = fma(-g.sy, ry, tau);
+    tau = fma(-g.sx, rx, tau);
+    if (GEOM == LW_GEOM_EXACT) {
+        double s = fma(g.nz, rz, fma(g.ny, ry, g.nx * rx));
+        double px = fma(-s, g.nx, rx), py = fma(-s, g.ny, ry), pz = fma(-s, g.nz, rz);
+        double p2 = fma(pz, pz, fma(py, py, px * px));
+        double ds = g.D - s;
+        double R = sqrt(fma(ds, ds, p2));
+        tau += p2 / (cdt * (R + ds));
+    }
+    return tau;
+}
+
+// Single-precision variant of the exact correction is not used: tau is always double.
+
+// Lienard-Wiechert field of one sample at one pixel.  Geometry (n, R, n - beta, kappa) in
+// double; the field arithmetic in T.  kappa = 1 - n.b is formed as (1-b^2)/(1+|b|) + |b||n - b^|^2/2.
+template <typename T, int GEOM>
+__device__ __forceinline__ void lw_field(const PixGeo &g, const double *xm, double rx, double ry, double rz,
+                                         double bx, double by, double bz, double ax, double ay, double az, double q,
+                                         int fmask, T &Ex, T &Ey, T &Ez, double *kappa_out = nullptr)
+{
+    double nx, ny, nz, R;
+    if (GEOM == LW_GEOM_EXACT) {
+        double dx = xm[0] - rx, dy = xm[1] - ry, dz = xm[2] - rz;
+        R = sqrt(dx * dx + dy * dy + dz * dz);
+        nx = dx / R;
+        ny = dy / R;
+        nz = dz / R;
+    } else {
+        nx = g.nx;
+        ny = g.ny;
+        nz = g.nz;
+        R = g.D;
+    }
+    double b2 = bx * bx + by * by + bz * bz;
+    double bn = sqrt(b2);
+    double kappa = 1.0;
+    if (bn > 0.0) {
+        double ib = 1.0 / bn;
+        double dx = nx - bx * ib, dy = ny - by * ib, dz = nz - bz * ib;
+        kappa = (1.0 - b2) / (1.0 + bn) + 0.5 * bn * (dx * dx + dy * dy + dz * dz);
+    }
+    if (kappa_out) *kappa_out = kappa;
+    T k = (T)kappa;
+    T ik3 = (T)1 / (k * k * k);
+    T pref = (T)(q * kCoulomb);
+    T tnx = (T)nx, tny = (T)ny, tnz = (T)nz;
+    // n - beta in double: n_z - beta_z ~ 1/(2 gamma^2) would lose most of its bits in float
+    T mx = (T)(nx - bx), my = (T)(ny - by), mz = (T)(nz - bz);
+    Ex = Ey = Ez = (T)0;
+    if (fmask & LW_FIELD_VELOCITY) {
+        T f = pref * (T)(1.0 - b2) * ik3 / (T)(R * R);
+        Ex += f * mx;
+        Ey += f * my;
+        Ez += f * mz;
+    }
+    if (fmask & LW_FIELD_ACCEL) {
+        T tax = (T)ax, tay = (T)ay, taz = (T)az;
+        // w = (n - b) x bd ; v = n x w
+        T wx = my * taz - mz * tay, wy = mz * tax - mx * taz, wz = mx * tay - my * tax;
+        T vx = tny * wz - tnz * wy, vy = tnz * wx - tnx * wz, vz = tnx * wy - tny * wx;
+        T f = pref * ik3 / (T)(kC * R);
+        Ex += f * vx;
+        Ey += f * vy;
+        Ez += f * vz;
+    }
+}
+
+__device__ __forceinline__ bool sample_usable(const double *r, const double *b, const double *a)
+{
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ok = ok && isfinite(r[c]) && isfinite(b[c]) && isfinite(a[c]);
+    return ok && (b[0] * b[0] + b[1] * b[1] + b[2] * b[2] < 1.0);
+}
+
+__device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+// host-side launch helpers (defined in the kernel files)
+lw_status launch_deposit(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom,
+                         bool accumulate, void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s);
+size_t deposit_ws_bytes(int64_t n_particles, int64_t n_samples);
+lw_status launch_fft(const void *E, int64_t n_pix, int64_t n_obs, double dt_obs, int prec, void *S, void *ws,
+                     size_t ws_bytes, hipStream_t s);
+size_t fft_ws_bytes(int64_t n_pix, int64_t n_obs, int prec);
+lw_status launch_direct_fd(const lw_traj_t *traj, const lw_grid_t *grid, const double *omega, int64_t n_omega,
+                           int prec, int field_mask, int geom, double *S, void *ws, size_t ws_bytes, hipStream_t s);
+size_t direct_fd_ws_bytes(int64_t n_pix, int64_t n_omega);
+lw_status launch_boris(const lw_traj_t *traj, double *r, double *beta, double *beta_dot, hipStream_t s);
+
+}  // namespace lw

@@ -192,18 +192,19 @@ def workload(key) -> Workload:
 
 
 def random_trajectory(n_p: int, n_samples: int, seed: int, dt: float = 1e-18, gamma: float = 20.0,
-                      wiggle: float = 1e-3):
+                      wiggle: float = 1e-3, spread: float = 1e-6):
     """Smooth synthetic trajectories for kernel tests that need no particular physics:
     r, beta, beta_dot [n_p][n_samples][3] with |beta| < 1 and |r_i - r_{i-1}| < c dt.
     Each particle moves along +z at speed ~ (1 - 1/(2 gamma^2)) c with a small sinusoidal
-    transverse wiggle of seeded amplitude, phase and period.  beta_dot is the
+    transverse wiggle of seeded amplitude, phase and period, starting from a seeded offset
+    of rms size ``spread`` (m).  beta_dot is the
     time derivative of the wiggle (consistent to the sampling)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     t = np.arange(n_samples) * dt
     amp = wiggle * (0.5 + rng.random((n_p, 2)))
     per = dt * n_samples / (3.0 + 5.0 * rng.random((n_p, 1)))
     ph = 2.0 * np.pi * rng.random((n_p, 2))
-    off = 1e-6 * rng.standard_normal((n_p, 3))
+    off = spread * rng.standard_normal((n_p, 3))
     w = 2.0 * np.pi / per
     bx = amp[:, :1] * np.sin(w * t[None] + ph[:, :1])
     by = amp[:, 1:] * np.sin(w * t[None] + ph[:, 1:])

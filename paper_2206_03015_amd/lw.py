@@ -1,0 +1,230 @@
+"""Thin ctypes binding of liblw.so (include/lw.h).
+
+Argument marshalling only: tensors are passed as device pointers, the stream is
+torch's current stream, and workspaces are allocated with torch.  Every step of
+the hot path runs inside the library's HIP kernels.  There is no fallback: if
+liblw.so is missing or fails to load, ``load()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime liblw.so binds to)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblw.so")
+
+LW_OK = 0
+PREC = {"fp64": 0, "mixed": 1}
+FIELD_ACCEL = 1
+FIELD_VELOCITY = 2
+GEOM = {"exact": 0, "farfield": 1}
+ACCUMULATE = 1 << 8
+TRAJ_SAMPLES = 0
+TRAJ_BORIS = 1
+WS_DEPOSIT, WS_FFT, WS_DIRECT_FD, WS_DEPOSIT_BWD, WS_FFT_BWD = 1, 2, 3, 4, 5
+
+c_d = ctypes.c_double
+c_i64 = ctypes.c_int64
+c_vp = ctypes.c_void_p
+
+
+class Laser(ctypes.Structure):
+    _fields_ = [("a0", c_d), ("lam", c_d), ("w0", c_d), ("n_cycles", c_d)]
+
+
+class Traj(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n_particles", c_i64),
+                ("n_samples", c_i64), ("t_start", c_d), ("dt", c_d), ("r", c_vp), ("beta", c_vp),
+                ("beta_dot", c_vp), ("init", c_vp), ("laser", Laser), ("charge", c_vp)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("n_pix", c_i64), ("x_det", c_vp), ("t0", c_d), ("dt_obs", c_d), ("n_obs", c_i64)]
+
+
+class LWError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"liblw status {status}: {msg}")
+        self.status = status
+
+
+# every function declared in include/lw.h, with its ctypes signature
+_SIGS = {
+    "lw_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, c_i64, c_i64, ctypes.c_int]),
+    "lw_deposit_td": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "lw_spectrum_fft": (ctypes.c_int, [c_vp, c_i64, c_i64, c_d, ctypes.c_int, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "lw_direct_fd": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), c_vp, c_i64, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "lw_trajectory_boris": (ctypes.c_int, [ctypes.POINTER(Traj), c_vp, c_vp, c_vp, c_vp]),
+    "lw_spectrum_fft_bwd": (ctypes.c_int, [c_vp, c_vp, c_i64, c_i64, c_d, ctypes.c_int, c_vp, c_vp,
+                                           ctypes.c_size_t, c_vp]),
+    "lw_deposit_td_bwd": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "lw_direct_fd_bwd": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), c_vp, c_i64, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t,
+                                        c_vp]),
+    "lw_last_error": (ctypes.c_char_p, []),
+    "lw_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load liblw.so (raises if it is missing: there is no other implementation)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing; build it with `python -m paper_2206_03015_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status):
+    if status != LW_OK:
+        raise LWError(status, load().lw_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def workspace_bytes(which, n_a, n_b, prec="mixed"):
+    return int(load().lw_workspace_bytes(which, int(n_a), int(n_b), PREC[prec]))
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def make_traj(r, beta, beta_dot, t_start, dt, charge=None):
+    """Traj struct over sample tensors [n_p][n_samples][3] (float64, device)."""
+    n_p, ns = int(r.shape[0]), int(r.shape[1])
+    for t, nm in ((r, "r"), (beta, "beta"), (beta_dot, "beta_dot")):
+        _need(t, torch.float64, (n_p, ns, 3), nm)
+    if charge is not None:
+        _need(charge, torch.float64, (n_p,), "charge")
+    tr = Traj()
+    tr.kind = TRAJ_SAMPLES
+    tr.reserved = 0
+    tr.n_particles = n_p
+    tr.n_samples = ns
+    tr.t_start = float(t_start)
+    tr.dt = float(dt)
+    tr.r, tr.beta, tr.beta_dot = (c_vp(t.data_ptr()) for t in (r, beta, beta_dot))
+    tr.init = None
+    tr.charge = None if charge is None else c_vp(charge.data_ptr())
+    return tr
+
+
+def make_grid(x_det, t0, dt_obs, n_obs):
+    _need(x_det, torch.float64, (int(x_det.shape[0]), 3), "x_det")
+    g = Grid()
+    g.n_pix = int(x_det.shape[0])
+    g.x_det = c_vp(x_det.data_ptr())
+    g.t0 = float(t0)
+    g.dt_obs = float(dt_obs)
+    g.n_obs = int(n_obs)
+    return g
+
+
+def deposit_td(r, beta, beta_dot, t_start, dt, x_det, t0, dt_obs, n_obs, prec="mixed", field_mask=FIELD_ACCEL,
+               geom="exact", charge=None, out=None, accumulate=False, diag=None, ws=None):
+    """lw_deposit_td.  Returns (E [n_pix][3][n_obs], diag int64[4])."""
+    lib = load()
+    tr = make_traj(r, beta, beta_dot, t_start, dt, charge)
+    gr = make_grid(x_det, t0, dt_obs, n_obs)
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    if out is None:
+        out = torch.empty((gr.n_pix, 3, int(n_obs)), dtype=dtype, device=r.device)
+    _need(out, dtype, (gr.n_pix, 3, int(n_obs)), "E")
+    if diag is None:
+        diag = torch.zeros(4, dtype=torch.int64, device=r.device)
+    need = workspace_bytes(WS_DEPOSIT, tr.n_particles, tr.n_samples, prec)
+    if ws is None:
+        ws = _workspace(need, r.device)
+    flags = GEOM[geom] | (ACCUMULATE if accumulate else 0)
+    _check(lib.lw_deposit_td(ctypes.byref(tr), ctypes.byref(gr), PREC[prec], int(field_mask), flags, _ptr(out),
+                             _ptr(diag), _ptr(ws), ws.numel(), _stream()))
+    return out, diag
+
+
+def spectrum_fft(E, dt_obs, prec=None, out=None, ws=None):
+    """lw_spectrum_fft.  E [n_pix][3][n_obs] float32 (mixed) or float64 (fp64)."""
+    lib = load()
+    if prec is None:
+        prec = "fp64" if E.dtype == torch.float64 else "mixed"
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    n_pix, _, n_obs = (int(v) for v in E.shape)
+    _need(E, dtype, (n_pix, 3, n_obs), "E")
+    if out is None:
+        out = torch.empty((n_pix, n_obs // 2 + 1), dtype=dtype, device=E.device)
+    _need(out, dtype, (n_pix, n_obs // 2 + 1), "S")
+    if ws is None:
+        ws = _workspace(workspace_bytes(WS_FFT, n_pix, n_obs, prec), E.device)
+    _check(lib.lw_spectrum_fft(_ptr(E), n_pix, n_obs, float(dt_obs), PREC[prec], _ptr(out), _ptr(ws), ws.numel(),
+                               _stream()))
+    return out
+
+
+def direct_fd(r, beta, beta_dot, t_start, dt, x_det, t0, omega, prec="mixed", field_mask=FIELD_ACCEL,
+              geom="exact", charge=None, out=None, ws=None):
+    """lw_direct_fd.  Returns S [n_pix][n_omega] float64."""
+    lib = load()
+    tr = make_traj(r, beta, beta_dot, t_start, dt, charge)
+    gr = make_grid(x_det, t0, 1.0, 1)
+    _need(omega, torch.float64, (int(omega.shape[0]),), "omega")
+    n_w = int(omega.shape[0])
+    if out is None:
+        out = torch.empty((gr.n_pix, n_w), dtype=torch.float64, device=r.device)
+    _need(out, torch.float64, (gr.n_pix, n_w), "S")
+    if ws is None:
+        ws = _workspace(workspace_bytes(WS_DIRECT_FD, gr.n_pix, n_w, prec), r.device)
+    _check(lib.lw_direct_fd(ctypes.byref(tr), ctypes.byref(gr), _ptr(omega), n_w, PREC[prec], int(field_mask),
+                            GEOM[geom], _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def trajectory_boris(init, n_samples, t_start, dt, a0, lam, w0, n_cycles, out=None):
+    """lw_trajectory_boris.  init [n_p][6] float64 device.  Returns (r, beta, beta_dot)."""
+    lib = load()
+    n_p = int(init.shape[0])
+    _need(init, torch.float64, (n_p, 6), "init")
+    tr = Traj()
+    tr.kind = TRAJ_BORIS
+    tr.reserved = 0
+    tr.n_particles = n_p
+    tr.n_samples = int(n_samples)
+    tr.t_start = float(t_start)
+    tr.dt = float(dt)
+    tr.init = c_vp(init.data_ptr())
+    tr.laser = Laser(float(a0), float(lam), float(w0), float(n_cycles))
+    if out is None:
+        out = tuple(torch.empty((n_p, int(n_samples), 3), dtype=torch.float64, device=init.device) for _ in range(3))
+    r, b, bd = out
+    _check(lib.lw_trajectory_boris(ctypes.byref(tr), _ptr(r), _ptr(b), _ptr(bd), _stream()))
+    return r, b, bd

@@ -1,0 +1,92 @@
+"""The C-ABI library loads and exports every entry point that include/lw.h declares
+(no GPU needed: only host-side calls)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lw.h")
+LIB = os.path.join(ROOT, "paper_2206_03015_amd", "liblw.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ ]*?\**\s*\b(lw_[a-z0-9_]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("liblw.so is not built (run __graft_entry__.build())")
+    from paper_2206_03015_amd import lw
+    return lw.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("lw_deposit_td", "lw_spectrum_fft", "lw_direct_fd", "lw_deposit_td_bwd", "lw_spectrum_fft_bwd",
+              "lw_direct_fd_bwd", "lw_trajectory_boris", "lw_workspace_bytes", "lw_last_error"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for n in declared_functions():
+        assert n in exported, n
+        assert getattr(lib, n) is not None
+
+
+def test_binding_covers_the_header():
+    from paper_2206_03015_amd import lw
+    assert set(declared_functions()) == set(lw._SIGS)
+
+
+def test_workspace_sizes(lib):
+    from paper_2206_03015_amd import lw
+    assert lw.workspace_bytes(lw.WS_DEPOSIT, 1000, 20001) >= 1000 * 4 + 20001 * 8
+    fft = lw.workspace_bytes(lw.WS_FFT, 7, 1 << 12, "fp64")
+    assert fft >= 3 * (1 << 12) * 16 and fft % (3 * (1 << 12) * 16) == 0
+    assert lw.workspace_bytes(lw.WS_DIRECT_FD, 3, 5) >= 3 * 5 * 6 * 8
+    assert lib.lw_workspace_bytes(999, 1, 1, 0) == 0
+
+
+def test_host_validation_rejects_bad_arguments(lib):
+    """Each call returns its error code before any HIP call for these inputs."""
+    from paper_2206_03015_amd import lw
+    tr = lw.Traj()
+    tr.kind = lw.TRAJ_SAMPLES
+    tr.n_particles = 1
+    tr.n_samples = 10
+    tr.t_start = 0.0
+    tr.dt = 1e-18
+    gr = lw.Grid()
+    gr.n_pix = 1
+    gr.t0 = 0.0
+    gr.dt_obs = 1e-20
+    gr.n_obs = 64
+    st = lib.lw_deposit_td(None, ctypes.byref(gr), 0, 1, 0, None, None, None, 0, None)
+    assert st == -1 and b"traj is NULL" in lib.lw_last_error()
+    st = lib.lw_deposit_td(ctypes.byref(tr), ctypes.byref(gr), 0, 1, 0, None, None, None, 0, None)
+    assert st == -1  # NULL trajectory arrays
+    tr.dt = -1.0
+    assert lib.lw_deposit_td(ctypes.byref(tr), ctypes.byref(gr), 0, 1, 0, None, None, None, 0, None) == -1
+    tr.dt = 1e-18
+    tr.n_samples = 0
+    assert lib.lw_deposit_td(ctypes.byref(tr), ctypes.byref(gr), 0, 1, 0, None, None, None, 0, None) == -2
+    tr.n_samples = 10
+    tr.kind = lw.TRAJ_BORIS
+    assert lib.lw_deposit_td(ctypes.byref(tr), ctypes.byref(gr), 0, 1, 0, None, None, None, 0, None) == -6
+    # spectrum: n_obs must be a power of two >= 4
+    assert lib.lw_spectrum_fft(None, 1, 100, 1e-20, 0, None, None, 0, None) == -2
+    assert lib.lw_spectrum_fft(None, 1, 2, 1e-20, 0, None, None, 0, None) == -2
+    assert lib.lw_spectrum_fft(None, 1, 64, -1.0, 0, None, None, 0, None) == -1
+    assert lib.lw_spectrum_fft(None, 1, 64, 1e-20, 7, None, None, 0, None) == -1
+    # misaligned pointers are refused
+    assert lib.lw_spectrum_fft(ctypes.c_void_p(8), 1, 64, 1e-20, 0, ctypes.c_void_p(16), None, 0, None) == -3
+    assert lib.lw_version().startswith(b"liblw")
