@@ -28,8 +28,19 @@ namespace lw {
 namespace {
 
 constexpr int kWavesPerBlock = 4;
-constexpr int kQCap = 128;
+constexpr int kQCap = 128;  // queue entries per wavefront (at most 63 pending + 64 appended)
+// write-combining line per pixel: 64-byte segments of the trace (16 floats or 8 doubles)
+template <typename T>
+struct WcLine {
+    static constexpr int N = 32 / sizeof(T);   // grid points per line
+    static constexpr int P = 3 * N + 1;        // LDS stride per pixel (odd: no bank conflicts)
+};
+constexpr uint64_t kWantNone = ~0ull;
+constexpr int kStage = 8;  // doubles per staged sample: alpha, x, y, z, |r|^2, pad
 constexpr int kTargetWaves = 16384;
+// (|r|/|x|)^2 up to which the series form of the exact-geometry arrival time is used
+constexpr double kSeriesBound = 1e-8;
+constexpr int kPrepassChunk = 8192;
 
 __device__ __forceinline__ double next_grid(double tau, double n_obs)
 {
@@ -48,31 +59,100 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// ---------------------------------------------------------------------------------------------
-// pre-pass: arrival-time base alpha_i = (t_i - t0)/dt_obs and the per-particle fast-path flag
-__global__ void k_prepass(const double *__restrict__ r, const double *__restrict__ beta,
-                          const double *__restrict__ beta_dot, int64_t n_particles, int64_t n_samples,
-                          double t_start, double dt, double t0, double dt_obs, double inv_cdt,
-                          double *__restrict__ alpha, int *__restrict__ pflag)
+__device__ __forceinline__ double uniform_double(double v)
 {
-    const int64_t total = n_particles * n_samples;
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct DepWs {
+    int *pflag;                 // [n_p] 0 = fast path
+    unsigned long long *rmax2;  // [n_p] bits of max_i |r_i|^2 (non-negative doubles order as integers)
+    double *alpha;              // [n_s] (t_i - t0)/dt_obs
+    double *rec;                // [n_p][n_s][4] x, y, z, |r|^2 (exact geometry)
+};
+
+DepWs carve(void *ws, int64_t n_p, int64_t ns)
+{
+    DepWs w;
+    char *p = (char *)ws;
+    w.pflag = (int *)p;
+    p += align_up((size_t)std::max<int64_t>(n_p, 1) * sizeof(int), 256);
+    w.rmax2 = (unsigned long long *)p;
+    p += align_up((size_t)std::max<int64_t>(n_p, 1) * sizeof(unsigned long long), 256);
+    w.alpha = (double *)p;
+    p += align_up((size_t)std::max<int64_t>(ns, 1) * sizeof(double), 256);
+    w.rec = (double *)p;
+    return w;
+}
+
+// ---------------------------------------------------------------------------------------------
+// pre-pass: one block per (particle, chunk of samples): arrival base alpha_i, sample records,
+// per-particle max |r|^2 and the fast-path flag
+__global__ __launch_bounds__(256) void k_prepass(const double *__restrict__ r, const double *__restrict__ beta,
+                                                 const double *__restrict__ beta_dot, int64_t n_samples,
+                                                 double t_start, double dt, double t0, double dt_obs, double inv_cdt,
+                                                 double *__restrict__ alpha, int *__restrict__ pflag,
+                                                 unsigned long long *__restrict__ rmax2, double *__restrict__ rec)
+{
+    __shared__ unsigned long long s_max[4];
+    __shared__ int s_bad[4];
+    const int64_t k = blockIdx.x;
+    const int64_t i_begin = (int64_t)blockIdx.y * kPrepassChunk;
+    const int64_t i_end = std::min<int64_t>(i_begin + kPrepassChunk, n_samples);
     const double cdt_step = kC * dt;
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < total;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        int64_t k = s / n_samples, i = s - k * n_samples;
-        if (k == 0) alpha[i] = ((t_start + (double)i * dt) - t0) / dt_obs;
-        const double *ri = r + 3 * s, *bi = beta + 3 * s, *ai = beta_dot + 3 * s;
-        bool bad = !sample_usable(ri, bi, ai);
-        if (!bad && i > 0) {
-            const double *rp = ri - 3;
-            double dx = ri[0] - rp[0], dy = ri[1] - rp[1], dz = ri[2] - rp[2];
-            double step = sqrt(dx * dx + dy * dy + dz * dz);
-            double a_i = ((t_start + (double)i * dt) - t0) / dt_obs;
-            double scale = fabs(a_i) + (fabs(ri[0]) + fabs(ri[1]) + fabs(ri[2])) * inv_cdt + 1.0;
-            double margin = (cdt_step - step) * inv_cdt;  // lower bound of tau_i - tau_{i-1}
-            bad = !(margin > 1e-9 + 1e-13 * scale);
+    double mx = 0.0;
+    int bad = 0;
+    for (int64_t i = i_begin + threadIdx.x; i < i_end; i += blockDim.x) {
+        const int64_t s = k * n_samples + i;
+        const double ai = ((t_start + (double)i * dt) - t0) / dt_obs;
+        if (k == 0) alpha[i] = ai;
+        const double *ri = r + 3 * s, *bi = beta + 3 * s, *di = beta_dot + 3 * s;
+        const double x = ri[0], y = ri[1], z = ri[2];
+        const double rr = fma(z, z, fma(y, y, x * x));
+        if (rec) {
+            rec[4 * s] = x;
+            rec[4 * s + 1] = y;
+            rec[4 * s + 2] = z;
+            rec[4 * s + 3] = rr;
         }
-        if (bad) atomicOr(pflag + k, 1);
+        bool b = !sample_usable(ri, bi, di);
+        if (!b) {
+            mx = fmax(mx, rr);
+            if (i > 0) {
+                const double dx = x - ri[-3], dy = y - ri[-2], dz = z - ri[-1];
+                const double step = sqrt(dx * dx + dy * dy + dz * dz);
+                const double scale = fabs(ai) + (fabs(x) + fabs(y) + fabs(z)) * inv_cdt + 1.0;
+                const double margin = (cdt_step - step) * inv_cdt;  // lower bound of tau_i - tau_{i-1}
+                b = !(margin > 1e-9 + 1e-13 * scale);
+            }
+        }
+        bad |= b ? 1 : 0;
+    }
+    // block reduction
+    for (int off = 32; off > 0; off >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, off));
+        bad |= __shfl_xor(bad, off);
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_max[wv] = (unsigned long long)__double_as_longlong(mx);
+        s_bad[wv] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = 0;
+        int bb = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            m = std::max(m, s_max[w]);
+            bb |= s_bad[w];
+        }
+        atomicMax(rmax2 + k, m);
+        if (bb) atomicOr(pflag + k, 1);
     }
 }
 
@@ -87,61 +167,291 @@ __global__ void k_fill(T *__restrict__ p, int64_t n)
 struct DepShape {
     int64_t n_particles, n_samples, n_pix, n_obs;
     int64_t n_tiles, n_tile_blocks, n_groups, parts_per_group;
-    double inv_cdt, cdt;
+    double inv_cdt;
     int fmask;
 };
 
-// Evaluate queued crossings: lane j takes entry (qh + j) mod kQCap for j < cnt.
+// Per-wavefront state of the deposit kernel.
 template <typename T, int GEOM>
-__device__ __forceinline__ void process_queue(const uint32_t *qi, const uint32_t *qkl, uint32_t qh, uint32_t cnt,
-                                              int lane, int64_t tile, int64_t k0, const double *__restrict__ r,
-                                              const double *__restrict__ beta, const double *__restrict__ beta_dot,
-                                              const double *__restrict__ charge, const double *__restrict__ x_det,
-                                              const double *__restrict__ alpha, T *__restrict__ E,
-                                              const DepShape &sh)
-{
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    if ((uint32_t)lane < cnt) {
-        uint32_t slot = (qh + (uint32_t)lane) & (kQCap - 1);
-        uint32_t i = qi[slot], kl = qkl[slot];
-        int64_t k = k0 + (int64_t)(kl >> 6);
-        int64_t m = tile * 64 + (int64_t)(kl & 63u);
-        PixGeo g = pix_geo(x_det, m, sh.inv_cdt);
-        const double *xm = x_det + 3 * m;
-        const size_t sa = (size_t)(k * sh.n_samples + (int64_t)i - 1) * 3, sb = sa + 3;
-        double ta = arrival_tau<GEOM>(g, alpha[i - 1], r[sa], r[sa + 1], r[sa + 2], sh.cdt);
-        double tb = arrival_tau<GEOM>(g, alpha[i], r[sb], r[sb + 1], r[sb + 2], sh.cdt);
-        double q = charge ? charge[k] : -kQe;
-        T eax, eay, eaz, ebx, eby, ebz;
-        lw_field<T, GEOM>(g, xm, r[sa], r[sa + 1], r[sa + 2], beta[sa], beta[sa + 1], beta[sa + 2], beta_dot[sa],
-                          beta_dot[sa + 1], beta_dot[sa + 2], q, sh.fmask, eax, eay, eaz);
-        lw_field<T, GEOM>(g, xm, r[sb], r[sb + 1], r[sb + 2], beta[sb], beta[sb + 1], beta[sb + 2], beta_dot[sb],
-                          beta_dot[sb + 1], beta_dot[sb + 2], q, sh.fmask, ebx, eby, ebz);
+struct Wave {
+    static constexpr int RS = GEOM == LW_GEOM_EXACT ? 4 : 3;  // doubles per streamed sample record
+    const double *__restrict__ r;
+    const double *__restrict__ beta;
+    const double *__restrict__ beta_dot;
+    const double *__restrict__ charge;
+    const double *__restrict__ x_det;
+    const double *__restrict__ alpha;
+    const double *__restrict__ src;  // streamed records: rec (exact) or r (far field)
+    const unsigned long long *__restrict__ rmax2;
+    T *__restrict__ E;
+    DepShape sh;
+    double invD2max;  // wavefront maximum of 1/|x_m|^2
+    int lane;
+    int64_t tile, k0;
+    uint2 *q;          // queue in LDS: {sample index, (particle - k0) << 6 | lane}
+    T *wc;             // write-combining lines in LDS, [64 pixels][WcLine<T>::P] (3 components x N)
+    int *wcb;          // [64] trace segment each line holds (-1: none)
+    uint64_t *want;    // [64] (queue position << 32 | segment of the grid point after the latest hit)
+    double *stage;     // staged sample records in LDS, [64][kStage]
+    uint32_t qn;
+
+    __device__ __forceinline__ bool series(int64_t k) const
+    {
+        return GEOM == LW_GEOM_EXACT && __longlong_as_double((long long)rmax2[k]) * invD2max <= kSeriesBound;
+    }
+
+    template <bool SERIES>
+    __device__ __forceinline__ double tau_rec(const PixGeo &g, double a, const double *p) const
+    {
+        return arrival_tau<GEOM, SERIES>(g, a, p[0], p[1], p[2], GEOM == LW_GEOM_EXACT ? p[3] : 0.0, sh.inv_cdt);
+    }
+
+    __device__ __forceinline__ double tau_any(const PixGeo &g, bool ser, int64_t k, int64_t i) const
+    {
+        const double *p = src + ((size_t)k * sh.n_samples + i) * RS;
+        return ser ? tau_rec<true>(g, alpha[i], p) : tau_rec<false>(g, alpha[i], p);
+    }
+
+    // Add the lines of the pixels in `mask` to the trace (one coalesced atomic instruction per
+    // line: lane t handles component t / N, grid point t % N) and clear them.
+    __device__ void flush_lines(uint64_t mask)
+    {
+        constexpr int NL = WcLine<T>::N;
+        const int c = lane / NL, o = lane % NL;
+        while (mask) {
+            const int p = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const int seg = wcb[p];
+            if (c < 3) {
+                T *line = wc + p * WcLine<T>::P + c * NL + o;
+                const T v = *line;
+                const int64_t u = (int64_t)seg * NL + o;
+                if (v != (T)0 && u < sh.n_obs) atomic_add(E + ((size_t)(tile * 64 + p) * 3 + c) * sh.n_obs + u, v);
+                *line = (T)0;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    // Evaluate the first cnt queued crossings (lane j takes entry j), then move the rest down.
+    __device__ void drain(uint32_t cnt)
+    {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if ((uint32_t)lane < cnt) {
+            const uint2 e = q[lane];
+            const uint32_t i = e.x, kl = e.y;
+            const int64_t k = k0 + (int64_t)(kl >> 6);
+            const int64_t m = tile * 64 + (int64_t)(kl & 63u);
+            const PixGeo g = pix_geo(x_det, m);
+            const bool ser = series(k);
+            const double ta = tau_any(g, ser, k, (int64_t)i - 1);
+            const double tb = tau_any(g, ser, k, (int64_t)i);
+            const double q = charge ? charge[k] : -kQe;
+            const size_t sa = ((size_t)k * sh.n_samples + i - 1) * 3, sb = sa + 3;
+            const double *xm = x_det + 3 * m;
+            T eax, eay, eaz, ebx, eby, ebz;
+            lw_field<T, GEOM>(g, xm, r[sa], r[sa + 1], r[sa + 2], beta[sa], beta[sa + 1], beta[sa + 2],
+                              beta_dot[sa], beta_dot[sa + 1], beta_dot[sa + 2], q, sh.fmask, eax, eay, eaz);
+            lw_field<T, GEOM>(g, xm, r[sb], r[sb + 1], r[sb + 2], beta[sb], beta[sb + 1], beta[sb + 2],
+                              beta_dot[sb], beta_dot[sb + 1], beta_dot[sb + 2], q, sh.fmask, ebx, eby, ebz);
+            const double nob = (double)sh.n_obs;
+            const int64_t u0 = grid_count(ta, nob), u1 = grid_count(tb, nob);
+            const double idt = 1.0 / (tb - ta);
+            T *Em = E + (size_t)m * 3 * sh.n_obs;
+            constexpr int NL = WcLine<T>::N;
+            const int ml = (int)(kl & 63u);
+            const int seg = wcb[ml];
+            for (int64_t u = u0; u < u1; ++u) {
+                const double wd = ((double)u - ta) * idt;
+                const T w = (T)wd, w1 = (T)(1.0 - wd);
+                const T vx = w1 * eax + w * ebx, vy = w1 * eay + w * eby, vz = w1 * eaz + w * ebz;
+                if (u / NL == seg) {
+                    T *line = wc + ml * WcLine<T>::P + (int)(u % NL);
+                    atomicAdd(line, vx);
+                    atomicAdd(line + NL, vy);
+                    atomicAdd(line + 2 * NL, vz);
+                } else {
+                    atomic_add(Em + u, vx);
+                    atomic_add(Em + sh.n_obs + u, vy);
+                    atomic_add(Em + 2 * sh.n_obs + u, vz);
+                }
+            }
+            if (u1 > u0) atomicMax((unsigned long long *)(want + ml), ((uint64_t)lane << 32) | (uint64_t)(u1 / NL));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // steer each pixel's line to the segment of its next grid point; flush lines that move
+        {
+            const uint64_t wnt = want[lane];
+            want[lane] = kWantNone;
+            const int cur = wcb[lane];
+            const int nxt = wnt == kWantNone ? cur : (int)(uint32_t)wnt;
+            const bool move = nxt != cur && nxt * (int64_t)WcLine<T>::N < sh.n_obs;
+            const uint64_t fm = __ballot(move && cur >= 0);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            flush_lines(fm);
+            if (move) wcb[lane] = nxt;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        const uint32_t rest = qn - cnt;
+        uint2 moved;
+        if ((uint32_t)lane < rest) moved = q[cnt + lane];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if ((uint32_t)lane < rest) q[lane] = moved;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        qn = rest;
+    }
+
+    // Append the lanes with `hit` set; drain when 64 entries are pending.
+    __device__ __forceinline__ void push(bool hit, uint64_t mask, uint32_t i, uint32_t tag)
+    {
+        if (hit) q[qn + lanes_below(mask)] = make_uint2(i, tag);
+        qn += (uint32_t)__popcll(mask);
+        if (qn >= 64) drain(64);
+    }
+
+    // Fast path: tau strictly increasing, all samples usable.  Samples go through LDS in
+    // chunks of 64 (lane j loads sample c0 + j with vector loads one chunk ahead); every lane
+    // then reads the staged samples by broadcast, four per trip.
+    template <bool SERIES>
+    __device__ void fast_particle(const PixGeo &g, bool lane_ok, bool pix_in, int64_t k, unsigned long long &c1,
+                                  unsigned long long &c2, unsigned long long &c3)
+    {
+        const int64_t ns = sh.n_samples;
         const double nob = (double)sh.n_obs;
-        int64_t u0 = grid_count(ta, nob), u1 = grid_count(tb, nob);
-        double idt = 1.0 / (tb - ta);
-        T *Em = E + (size_t)m * 3 * sh.n_obs;
-        for (int64_t u = u0; u < u1; ++u) {
-            double wd = ((double)u - ta) * idt;
-            T w = (T)wd, w1 = (T)(1.0 - wd);
-            atomic_add(Em + u, w1 * eax + w * ebx);
-            atomic_add(Em + sh.n_obs + u, w1 * eay + w * eby);
-            atomic_add(Em + 2 * sh.n_obs + u, w1 * eaz + w * ebz);
+        const double *s0 = src + (size_t)k * ns * RS;
+        const uint32_t tag = ((uint32_t)(k - k0) << 6) | (uint32_t)lane;
+        double pa, px, py, pz, prr;
+        // unconditional (clamped) loads, so that they stay in flight until the next chunk
+        auto fetch = [&](int64_t c0) {
+            const int64_t idx = std::min<int64_t>(c0 + lane, ns - 1);
+            const double *p = s0 + (size_t)idx * RS;
+            pa = alpha[idx];
+            px = p[0];
+            py = p[1];
+            pz = p[2];
+            prr = GEOM == LW_GEOM_EXACT ? p[3] : 0.0;
+        };
+        fetch(0);
+        double tau = 0.0, tau0 = 0.0, gnext = INFINITY;
+        for (int64_t c0 = 0; c0 < ns; c0 += 64) {
+            double *st = stage + lane * kStage;
+            st[0] = pa;
+            st[1] = px;
+            st[2] = py;
+            st[3] = pz;
+            st[4] = prr;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            fetch(c0 + 64);
+            const int cnt = (int)std::min<int64_t>(64, ns - c0);
+            int j = 0;
+            if (c0 == 0) {
+                tau = tau0 = arrival_tau<GEOM, SERIES>(g, stage[0], stage[1], stage[2], stage[3], stage[4], sh.inv_cdt);
+                gnext = lane_ok ? next_grid(tau, nob) : INFINITY;
+                j = 1;
+            }
+            auto step = [&](int jj, const double *e) {
+                tau = arrival_tau<GEOM, SERIES>(g, e[0], e[1], e[2], e[3], e[4], sh.inv_cdt);
+                const bool hit = tau >= gnext;
+                const uint64_t mask = __ballot(hit);
+                if (mask) {
+                    if (hit) {
+                        const double f = floor(tau) + 1.0;
+                        gnext = f >= nob ? INFINITY : f;
+                    }
+                    push(hit, mask, (uint32_t)(c0 + jj), tag);
+                }
+            };
+            for (; j + 3 < cnt; j += 4) {
+                double v[4][5];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) v[u][c] = stage[(j + u) * kStage + c];
+                step(j, v[0]);
+                step(j + 1, v[1]);
+                step(j + 2, v[2]);
+                step(j + 3, v[3]);
+            }
+            for (; j < cnt; ++j) step(j, stage + j * kStage);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (lane_ok) {
+            const int64_t inside = grid_count(tau, nob) - grid_count(tau0, nob);
+            c3 += (unsigned long long)inside;
+            c2 += (unsigned long long)((int64_t)(floor(tau) - floor(tau0)) - inside);
+        } else if (pix_in) {
+            c1 += (unsigned long long)(ns - 1);
         }
     }
-    __builtin_amdgcn_wave_barrier();
-}
+
+    // Careful path: the skip rules of lw_deposit_td interval by interval.
+    __device__ void careful_particle(const PixGeo &g, bool lane_ok, bool pix_in, int64_t m, int64_t k,
+                                     unsigned long long &c0, unsigned long long &c1, unsigned long long &c2,
+                                     unsigned long long &c3)
+    {
+        const int64_t ns = sh.n_samples;
+        const double nob = (double)sh.n_obs;
+        const bool ser = series(k);
+        const double q = charge ? charge[k] : -kQe;
+        bool prev_ok = false;
+        double tprev = 0.0;
+        const uint32_t tag = ((uint32_t)(k - k0) << 6) | (uint32_t)lane;
+        for (int64_t i = 0; i < ns; ++i) {
+            const size_t s = (size_t)k * ns + i;
+            bool ok = lane_ok && sample_usable(r + 3 * s, beta + 3 * s, beta_dot + 3 * s);
+            double tau = NAN;
+            if (ok) {
+                tau = tau_any(g, ser, k, i);
+                T ex, ey, ez;
+                lw_field<T, GEOM>(g, x_det + 3 * m, r[3 * s], r[3 * s + 1], r[3 * s + 2], beta[3 * s],
+                                  beta[3 * s + 1], beta[3 * s + 2], beta_dot[3 * s], beta_dot[3 * s + 1],
+                                  beta_dot[3 * s + 2], q, sh.fmask, ex, ey, ez);
+                ok = isfinite(tau) && isfinite((double)ex) && isfinite((double)ey) && isfinite((double)ez);
+            }
+            bool hit = false;
+            if (i > 0 && pix_in) {
+                if (!ok || !prev_ok) {
+                    c1 += 1;
+                } else if (!(tau > tprev)) {
+                    c0 += 1;
+                } else {
+                    const int64_t fa = grid_count(tprev, nob), fb = grid_count(tau, nob);
+                    c3 += (unsigned long long)(fb - fa);
+                    c2 += (unsigned long long)((int64_t)(floor(tau) - floor(tprev)) - (fb - fa));
+                    hit = fb > fa;
+                }
+            }
+            const uint64_t mask = __ballot(hit);
+            if (mask) push(hit, mask, (uint32_t)i, tag);
+            prev_ok = ok;
+            tprev = tau;
+        }
+    }
+};
 
 template <typename T, int GEOM>
 __global__ __launch_bounds__(256) void k_deposit(const double *__restrict__ r, const double *__restrict__ beta,
                                                  const double *__restrict__ beta_dot,
                                                  const double *__restrict__ charge, const double *__restrict__ x_det,
-                                                 const double *__restrict__ alpha, const int *__restrict__ pflag,
-                                                 T *__restrict__ E, unsigned long long *__restrict__ diag, DepShape sh)
+                                                 const double *__restrict__ alpha, const double *__restrict__ rec,
+                                                 const int *__restrict__ pflag,
+                                                 const unsigned long long *__restrict__ rmax2, T *__restrict__ E,
+                                                 unsigned long long *__restrict__ diag, DepShape sh)
 {
-    __shared__ uint32_t q_i[kWavesPerBlock][kQCap];
-    __shared__ uint32_t q_kl[kWavesPerBlock][kQCap];
+    __shared__ uint2 q_all[kWavesPerBlock][kQCap];
+    __shared__ T wc_all[kWavesPerBlock][64 * WcLine<T>::P];
+    __shared__ int wcb_all[kWavesPerBlock][64];
+    __shared__ uint64_t want_all[kWavesPerBlock][64];
+    __shared__ double stage_all[kWavesPerBlock][64 * kStage];
     __shared__ unsigned long long red[4];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
@@ -159,119 +469,52 @@ __global__ __launch_bounds__(256) void k_deposit(const double *__restrict__ r, c
     const int64_t k1 = grp < sh.n_groups ? std::min(k0 + sh.parts_per_group, sh.n_particles) : k0;
     const bool wave_live = tile < sh.n_tiles;
 
-    PixGeo g = pix_geo(x_det, pix_in ? m : 0, sh.inv_cdt);
+    const PixGeo g = pix_geo(x_det, pix_in ? m : 0);
     const bool lane_ok = pix_in && g.ok;
-    const double nob = (double)sh.n_obs;
-    unsigned long long c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-    uint32_t qh = 0, qn = 0;
-    uint32_t *qi = q_i[wv], *qkl = q_kl[wv];
-    const int64_t ns = sh.n_samples;
+    double id2 = lane_ok ? g.invD * g.invD : 0.0;
+    for (int off = 32; off > 0; off >>= 1) id2 = fmax(id2, __shfl_xor(id2, off));
 
+    Wave<T, GEOM> w;
+    w.r = r;
+    w.beta = beta;
+    w.beta_dot = beta_dot;
+    w.charge = charge;
+    w.x_det = x_det;
+    w.alpha = alpha;
+    w.src = GEOM == LW_GEOM_EXACT ? rec : r;
+    w.rmax2 = rmax2;
+    w.E = E;
+    w.sh = sh;
+    w.invD2max = uniform_double(id2);
+    w.lane = lane;
+    w.tile = tile;
+    w.k0 = k0;
+    w.q = q_all[wv];
+    w.wc = wc_all[wv];
+    w.wcb = wcb_all[wv];
+    w.want = want_all[wv];
+    w.stage = stage_all[wv];
+    w.qn = 0;
+    for (int j = lane; j < 64 * WcLine<T>::P; j += 64) w.wc[j] = (T)0;
+    w.wcb[lane] = -1;
+    w.want[lane] = kWantNone;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+
+    unsigned long long c0 = 0, c1 = 0, c2 = 0, c3 = 0;
     for (int64_t k = wave_live ? k0 : k1; k < k1; ++k) {
-        const double *rk = r + (size_t)k * ns * 3;
         if (pflag[k] == 0) {
-            // ---- fast path: tau strictly increasing, all samples usable
-            double tau = arrival_tau<GEOM>(g, alpha[0], rk[0], rk[1], rk[2], sh.cdt);
-            const double tau0 = tau;
-            double gnext = lane_ok ? next_grid(tau, nob) : INFINITY;
-            const uint32_t kl_tag = ((uint32_t)(k - k0) << 6) | (uint32_t)lane;
-            // one sample: crossing test, queue append, queue drain when 64 entries are pending
-            auto step = [&](int64_t i, double ai, double x, double y, double z) {
-                tau = arrival_tau<GEOM>(g, ai, x, y, z, sh.cdt);
-                const bool hit = tau >= gnext;
-                const uint64_t mask = __ballot(hit);
-                if (mask) {
-                    if (hit) {
-                        uint32_t pos = (qh + qn + lanes_below(mask)) & (kQCap - 1);
-                        qi[pos] = (uint32_t)i;
-                        qkl[pos] = kl_tag;
-                        gnext = next_grid(tau, nob);
-                    }
-                    qn += (uint32_t)__popcll(mask);
-                    if (qn >= 64) {
-                        process_queue<T, GEOM>(qi, qkl, qh, 64, lane, tile, k0, r, beta, beta_dot, charge, x_det,
-                                               alpha, E, sh);
-                        qh = (qh + 64) & (kQCap - 1);
-                        qn -= 64;
-                    }
-                }
-            };
-            int64_t i = 1;
-            // four samples per trip; all wavefront-uniform loads issued before the first use
-            for (; i + 3 < ns; i += 4) {
-                const double a0 = alpha[i], a1 = alpha[i + 1], a2 = alpha[i + 2], a3 = alpha[i + 3];
-                const double *rp = rk + 3 * i;
-                const double x0 = rp[0], y0 = rp[1], z0 = rp[2], x1 = rp[3], y1 = rp[4], z1 = rp[5];
-                const double x2 = rp[6], y2 = rp[7], z2 = rp[8], x3 = rp[9], y3 = rp[10], z3 = rp[11];
-                step(i, a0, x0, y0, z0);
-                step(i + 1, a1, x1, y1, z1);
-                step(i + 2, a2, x2, y2, z2);
-                step(i + 3, a3, x3, y3, z3);
-            }
-            for (; i < ns; ++i) step(i, alpha[i], rk[3 * i], rk[3 * i + 1], rk[3 * i + 2]);
-            if (lane_ok) {
-                int64_t inside = grid_count(tau, nob) - grid_count(tau0, nob);
-                c3 += (unsigned long long)inside;
-                c2 += (unsigned long long)((int64_t)(floor(tau) - floor(tau0)) - inside);
-            } else if (pix_in) {
-                c1 += (unsigned long long)(ns - 1);
-            }
+            if (GEOM == LW_GEOM_EXACT && w.series(k))
+                w.template fast_particle<true>(g, lane_ok, pix_in, k, c1, c2, c3);
+            else
+                w.template fast_particle<false>(g, lane_ok, pix_in, k, c1, c2, c3);
         } else {
-            // ---- careful path: interval-by-interval skip rules
-            const double *bk = beta + (size_t)k * ns * 3, *ak = beta_dot + (size_t)k * ns * 3;
-            const double q = charge ? charge[k] : -kQe;
-            bool prev_ok = false;
-            double tprev = 0.0;
-            for (int64_t i = 0; i < ns; ++i) {
-                bool ok = lane_ok && sample_usable(rk + 3 * i, bk + 3 * i, ak + 3 * i);
-                double tau = NAN;
-                if (ok) {
-                    tau = arrival_tau<GEOM>(g, alpha[i], rk[3 * i], rk[3 * i + 1], rk[3 * i + 2], sh.cdt);
-                    T ex, ey, ez;
-                    lw_field<T, GEOM>(g, x_det + 3 * m, rk[3 * i], rk[3 * i + 1], rk[3 * i + 2], bk[3 * i],
-                                      bk[3 * i + 1], bk[3 * i + 2], ak[3 * i], ak[3 * i + 1], ak[3 * i + 2], q,
-                                      sh.fmask, ex, ey, ez);
-                    ok = isfinite(tau) && isfinite((double)ex) && isfinite((double)ey) && isfinite((double)ez);
-                }
-                bool hit = false;
-                if (i > 0 && pix_in) {
-                    if (!ok || !prev_ok) {
-                        c1 += 1;
-                    } else if (!(tau > tprev)) {
-                        c0 += 1;
-                    } else {
-                        int64_t fa = grid_count(tprev, nob), fb = grid_count(tau, nob);
-                        c3 += (unsigned long long)(fb - fa);
-                        c2 += (unsigned long long)((int64_t)(floor(tau) - floor(tprev)) - (fb - fa));
-                        hit = fb > fa;
-                    }
-                }
-                const uint64_t mask = __ballot(hit);
-                if (mask) {
-                    if (hit) {
-                        uint32_t pos = (qh + qn + lanes_below(mask)) & (kQCap - 1);
-                        qi[pos] = (uint32_t)i;
-                        qkl[pos] = ((uint32_t)(k - k0) << 6) | (uint32_t)lane;
-                    }
-                    qn += (uint32_t)__popcll(mask);
-                    if (qn >= 64) {
-                        process_queue<T, GEOM>(qi, qkl, qh, 64, lane, tile, k0, r, beta, beta_dot, charge, x_det,
-                                               alpha, E, sh);
-                        qh = (qh + 64) & (kQCap - 1);
-                        qn -= 64;
-                    }
-                }
-                prev_ok = ok;
-                tprev = tau;
-            }
+            w.careful_particle(g, lane_ok, pix_in, m, k, c0, c1, c2, c3);
         }
     }
-    while (qn > 0) {
-        uint32_t cnt = qn < 64 ? qn : 64;
-        process_queue<T, GEOM>(qi, qkl, qh, cnt, lane, tile, k0, r, beta, beta_dot, charge, x_det, alpha, E, sh);
-        qh = (qh + cnt) & (kQCap - 1);
-        qn -= cnt;
-    }
+    while (w.qn > 0) w.drain(w.qn < 64 ? w.qn : 64);
+    w.flush_lines(__ballot(w.wcb[lane] >= 0));
+
     // counters: block reduction in LDS, then one global atomic per counter
     if (c0) atomicAdd(&red[0], c0);
     if (c1) atomicAdd(&red[1], c1);
@@ -281,14 +524,13 @@ __global__ __launch_bounds__(256) void k_deposit(const double *__restrict__ r, c
     if (diag && threadIdx.x < 4 && red[threadIdx.x]) atomicAdd(diag + threadIdx.x, red[threadIdx.x]);
 }
 
-inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
 }  // namespace
 
 size_t deposit_ws_bytes(int64_t n_particles, int64_t n_samples)
 {
-    return align_up((size_t)std::max<int64_t>(n_particles, 1) * sizeof(int), 256) +
-           align_up((size_t)std::max<int64_t>(n_samples, 1) * sizeof(double), 256);
+    const size_t np = (size_t)std::max<int64_t>(n_particles, 1), ns = (size_t)std::max<int64_t>(n_samples, 1);
+    return align_up(np * sizeof(int), 256) + align_up(np * sizeof(unsigned long long), 256) +
+           align_up(ns * sizeof(double), 256) + align_up(np * ns * 4 * sizeof(double), 256);
 }
 
 lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int fmask, int geom, bool accumulate,
@@ -299,7 +541,7 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
     const bool f64 = prec == LW_PREC_FP64;
     if (!accumulate) {
         if (trace_elems) {
-            int blocks = (int)std::min<size_t>((trace_elems + 255) / 256, 65536);
+            const int blocks = (int)std::min<size_t>((trace_elems + 255) / 256, 65536);
             if (f64)
                 k_fill<double><<<blocks, 256, 0, s>>>((double *)E, (int64_t)trace_elems);
             else
@@ -308,15 +550,17 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
         if (diag) k_fill<unsigned long long><<<1, 64, 0, s>>>((unsigned long long *)diag, 4);
     }
     if (n_p == 0 || n_pix == 0 || ns == 0) return check_launch("deposit fill");
-    int *pflag = (int *)ws;
-    double *alpha = (double *)((char *)ws + align_up((size_t)n_p * sizeof(int), 256));
+    const DepWs w = carve(ws, n_p, ns);
     const double inv_cdt = 1.0 / (kC * gr->dt_obs);
-    k_fill<int><<<(int)std::min<int64_t>((n_p + 255) / 256, 65536), 256, 0, s>>>(pflag, n_p);
+    const int fill_blocks = (int)std::min<int64_t>((n_p + 255) / 256, 65536);
+    k_fill<int><<<fill_blocks, 256, 0, s>>>(w.pflag, n_p);
+    k_fill<unsigned long long><<<fill_blocks, 256, 0, s>>>(w.rmax2, n_p);
     {
-        int64_t total = n_p * ns;
-        int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
-        k_prepass<<<blocks, 256, 0, s>>>(t->r, t->beta, t->beta_dot, n_p, ns, t->t_start, t->dt, gr->t0, gr->dt_obs,
-                                         inv_cdt, alpha, pflag);
+        const int64_t chunks = (ns + kPrepassChunk - 1) / kPrepassChunk;
+        if (n_p > 0x7fffffff || chunks > 65535) return fail(LW_E_SHAPE, "lw_deposit_td: too many samples");
+        k_prepass<<<dim3((unsigned)n_p, (unsigned)chunks), 256, 0, s>>>(
+            t->r, t->beta, t->beta_dot, ns, t->t_start, t->dt, gr->t0, gr->dt_obs, inv_cdt, w.alpha, w.pflag,
+            w.rmax2, geom == LW_GEOM_EXACT ? w.rec : nullptr);
     }
     DepShape sh;
     sh.n_particles = n_p;
@@ -330,28 +574,27 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
     sh.parts_per_group = (n_p + groups - 1) / groups;
     sh.n_groups = (n_p + sh.parts_per_group - 1) / sh.parts_per_group;
     sh.inv_cdt = inv_cdt;
-    sh.cdt = kC * gr->dt_obs;
     sh.fmask = fmask;
     const int64_t group_slots = (sh.n_groups + 7) / 8 * 8;
     const int64_t blocks = group_slots * sh.n_tile_blocks;
     if (blocks > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: problem too large for one launch");
     unsigned long long *dg = (unsigned long long *)diag;
-    dim3 grid((unsigned)blocks), block(64 * kWavesPerBlock);
+    const dim3 grid((unsigned)blocks), block(64 * kWavesPerBlock);
+#define LW_DEPOSIT_LAUNCH(T, G)                                                                                     \
+    k_deposit<T, G><<<grid, block, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge, gr->x_det, w.alpha, w.rec, w.pflag, \
+                                           w.rmax2, (T *)E, dg, sh)
     if (f64) {
         if (geom == LW_GEOM_EXACT)
-            k_deposit<double, LW_GEOM_EXACT><<<grid, block, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge,
-                                                                    gr->x_det, alpha, pflag, (double *)E, dg, sh);
+            LW_DEPOSIT_LAUNCH(double, LW_GEOM_EXACT);
         else
-            k_deposit<double, LW_GEOM_FARFIELD><<<grid, block, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge,
-                                                                       gr->x_det, alpha, pflag, (double *)E, dg, sh);
+            LW_DEPOSIT_LAUNCH(double, LW_GEOM_FARFIELD);
     } else {
         if (geom == LW_GEOM_EXACT)
-            k_deposit<float, LW_GEOM_EXACT><<<grid, block, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge, gr->x_det,
-                                                                   alpha, pflag, (float *)E, dg, sh);
+            LW_DEPOSIT_LAUNCH(float, LW_GEOM_EXACT);
         else
-            k_deposit<float, LW_GEOM_FARFIELD><<<grid, block, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge,
-                                                                      gr->x_det, alpha, pflag, (float *)E, dg, sh);
+            LW_DEPOSIT_LAUNCH(float, LW_GEOM_FARFIELD);
     }
+#undef LW_DEPOSIT_LAUNCH
     return check_launch("lw_deposit_td");
 }
 

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_direct_fd(const double *__restrict__ r,
     const bool w_ok = w < sh.n_omega;
     const double nu = w_ok ? omega[w] / (2.0 * kPi) : 0.0;  // cycles per second
     const int64_t k0 = grp * sh.parts_per_group, k1 = std::min(k0 + sh.parts_per_group, sh.n_particles);
-    PixGeo g = pix_geo(x_det, m, sh.inv_cdt);
+    PixGeo g = pix_geo(x_det, m);
     const double *xm = x_det + 3 * m;
     double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;  // Re/Im of F_x, F_y, F_z
     const int64_t ns = sh.n_samples;
@@ -62,9 +62,10 @@ __global__ __launch_bounds__(256) void k_direct_fd(const double *__restrict__ r,
                         lw_field<T, GEOM>(g, xm, r[s], r[s + 1], r[s + 2], beta[s], beta[s + 1], beta[s + 2],
                                           beta_dot[s], beta_dot[s + 1], beta_dot[s + 2], q, sh.fmask, ex, ey, ez,
                                           &kap);
-                        // arrival time relative to t0 (s): tau * dt_obs with dt_obs = cdt / c
-                        const double alpha = ((sh.t_start + (double)i * sh.dt) - sh.t0) / (sh.cdt / kC);
-                        ta = arrival_tau<GEOM>(g, alpha, r[s], r[s + 1], r[s + 2], sh.cdt) * (sh.cdt / kC);
+                        // arrival time relative to t0 (s), formed in units of u = cdt / c
+                        const double u = sh.cdt / kC;
+                        const double alpha = ((sh.t_start + (double)i * sh.dt) - sh.t0) / u;
+                        ta = arrival_tau<GEOM, false>(g, alpha, r[s], r[s + 1], r[s + 2], 0.0, sh.inv_cdt) * u;
                         const T tk = (T)kap;
                         ex *= tk;
                         ey *= tk;

@@ -5,7 +5,7 @@
 
 #include <cstdint>
 
-#include "../../include/lw.h"
+#include "lw.h"
 
 namespace lw {
 
@@ -28,12 +28,11 @@ inline bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintp
 // Pixel geometry, shared by the arrival-time and field evaluations.
 struct PixGeo {
     double nx, ny, nz;  // unit direction x_m / |x_m|
-    double D;           // |x_m|
-    double sx, sy, sz;  // n / (c dt_obs): arrival shift per metre, in grid units
+    double D, invD;     // |x_m|, 1/|x_m|
     bool ok;
 };
 
-__device__ __forceinline__ PixGeo pix_geo(const double *x_det, int64_t m, double inv_cdt)
+__device__ __forceinline__ PixGeo pix_geo(const double *x_det, int64_t m)
 {
     PixGeo g;
     double x = x_det[3 * m], y = x_det[3 * m + 1], z = x_det[3 * m + 2];
@@ -44,36 +43,45 @@ __device__ __forceinline__ PixGeo pix_geo(const double *x_det, int64_t m, double
     g.ny = y / D;
     g.nz = z / D;
     g.D = D;
-    g.sx = g.nx * inv_cdt;
-    g.sy = g.ny * inv_cdt;
-    g.sz = g.nz * inv_cdt;
+    g.invD = 1.0 / D;
     return g;
 }
 
-// Arrival time in grid units, tau = alpha_i - n.r/(c dt_obs) [+ exact-geometry correction],
-// alpha_i = (t_i - t0)/dt_obs.  The exact correction uses
-// |x - r| - |x| = -n.r + |r_perp|^2 / (|x - r| + |x| - n.r),  r_perp = r - (n.r) n,
-// which has no cancellation.  Written with explicit fma so that every caller that
-// evaluates the same (pixel, sample) gets the same bits.
-template <int GEOM>
-__device__ __forceinline__ double arrival_tau(const PixGeo &g, double alpha, double rx, double ry, double rz,
-                                              double cdt)
+// Arrival time in grid units of sample (r, |r|^2 = rr) at pixel g:
+//   far field (Eq. far_adv):            tau = alpha - s/(c dt_obs),     s = n.r
+//   exact (Eq. advanced_condition):     tau = alpha - s/(c dt_obs) + |r_perp|^2 / (c dt_obs (|x - r| + |x| - s))
+// with alpha = (t_i - t0)/dt_obs and r_perp = r - s n.  The exact correction is the identity
+// |x - r| - |x| = -s + |r_perp|^2/(|x - r| + |x| - s), free of cancellation.
+// SERIES (valid when |r| <= 1e-4 |x|, checked by the caller): with x = s/|x| and
+// q = |r_perp|^2/(|x| - s)^2,  1/(|x| - s) = (1 + x + x^2 + x^3 + O(x^4))/|x|  and
+// 1/(|x - r| + |x| - s) = (1/(|x| - s)) (1/2 - q/8 + O(q^2)); |r_perp|^2 = |r|^2 - s^2.
+// Truncation is below 1e-16 relative under that bound.  Otherwise the sqrt/divide form is used.
+// Written with explicit fma so that every evaluation of the same (pixel, sample) gives the same bits.
+template <int GEOM, bool SERIES>
+__device__ __forceinline__ double arrival_tau(const PixGeo &g, double alpha, double rx, double ry, double rz, double rr,
+                                              double inv_cdt)
 {
-    double tau = fma(-g.sz, rz, alpha);
-    tau = fma(-g.sy, ry, tau);
-    tau = fma(-g.sx, rx, tau);
+    const double s = fma(g.nz, rz, fma(g.ny, ry, g.nx * rx));
+    double tau = fma(-s, inv_cdt, alpha);
     if (GEOM == LW_GEOM_EXACT) {
-        double s = fma(g.nz, rz, fma(g.ny, ry, g.nx * rx));
-        double px = fma(-s, g.nx, rx), py = fma(-s, g.ny, ry), pz = fma(-s, g.nz, rz);
-        double p2 = fma(pz, pz, fma(py, py, px * px));
-        double ds = g.D - s;
-        double R = sqrt(fma(ds, ds, p2));
-        tau += p2 / (cdt * (R + ds));
+        if (SERIES) {
+            const double p2 = fma(-s, s, rr);
+            const double x = s * g.invD;
+            const double h = fma(x, fma(x, x + 1.0, 1.0), 1.0);
+            const double y = g.invD * h;
+            const double py = p2 * y;
+            const double q = py * y;
+            tau = fma(py, fma(q, -0.125 * inv_cdt, 0.5 * inv_cdt), tau);
+        } else {
+            const double px = fma(-s, g.nx, rx), py = fma(-s, g.ny, ry), pz = fma(-s, g.nz, rz);
+            const double p2 = fma(pz, pz, fma(py, py, px * px));
+            const double ds = g.D - s;
+            const double R = sqrt(fma(ds, ds, p2));
+            tau += p2 * inv_cdt / (R + ds);
+        }
     }
     return tau;
 }
-
-// Single-precision variant of the exact correction is not used: tau is always double.
 
 // Lienard-Wiechert field of one sample at one pixel.  Geometry (n, R, n - beta, kappa) in
 // double; the field arithmetic in T.  kappa = 1 - n.b is formed as (1-b^2)/(1+|b|) + |b||n - b^|^2/2.
