@@ -1,0 +1,130 @@
+"""Oracle gradients (test infrastructure only).
+
+* ``spectrum_vjp``: dJ/dE of J = sum_j dS_j S_j with S from ``spectrum`` (Eq. efield_xfrom):
+  dE_c[u] = (dt^2/pi) Re sum_{j<=N/2} dS_j F_c[j] exp(+2 pi i j u / N),  F_c = rfft(E_c).
+  Pinned by the exact central difference of the quadratic S (test_oracle_grad.py).
+* ``chain_complex``: the whole chain -- arrival time and field of every sample
+  (Eqs. advanced_condition / far_adv, lw_fields_retarded), Algorithm 2 interpolation,
+  spectrum, objective -- evaluated in complex arithmetic.  With inputs x + i h v
+  (h ~ 1e-30) the imaginary part of the result is h times the exact directional
+  derivative of the FP64 chain along v (complex-step differentiation; every
+  discrete decision uses real parts).  Pinned against central finite differences of
+  the real C oracle and against the real part of the C oracle itself.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+C_LIGHT = 299792458.0
+Q_E = 1.602176634e-19
+EPS0 = 8.8541878128e-12
+
+
+def spectrum_vjp(E_tot, dS, dt_obs):
+    """dJ/dE for J = sum dS * spectrum(E_tot, dt_obs).  E_tot [..., 3, N], dS [..., N/2+1]."""
+    E_tot = np.asarray(E_tot, dtype=np.float64)
+    N = E_tot.shape[-1]
+    F = np.fft.rfft(E_tot, axis=-1)
+    G = np.asarray(dS, dtype=np.float64)[..., None, :] * F
+    pad = np.zeros(E_tot.shape[:-1] + (N,), dtype=np.complex128)
+    pad[..., : N // 2 + 1] = G
+    return (dt_obs * dt_obs / np.pi) * (N * np.fft.ifft(pad, axis=-1)).real
+
+
+def _dot(a, b):
+    return np.sum(a * b, axis=-1)
+
+
+def eval_complex(x, r, b, a, q, field_mask=1, geom=0):
+    """Arrival shift tt (relative to t + |x|/c) and field E of samples r, b, a [n][3] (complex
+    allowed) at observer x, written with the analytic (complex-differentiable) operations of
+    the definitions; the exact-geometry shift uses the cancellation-free identity
+    |x - r| - |x| = -s + |r - s n|^2 / (|x - r| + |x| - s)."""
+    x = np.asarray(x, dtype=np.float64)
+    D = np.sqrt(x @ x)
+    nm = x / D
+    s = r @ nm
+    if geom == 1:
+        n = np.broadcast_to(nm, r.shape)
+        R = D
+        tt = -s / C_LIGHT
+    else:
+        rp = r - s[:, None] * nm
+        p2 = _dot(rp, rp)
+        d = x - r
+        R = np.sqrt(_dot(d, d))
+        n = d / R[:, None]
+        tt = -s / C_LIGHT + p2 / (C_LIGHT * (R + D - s))
+    kappa = 1.0 - _dot(n, b)
+    pref = q / (4.0 * np.pi * EPS0)
+    E = np.zeros(r.shape, dtype=np.result_type(r, b, a))
+    nb = n - b
+    Rc = R if np.ndim(R) == 0 else R[:, None]
+    if field_mask & 2:
+        E = E + (pref * (1.0 - _dot(b, b)) / (kappa ** 3))[:, None] * nb / Rc ** 2
+    if field_mask & 1:
+        w = np.cross(nb, a)
+        v = np.cross(n, w)
+        E = E + (pref / (C_LIGHT * kappa ** 3))[:, None] * v / Rc
+    return tt, E
+
+
+def deposit_complex(t_start, dt, r, b, a, x_det, t0, dt_obs, n_obs, charge=None, field_mask=1, geom=0):
+    """Algorithm 2 deposit (all samples assumed usable) in complex arithmetic; decisions on
+    real parts.  Returns E_tot [n_pix][3][n_obs] complex."""
+    r = np.asarray(r)
+    n_p, ns = r.shape[0], r.shape[1]
+    x_det = np.asarray(x_det, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros((x_det.shape[0], 3, n_obs), dtype=np.complex128)
+    ti = t_start + np.arange(ns) * dt
+    for m in range(x_det.shape[0]):
+        for k in range(n_p):
+            q = -Q_E if charge is None else charge[k]
+            tt, E = eval_complex(x_det[m], r[k], b[k], a[k], q, field_mask, geom)
+            tau = ((ti + tt) - t0) / dt_obs
+            tr = tau.real
+            lo = np.floor(tr[:-1]) + 1.0
+            hi = np.floor(tr[1:])
+            good = tr[1:] > tr[:-1]
+            lo = np.maximum(lo, 0.0)
+            hi = np.minimum(hi, n_obs - 1.0)
+            cnt = np.where(good, np.maximum(hi - lo + 1.0, 0.0), 0.0).astype(np.int64)
+            if cnt.sum() == 0:
+                continue
+            idx = np.repeat(np.arange(ns - 1), cnt)
+            starts = np.repeat(lo.astype(np.int64), cnt)
+            offs = np.arange(cnt.sum()) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+            u = starts + offs
+            w = (u - tau[idx]) / (tau[idx + 1] - tau[idx])
+            val = (1.0 - w)[:, None] * E[idx] + w[:, None] * E[idx + 1]
+            for c in range(3):
+                np.add.at(out[m, c], u, val[:, c])
+    return out
+
+
+def spectrum_complex(E_tot, dt_obs):
+    """S = (dt^2/2pi) sum_c (Re F_c)^2 + (Im F_c)^2 with Re F, Im F the real-linear maps of the
+    DFT applied to a complex (complex-step) trace."""
+    Er = np.fft.rfft(E_tot.real, axis=-1)
+    Ei = np.fft.rfft(E_tot.imag, axis=-1)
+    Fre = Er.real + 1j * Ei.real
+    Fim = Er.imag + 1j * Ei.imag
+    return (dt_obs * dt_obs / (2.0 * np.pi)) * np.sum(Fre * Fre + Fim * Fim, axis=-2)
+
+
+def chain_complex(t_start, dt, r, b, a, x_det, t0, dt_obs, n_obs, weights=None, dE=None, charge=None,
+                  field_mask=1, geom=0):
+    """J = sum(weights * S) (or sum(dE * E_tot) when dE is given) through the complex chain."""
+    E = deposit_complex(t_start, dt, r, b, a, x_det, t0, dt_obs, n_obs, charge, field_mask, geom)
+    if dE is not None:
+        return np.sum(np.asarray(dE) * E)
+    S = spectrum_complex(E, dt_obs)
+    return np.sum(np.asarray(weights) * S)
+
+
+def directional_derivative(t_start, dt, r, b, a, v_r, v_b, v_a, x_det, t0, dt_obs, n_obs, weights=None, dE=None,
+                           charge=None, field_mask=1, geom=0, h=1e-30):
+    """Complex-step derivative of J along (v_r, v_b, v_a) at (r, b, a)."""
+    J = chain_complex(t_start, dt, r + 1j * h * v_r, b + 1j * h * v_b, a + 1j * h * v_a, x_det, t0, dt_obs, n_obs,
+                      weights, dE, charge, field_mask, geom)
+    return J.imag / h, J.real

@@ -295,6 +295,143 @@ __global__ __launch_bounds__(256) void k_fft_rows(const typename C2<T>::type *__
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Adjoint.  With F_c = DFT(E_c) and S_j = (dt^2/2pi) sum_c |F_c[j]|^2 (j <= N/2):
+//   dE_c[u] = (dt^2/pi) Re sum_{j<=N/2} dS_j F_c[j] e^{+2 pi i j u/N}
+//           = (dt^2/pi) IDFT(G_c)[u],   G_c[j] = h_j dS_{min(j,N-j)} F_c[j],  h_0 = h_{N/2} = 1, else 1/2,
+// an IDFT whose output is real.  In the packed transforms Z = a + i b this gives
+//   Z0, Z1:  G = h dS_{j*} Z[j]
+//   Z2:      G = (h/2) [(dS_m + dS_m+1) Z2[j] + (dS_m - dS_m+1) conj Z2[N-j]]
+// and the real / imaginary parts of IDFT(G) are the two packed components.
+// The inverse four-step runs rows then columns, each as conj(DFT(conj(.))).
+
+// pass B': forward row transforms, multiply, inverse row transforms, inverse twiddle; in place
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_rows_bwd(typename C2<T>::type *__restrict__ Y, const T *__restrict__ dS,
+                                                      FftShape sh)
+{
+    using T2 = typename C2<T>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T2 *smem = reinterpret_cast<T2 *>(smem_raw);
+    const int N1 = 1 << sh.lg1, N2 = 1 << sh.lg2;
+    const int64_t N = (int64_t)N1 * N2, half = N / 2;
+    const int rp = blockIdx.x;
+    const int64_t pl = blockIdx.y, p = sh.pair0 + pl;
+    const int64_t m = 2 * p, m1 = 2 * p + 1;
+    const bool has1 = m1 < sh.n_pix;
+    const int ka = rp, kb = (N1 - rp) & (N1 - 1);
+    const int nrows = ka == kb ? 1 : 2;
+    T2 *bufA = smem, *bufB = smem + 2 * N2, *tw = smem + 4 * N2;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int q = tid; q < N2; q += nthr) tw[q] = twiddle<T2>(q, N2);
+    const int64_t ldS = half + 1;
+    const T *dSm = dS + m * ldS, *dSm1 = has1 ? dS + m1 * ldS : nullptr;
+    for (int t = 0; t < 3; ++t) {
+        if (t == 1 && !has1) continue;
+        T2 *Yt = Y + (pl * 3 + t) * N;
+        __syncthreads();
+        for (int idx = tid; idx < nrows * N2; idx += nthr) {
+            const int row = idx >> sh.lg2, k2 = idx & (N2 - 1);
+            bufA[row * N2 + k2] = Yt[(int64_t)(row ? kb : ka) * N2 + k2];
+        }
+        __syncthreads();
+        T2 *res = lds_fft(bufA, bufB, sh.lg2, nrows, N2, tw, tid, nthr);
+        T2 *oth = res == bufA ? bufB : bufA;
+        for (int q = tid; q < nrows * N2; q += nthr) {
+            const int row = q >> sh.lg2, k2 = q & (N2 - 1);
+            const int kr = row ? kb : ka;
+            const int64_t j = kr + (int64_t)N1 * k2;
+            const int64_t jm = (N - j) & (N - 1);
+            const int64_t js = j < jm ? j : jm;
+            const T h = (j == 0 || j == half) ? (T)1 : (T)0.5;
+            const T2 z = res[q];
+            T2 g;
+            if (t < 2) {
+                const T d = h * (t == 0 ? dSm[js] : dSm1[js]);
+                g.x = d * z.x;
+                g.y = d * z.y;
+            } else {
+                int mrow, mk2;
+                if (kr == 0) {
+                    mrow = row;
+                    mk2 = (N2 - k2) & (N2 - 1);
+                } else {
+                    mrow = (N1 - kr == ka) ? 0 : 1;
+                    mk2 = N2 - 1 - k2;
+                }
+                const T2 zm = res[mrow * N2 + mk2];
+                const T a = dSm[js], b = has1 ? dSm1[js] : (T)0;
+                const T sp = (T)0.5 * h * (a + b), sm = (T)0.5 * h * (a - b);
+                // sp z + sm conj(zm)
+                g.x = sp * z.x + sm * zm.x;
+                g.y = sp * z.y - sm * zm.y;
+            }
+            g.y = -g.y;  // conj before the forward transform
+            oth[q] = g;
+        }
+        __syncthreads();
+        T2 *res2 = lds_fft(oth, res, sh.lg2, nrows, N2, tw, tid, nthr);
+        for (int q = tid; q < nrows * N2; q += nthr) {
+            const int row = q >> sh.lg2, n2 = q & (N2 - 1);
+            const int kr = row ? kb : ka;
+            T2 v = res2[q];
+            v.y = -v.y;  // conj after: inverse row transform
+            // inverse twiddle exp(+2 pi i n2 kr / N) = conj(exp(-2 pi i n2 kr / N))
+            T2 w = twiddle<T2>(((int64_t)n2 * kr) & (N - 1), N);
+            w.y = -w.y;
+            Yt[(int64_t)kr * N2 + n2] = cmul(v, w);
+        }
+    }
+}
+
+// pass C: inverse column transforms; real / imaginary parts are the two packed components of dE
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_cols_inv(const typename C2<T>::type *__restrict__ Y, T *__restrict__ dE,
+                                                      FftShape sh, T scale)
+{
+    using T2 = typename C2<T>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T2 *smem = reinterpret_cast<T2 *>(smem_raw);
+    const int N1 = 1 << sh.lg1, N2 = 1 << sh.lg2;
+    const int64_t N = (int64_t)N1 * N2;
+    const int t = blockIdx.y;
+    const int64_t pl = blockIdx.z, p = sh.pair0 + pl;
+    const int64_t m = 2 * p, m1 = 2 * p + 1;
+    const bool has1 = m1 < sh.n_pix;
+    if (t == 1 && !has1) return;
+    T *re, *im;
+    if (t == 0) {
+        re = dE + (m * 3 + 0) * N;
+        im = dE + (m * 3 + 1) * N;
+    } else if (t == 1) {
+        re = dE + (m1 * 3 + 0) * N;
+        im = dE + (m1 * 3 + 1) * N;
+    } else {
+        re = dE + (m * 3 + 2) * N;
+        im = has1 ? dE + (m1 * 3 + 2) * N : nullptr;
+    }
+    const int C = sh.C, c0 = blockIdx.x * C;
+    T2 *bufA = smem, *bufB = smem + C * N1, *tw = smem + 2 * C * N1;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int q = tid; q < N1; q += nthr) tw[q] = twiddle<T2>(q, N1);
+    const T2 *Yt = Y + (pl * 3 + t) * N;
+    for (int idx = tid; idx < N1 * C; idx += nthr) {
+        const int k1 = idx / C, cc = idx - k1 * C;
+        T2 v = Yt[(int64_t)k1 * N2 + c0 + cc];
+        v.y = -v.y;
+        bufA[cc * N1 + k1] = v;
+    }
+    __syncthreads();
+    T2 *res = lds_fft(bufA, bufB, sh.lg1, C, N1, tw, tid, nthr);
+    for (int idx = tid; idx < N1 * C; idx += nthr) {
+        const int n1 = idx / C, cc = idx - n1 * C;
+        const T2 v = res[cc * N1 + n1];
+        const int64_t n = (int64_t)n1 * N2 + c0 + cc;
+        re[n] = scale * v.x;
+        if (im) im[n] = -scale * v.y;
+    }
+}
+
 int ilog2(int64_t v)
 {
     int l = 0;
@@ -349,6 +486,46 @@ lw_status run_fft(const T *E, int64_t n_pix, int64_t n_obs, double dt_obs, T *S,
     return check_launch("lw_spectrum_fft");
 }
 
+template <typename T>
+lw_status run_fft_bwd(const T *E, const T *dS, int64_t n_pix, int64_t n_obs, double dt_obs, T *dE, void *ws,
+                      size_t ws_bytes, hipStream_t s)
+{
+    using T2 = typename C2<T>::type;
+    const int lg = ilog2(n_obs);
+    FftShape sh;
+    sh.n_pix = n_pix;
+    sh.lg2 = lg / 2;
+    sh.lg1 = lg - sh.lg2;
+    const int N1 = 1 << sh.lg1, N2 = 1 << sh.lg2;
+    if (2 * N2 > 16 * 256) return fail(LW_E_SHAPE, "lw_spectrum_fft_bwd: n_obs too large");
+    const size_t lds_budget = 64 * 1024;
+    int C = 1;
+    while (C * 2 <= N2 && (size_t)(2 * (C * 2) * N1 + N1) * sizeof(T2) <= lds_budget && C * 2 <= 16) C *= 2;
+    sh.C = C;
+    const size_t smemA = (size_t)(2 * C * N1 + N1) * sizeof(T2);
+    const size_t smemB = (size_t)(5 * N2) * sizeof(T2);
+    const void *kerA[2] = {(const void *)k_fft_cols<T>, (const void *)k_fft_cols_inv<T>};
+    for (const void *kk : kerA)
+        if (smemA > 64 * 1024 &&
+            hipFuncSetAttribute(kk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smemA) != hipSuccess)
+            return fail(LW_E_UNSUPPORTED, "lw_spectrum_fft_bwd: LDS request of %zu bytes refused", smemA);
+    if (smemB > 64 * 1024 && hipFuncSetAttribute((const void *)k_fft_rows_bwd<T>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smemB) != hipSuccess)
+        return fail(LW_E_UNSUPPORTED, "lw_spectrum_fft_bwd: LDS request of %zu bytes refused", smemB);
+    const int64_t pairs = (n_pix + 1) / 2;
+    const int64_t batch = std::min<int64_t>(pairs, (int64_t)(ws_bytes / per_pair_bytes<T>(n_obs)));
+    T2 *Y = (T2 *)ws;
+    const T scale = (T)(dt_obs * dt_obs / kPi);
+    for (int64_t p0 = 0; p0 < pairs; p0 += batch) {
+        const int64_t nb = std::min(batch, pairs - p0);
+        sh.pair0 = p0;
+        k_fft_cols<T><<<dim3(N2 / C, 3, (unsigned)nb), 256, smemA, s>>>(E, Y, sh);
+        k_fft_rows_bwd<T><<<dim3(N1 / 2 + 1, (unsigned)nb, 1), 256, smemB, s>>>(Y, dS, sh);
+        k_fft_cols_inv<T><<<dim3(N2 / C, 3, (unsigned)nb), 256, smemA, s>>>(Y, dE, sh, scale);
+    }
+    return check_launch("lw_spectrum_fft_bwd");
+}
+
 }  // namespace
 
 size_t fft_ws_bytes(int64_t n_pix, int64_t n_obs, int prec)
@@ -374,4 +551,21 @@ lw_status launch_fft(const void *E, int64_t n_pix, int64_t n_obs, double dt_obs,
     return run_fft<float>((const float *)E, n_pix, n_obs, dt_obs, (float *)S, ws, ws_bytes, s);
 }
 
+}  // namespace lw
+
+namespace lw {
+lw_status launch_fft_bwd(const void *E, const void *dS, int64_t n_pix, int64_t n_obs, double dt_obs, int prec,
+                         void *dE, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    if (n_pix == 0) return LW_OK;
+    const size_t per = prec == LW_PREC_FP64 ? per_pair_bytes<double>(n_obs) : per_pair_bytes<float>(n_obs);
+    if (!ws || ws_bytes < per)
+        return fail(LW_E_WORKSPACE, "lw_spectrum_fft_bwd: workspace of %zu bytes < %zu needed for one pixel pair",
+                    ws_bytes, per);
+    if (prec == LW_PREC_FP64)
+        return run_fft_bwd<double>((const double *)E, (const double *)dS, n_pix, n_obs, dt_obs, (double *)dE, ws,
+                                   ws_bytes, s);
+    return run_fft_bwd<float>((const float *)E, (const float *)dS, n_pix, n_obs, dt_obs, (float *)dE, ws, ws_bytes,
+                              s);
+}
 }  // namespace lw

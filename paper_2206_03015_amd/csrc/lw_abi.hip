@@ -91,8 +91,9 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec)
 {
     switch (which) {
     case LW_WS_DEPOSIT:
-    case LW_WS_DEPOSIT_BWD:
         return deposit_ws_bytes(n_a, n_b);
+    case LW_WS_DEPOSIT_BWD:
+        return 0;
     case LW_WS_FFT:
     case LW_WS_FFT_BWD:
         return fft_ws_bytes(n_a, n_b, prec);
@@ -184,16 +185,43 @@ lw_status lw_trajectory_boris(const lw_traj_t *traj, double *r, double *beta, do
     return launch_boris(traj, r, beta, beta_dot, stream);
 }
 
-lw_status lw_spectrum_fft_bwd(const void *, const void *, int64_t, int64_t, double, int, void *, void *, size_t,
-                              hipStream_t)
+lw_status lw_spectrum_fft_bwd(const void *E, const void *dS, int64_t n_pix, int64_t n_obs, double dt_obs, int prec,
+                              void *dE, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    return fail(LW_E_UNSUPPORTED, "lw_spectrum_fft_bwd: not built yet");
+    const char *fn = "lw_spectrum_fft_bwd";
+    if (prec != LW_PREC_FP64 && prec != LW_PREC_MIXED) return fail(LW_E_ARG, "%s: unknown prec %d", fn, prec);
+    if (n_pix < 0) return fail(LW_E_SHAPE, "%s: n_pix < 0", fn);
+    if (!pow2(n_obs) || n_obs < 4 || n_obs > (int64_t(1) << 22))
+        return fail(LW_E_SHAPE, "%s: n_obs must be a power of two in [4, 2^22] (got %lld)", fn, (long long)n_obs);
+    if (!finite_pos(dt_obs)) return fail(LW_E_ARG, "%s: dt_obs must be positive and finite", fn);
+    if (n_pix > 0 && (!E || !dS || !dE)) return fail(LW_E_ARG, "%s: E, dS and dE must be non-NULL", fn);
+    if ((E && !aligned(E, 16)) || (dS && !aligned(dS, 16)) || (dE && !aligned(dE, 16)) || (ws && !aligned(ws, 256)))
+        return fail(LW_E_ALIGN, "%s: E, dS, dE must be 16-byte and ws 256-byte aligned", fn);
+    if (E == (const void *)dE) return fail(LW_E_ARG, "%s: dE must not alias E", fn);
+    return launch_fft_bwd(E, dS, n_pix, n_obs, dt_obs, prec, dE, ws, ws_bytes, stream);
 }
 
-lw_status lw_deposit_td_bwd(const lw_traj_t *, const lw_grid_t *, int, int, int, const void *, double *, double *,
-                            double *, void *, size_t, hipStream_t)
+lw_status lw_deposit_td_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom,
+                            const void *dE, double *d_r, double *d_beta, double *d_beta_dot, void *ws,
+                            size_t ws_bytes, hipStream_t stream)
 {
-    return fail(LW_E_UNSUPPORTED, "lw_deposit_td_bwd: not built yet");
+    (void)ws;
+    (void)ws_bytes;
+    const char *fn = "lw_deposit_td_bwd";
+    lw_status st = check_traj_samples(traj, fn);
+    if (st != LW_OK) return st;
+    if ((st = check_grid(grid, fn, true)) != LW_OK) return st;
+    if (prec == LW_PREC_MIXED) return fail(LW_E_UNSUPPORTED, "%s: only LW_PREC_FP64 is supported", fn);
+    if (prec != LW_PREC_FP64) return fail(LW_E_ARG, "%s: unknown prec %d", fn, prec);
+    if (field_mask <= 0 || (field_mask & ~(LW_FIELD_ACCEL | LW_FIELD_VELOCITY)))
+        return fail(LW_E_ARG, "%s: field_mask must be a non-empty combination of LW_FIELD_*", fn);
+    if (geom != LW_GEOM_EXACT && geom != LW_GEOM_FARFIELD) return fail(LW_E_ARG, "%s: unknown geometry %d", fn, geom);
+    if (traj->n_particles > 0 && grid->n_pix > 0 && (!dE || !d_r || !d_beta || !d_beta_dot))
+        return fail(LW_E_ARG, "%s: dE, d_r, d_beta, d_beta_dot must be non-NULL", fn);
+    if ((dE && !aligned(dE, 16)) || (d_r && !aligned(d_r, 8)) || (d_beta && !aligned(d_beta, 8)) ||
+        (d_beta_dot && !aligned(d_beta_dot, 8)))
+        return fail(LW_E_ALIGN, "%s: misaligned pointer", fn);
+    return launch_deposit_bwd(traj, grid, field_mask, geom, (const double *)dE, d_r, d_beta, d_beta_dot, stream);
 }
 
 lw_status lw_direct_fd_bwd(const lw_traj_t *, const lw_grid_t *, const double *, int64_t, int, int, int,

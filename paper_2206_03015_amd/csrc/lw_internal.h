@@ -137,6 +137,81 @@ __device__ __forceinline__ void lw_field(const PixGeo &g, const double *xm, doub
     }
 }
 
+// Vector-Jacobian product of lw_field (double): given g = dJ/dE at one (sample, pixel), adds
+// dJ/dr, dJ/dbeta, dJ/dbeta_dot to gr, gb, ga.  Reverse mode written from the field formula
+// E = P [F_vel (1-b^2)(n-b)/(kappa^3 R^2) + F_acc n x ((n-b) x a)/(c kappa^3 R)], kappa = 1 - n.b,
+// with n = (x - r)/R, R = |x - r| (exact geometry) or n, R fixed (far field).
+template <int GEOM>
+__device__ __forceinline__ void lw_field_vjp(const PixGeo &g, const double *xm, const double *r, const double *b,
+                                             const double *a, double q, int fmask, const double *gE, double *gr,
+                                             double *gb, double *ga)
+{
+    double n[3], R;
+    if (GEOM == LW_GEOM_EXACT) {
+        const double d0 = xm[0] - r[0], d1 = xm[1] - r[1], d2 = xm[2] - r[2];
+        R = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        n[0] = d0 / R;
+        n[1] = d1 / R;
+        n[2] = d2 / R;
+    } else {
+        n[0] = g.nx;
+        n[1] = g.ny;
+        n[2] = g.nz;
+        R = g.D;
+    }
+    const double b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    const double bn = sqrt(b2);
+    double kappa = 1.0;
+    if (bn > 0.0) {
+        const double ib = 1.0 / bn;
+        const double e0 = n[0] - b[0] * ib, e1 = n[1] - b[1] * ib, e2 = n[2] - b[2] * ib;
+        kappa = (1.0 - b2) / (1.0 + bn) + 0.5 * bn * (e0 * e0 + e1 * e1 + e2 * e2);
+    }
+    const double P = q * kCoulomb;
+    const double k3 = kappa * kappa * kappa;
+    const double nb[3] = {n[0] - b[0], n[1] - b[1], n[2] - b[2]};
+    double gn[3] = {0, 0, 0}, gnb[3] = {0, 0, 0}, gk = 0.0, gR = 0.0, gbb[3] = {0, 0, 0};
+    if (fmask & LW_FIELD_ACCEL) {
+        const double w[3] = {nb[1] * a[2] - nb[2] * a[1], nb[2] * a[0] - nb[0] * a[2], nb[0] * a[1] - nb[1] * a[0]};
+        const double v[3] = {n[1] * w[2] - n[2] * w[1], n[2] * w[0] - n[0] * w[2], n[0] * w[1] - n[1] * w[0]};
+        const double sa = P / (kC * k3 * R);
+        const double gsa = gE[0] * v[0] + gE[1] * v[1] + gE[2] * v[2];
+        const double gv[3] = {sa * gE[0], sa * gE[1], sa * gE[2]};
+        // v = n x w : gn += w x gv ; gw = gv x n
+        gn[0] += w[1] * gv[2] - w[2] * gv[1];
+        gn[1] += w[2] * gv[0] - w[0] * gv[2];
+        gn[2] += w[0] * gv[1] - w[1] * gv[0];
+        const double gw[3] = {gv[1] * n[2] - gv[2] * n[1], gv[2] * n[0] - gv[0] * n[2], gv[0] * n[1] - gv[1] * n[0]};
+        // w = nb x a : gnb += a x gw ; ga += gw x nb
+        gnb[0] += a[1] * gw[2] - a[2] * gw[1];
+        gnb[1] += a[2] * gw[0] - a[0] * gw[2];
+        gnb[2] += a[0] * gw[1] - a[1] * gw[0];
+        ga[0] += gw[1] * nb[2] - gw[2] * nb[1];
+        ga[1] += gw[2] * nb[0] - gw[0] * nb[2];
+        ga[2] += gw[0] * nb[1] - gw[1] * nb[0];
+        gk += gsa * (-3.0 * sa / kappa);
+        gR += gsa * (-sa / R);
+    }
+    if (fmask & LW_FIELD_VELOCITY) {
+        const double sv = P * (1.0 - b2) / (k3 * R * R);
+        const double gsv = gE[0] * nb[0] + gE[1] * nb[1] + gE[2] * nb[2];
+        for (int c = 0; c < 3; ++c) gnb[c] += sv * gE[c];
+        const double gb2 = gsv * (-P / (k3 * R * R));
+        gk += gsv * (-3.0 * sv / kappa);
+        gR += gsv * (-2.0 * sv / R);
+        for (int c = 0; c < 3; ++c) gbb[c] += 2.0 * gb2 * b[c];
+    }
+    for (int c = 0; c < 3; ++c) {
+        gn[c] += gnb[c] - gk * b[c];
+        gbb[c] += -gnb[c] - gk * n[c];
+        gb[c] += gbb[c];
+    }
+    if (GEOM == LW_GEOM_EXACT) {
+        const double gnn = gn[0] * n[0] + gn[1] * n[1] + gn[2] * n[2];
+        for (int c = 0; c < 3; ++c) gr[c] -= (gn[c] - gnn * n[c]) / R + gR * n[c];
+    }
+}
+
 __device__ __forceinline__ bool sample_usable(const double *r, const double *b, const double *a)
 {
     bool ok = true;
@@ -155,9 +230,13 @@ size_t deposit_ws_bytes(int64_t n_particles, int64_t n_samples);
 lw_status launch_fft(const void *E, int64_t n_pix, int64_t n_obs, double dt_obs, int prec, void *S, void *ws,
                      size_t ws_bytes, hipStream_t s);
 size_t fft_ws_bytes(int64_t n_pix, int64_t n_obs, int prec);
+lw_status launch_fft_bwd(const void *E, const void *dS, int64_t n_pix, int64_t n_obs, double dt_obs, int prec,
+                         void *dE, void *ws, size_t ws_bytes, hipStream_t s);
 lw_status launch_direct_fd(const lw_traj_t *traj, const lw_grid_t *grid, const double *omega, int64_t n_omega,
                            int prec, int field_mask, int geom, double *S, void *ws, size_t ws_bytes, hipStream_t s);
 size_t direct_fd_ws_bytes(int64_t n_pix, int64_t n_omega);
 lw_status launch_boris(const lw_traj_t *traj, double *r, double *beta, double *beta_dot, hipStream_t s);
+lw_status launch_deposit_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int field_mask, int geom, const double *dE,
+                             double *d_r, double *d_beta, double *d_beta_dot, hipStream_t s);
 
 }  // namespace lw

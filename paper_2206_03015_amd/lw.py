@@ -228,3 +228,39 @@ def trajectory_boris(init, n_samples, t_start, dt, a0, lam, w0, n_cycles, out=No
     r, b, bd = out
     _check(lib.lw_trajectory_boris(ctypes.byref(tr), _ptr(r), _ptr(b), _ptr(bd), _stream()))
     return r, b, bd
+
+
+def spectrum_fft_bwd(E, dS, dt_obs, prec=None, out=None, ws=None):
+    """lw_spectrum_fft_bwd: dJ/dE [n_pix][3][n_obs] from dJ/dS [n_pix][n_obs/2+1] and the trace E."""
+    lib = load()
+    if prec is None:
+        prec = "fp64" if E.dtype == torch.float64 else "mixed"
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    n_pix, _, n_obs = (int(v) for v in E.shape)
+    _need(E, dtype, (n_pix, 3, n_obs), "E")
+    _need(dS, dtype, (n_pix, n_obs // 2 + 1), "dS")
+    if out is None:
+        out = torch.empty_like(E)
+    _need(out, dtype, (n_pix, 3, n_obs), "dE")
+    if ws is None:
+        ws = _workspace(workspace_bytes(WS_FFT_BWD, n_pix, n_obs, prec), E.device)
+    _check(lib.lw_spectrum_fft_bwd(_ptr(E), _ptr(dS), n_pix, n_obs, float(dt_obs), PREC[prec], _ptr(out), _ptr(ws),
+                                   ws.numel(), _stream()))
+    return out
+
+
+def deposit_td_bwd(r, beta, beta_dot, t_start, dt, x_det, t0, dt_obs, n_obs, dE, field_mask=FIELD_ACCEL,
+                   geom="exact", charge=None, out=None):
+    """lw_deposit_td_bwd (FP64): adds dJ/d(r, beta, beta_dot) into `out` (zeros if None) and returns it."""
+    lib = load()
+    tr = make_traj(r, beta, beta_dot, t_start, dt, charge)
+    gr = make_grid(x_det, t0, dt_obs, n_obs)
+    _need(dE, torch.float64, (gr.n_pix, 3, int(n_obs)), "dE")
+    if out is None:
+        out = tuple(torch.zeros_like(r) for _ in range(3))
+    d_r, d_b, d_bd = out
+    for t, nm in ((d_r, "d_r"), (d_b, "d_beta"), (d_bd, "d_beta_dot")):
+        _need(t, torch.float64, tuple(r.shape), nm)
+    _check(lib.lw_deposit_td_bwd(ctypes.byref(tr), ctypes.byref(gr), PREC["fp64"], int(field_mask), GEOM[geom],
+                                 _ptr(dE), _ptr(d_r), _ptr(d_b), _ptr(d_bd), None, 0, _stream()))
+    return d_r, d_b, d_bd
