@@ -206,6 +206,23 @@ lw_status lw_direct_fd(const lw_traj_t *traj, const lw_grid_t *grid, const doubl
 lw_status lw_trajectory_boris(const lw_traj_t *traj, double *r, double *beta, double *beta_dot, hipStream_t stream);
 
 /*
+ * lw_trajectory_boris_bwd -- gradient of a scalar J through lw_trajectory_boris
+ * (chains the sample gradients of lw_deposit_td_bwd to the beam's initial phase
+ * space and to the laser amplitude a0).  Given g_r = dJ/dr, g_beta = dJ/dbeta,
+ * g_beta_dot = dJ/dbeta_dot [n_particles][n_samples][3] (double), writes
+ *   grad_init[k][c] = dJ/d init[k][c]        [n_particles][6]   (overwritten)
+ *   grad_a0[k]      = the part of dJ/d a0 carried by particle k   [n_particles]
+ *                     (dJ/d a0 = sum_k grad_a0[k]; overwritten)
+ * The pusher is the one of lw_trajectory_boris, recomputed in FP64 with forward-mode
+ * tangents, one per particle and parameter (each trajectory depends only on its own
+ * initial condition and on a0).  traj: kind LW_TRAJ_BORIS, as for
+ * lw_trajectory_boris.  All arrays device memory, 8-byte aligned, non-NULL when
+ * n_particles > 0.
+ */
+lw_status lw_trajectory_boris_bwd(const lw_traj_t *traj, const double *g_r, const double *g_beta,
+                                  const double *g_beta_dot, double *grad_init, double *grad_a0, hipStream_t stream);
+
+/*
  * lw_spectrum_fft_bwd -- adjoint of lw_spectrum_fft: given dJ/dS (same layout
  * as S) and the trace E the forward pass used, writes
  *   dE[m][c][u] = dJ/dE[m][c][u] = (dt_obs^2/2pi) sum_j dS[m][j] * 2 Re( conj(F_c[j]) dF_c[j]/dE[c][u] ).

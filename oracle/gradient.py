@@ -10,6 +10,13 @@
   derivative of the FP64 chain along v (complex-step differentiation; every
   discrete decision uses real parts).  Pinned against central finite differences of
   the real C oracle and against the real part of the C oracle itself.
+* ``boris_complex``: the leap-frog Boris pusher of the C oracle's ``orc_boris`` written
+  with numpy over particles in complex arithmetic, so that a complex step in the initial
+  phase space or in a0 gives the exact directional derivative of the trajectory (the
+  forward-mode tangent of the pusher).  Pinned against the real C oracle (real part) and
+  against its central differences (imaginary part).
+* ``params_derivative``: dJ/dgamma_mean and dJ/da0 of the band objective by one complex
+  step through the seeded bunch draw, the pusher and the chain above.
 """
 from __future__ import annotations
 
@@ -18,6 +25,7 @@ import numpy as np
 C_LIGHT = 299792458.0
 Q_E = 1.602176634e-19
 EPS0 = 8.8541878128e-12
+M_E = 9.1093837015e-31
 
 
 def spectrum_vjp(E_tot, dS, dt_obs):
@@ -127,4 +135,87 @@ def directional_derivative(t_start, dt, r, b, a, v_r, v_b, v_a, x_det, t0, dt_ob
     """Complex-step derivative of J along (v_r, v_b, v_a) at (r, b, a)."""
     J = chain_complex(t_start, dt, r + 1j * h * v_r, b + 1j * h * v_b, a + 1j * h * v_a, x_det, t0, dt_obs, n_obs,
                       weights, dE, charge, field_mask, geom)
+    return J.imag / h, J.real
+
+
+def _laser_eb(lam, w0, n_cycles, a0, x, y, z, t):
+    """E_x and B_y of the x-polarised pulse travelling along -z (normalised vector potential
+    a0 g(phi) sin(phi), g = cos^2(phi/(2 n_cycles)) on |phi| < pi n_cycles, phi = wl (t + z/c),
+    transverse factor exp(-(x^2+y^2)/w0^2) when w0 > 0): E_x = -E0 T d(g sin)/dphi, B_y = -E_x/c."""
+    wl = 2.0 * np.pi * C_LIGHT / lam
+    phi = wl * (t + z / C_LIGHT)
+    inside = np.abs(phi.real) < np.pi * n_cycles
+    g = np.cos(phi / (2.0 * n_cycles)) ** 2
+    gp = -np.sin(phi / n_cycles) / (2.0 * n_cycles)
+    sp = gp * np.sin(phi) + g * np.cos(phi)
+    T = np.exp(-(x * x + y * y) / (w0 * w0)) if w0 > 0.0 else 1.0
+    E0 = a0 * M_E * C_LIGHT * wl / Q_E
+    Ex = np.where(inside, -E0 * T * sp, 0.0)
+    return Ex, -Ex / C_LIGHT
+
+
+def _kick(u, Ex, By, h):
+    """Boris update of u = gamma beta [n][3] over time h for electrons in E = (Ex,0,0), B = (0,By,0):
+    half electric kick, magnetic rotation with t = q h B/(2 m gamma), s = 2 t/(1+t^2), half kick."""
+    q, m = -Q_E, M_E
+    a = q * h / (2.0 * m * C_LIGHT)
+    um = u + np.stack([a * Ex, 0.0 * Ex, 0.0 * Ex], axis=-1)
+    gm = np.sqrt(1.0 + _dot(um, um))
+    tv = np.stack([0.0 * By, q * h * By / (2.0 * m * gm), 0.0 * By], axis=-1)
+    sv = 2.0 * tv / (1.0 + _dot(tv, tv))[:, None]
+    up = um + np.cross(um, tv)
+    return um + np.cross(up, sv) + np.stack([a * Ex, 0.0 * Ex, 0.0 * Ex], axis=-1)
+
+
+def boris_complex(init, n_samples, t_start, dt, a0, lam, w0, n_cycles):
+    """r, beta, beta_dot [n_p][n_samples][3] of electrons from init [n_p][6] (x, y, z, u = gamma beta)
+    by the leap-frog Boris scheme: u_{1/2} from a half kick at (r_0, t_0); r_{i+1} = r_i + c u_{i+1/2}
+    / gamma_{i+1/2} dt; u_{i+3/2} from a full kick at (r_{i+1}, t_{i+1}); beta_0 from u_0 and
+    beta_i from (u_{i-1/2} + u_{i+1/2})/2; beta_dot from the Lorentz force
+    q/(gamma m c) [E + c beta x B - beta (beta.E)].  Complex inputs allowed (complex step)."""
+    init = np.asarray(init)
+    dtype = np.result_type(init, a0, np.float64)
+    n_p = init.shape[0]
+    r = np.empty((n_p, n_samples, 3), dtype=dtype)
+    b = np.empty_like(r)
+    bd = np.empty_like(r)
+    x = init[:, :3].astype(dtype)
+    us = init[:, 3:].astype(dtype)
+    q, m = -Q_E, M_E
+    Ex, By = _laser_eb(lam, w0, n_cycles, a0, x[:, 0], x[:, 1], x[:, 2], t_start)
+    uh = _kick(us, Ex, By, 0.5 * dt)
+    for i in range(n_samples):
+        ti = t_start + i * dt
+        g = np.sqrt(1.0 + _dot(us, us))
+        bb = us / g[:, None]
+        Ex, By = _laser_eb(lam, w0, n_cycles, a0, x[:, 0], x[:, 1], x[:, 2], ti)
+        E = np.stack([Ex, 0.0 * Ex, 0.0 * Ex], axis=-1)
+        B = np.stack([0.0 * By, By, 0.0 * By], axis=-1)
+        f = q / (g * m * C_LIGHT)
+        r[:, i] = x
+        b[:, i] = bb
+        bd[:, i] = f[:, None] * (E + C_LIGHT * np.cross(bb, B) - bb * _dot(bb, E)[:, None])
+        if i + 1 == n_samples:
+            break
+        gh = np.sqrt(1.0 + _dot(uh, uh))
+        x = x + C_LIGHT * uh / gh[:, None] * dt
+        Ex, By = _laser_eb(lam, w0, n_cycles, a0, x[:, 0], x[:, 1], x[:, 2], t_start + (i + 1) * dt)
+        un = _kick(uh, Ex, By, dt)
+        us = 0.5 * (uh + un)
+        uh = un
+    return r, b, bd
+
+
+def params_derivative(init_of_gamma, gamma, a0, laser, n_samples, t_start, dt, x_det, t0, dt_obs, n_obs, weights,
+                      which, geom=0, h=1e-30):
+    """Complex-step dJ/dgamma_mean (which = "gamma") or dJ/da0 (which = "a0") of
+    J = sum(weights * S) with trajectories from ``boris_complex`` and initial conditions
+    init_of_gamma(gamma) (the seeded bunch draw at mean Lorentz factor gamma).
+    laser = (lam, w0, n_cycles).  Returns (derivative, J)."""
+    lam, w0, n_cycles = laser
+    g = gamma + (1j * h if which == "gamma" else 0.0)
+    a = a0 + (1j * h if which == "a0" else 0.0)
+    init = init_of_gamma(g)
+    r, b, bd = boris_complex(init, n_samples, t_start, dt, a, lam, w0, n_cycles)
+    J = chain_complex(t_start, dt, r, b, bd, x_det, t0, dt_obs, n_obs, weights=weights, geom=geom)
     return J.imag / h, J.real

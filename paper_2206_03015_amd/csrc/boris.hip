@@ -1,6 +1,7 @@
 // FP64 Boris trajectories of electrons in the laser pulse (the trajectory source of
 // the time-domain method; the paper integrates the equations of motion with the
-// Boris method).  One lane per particle; the samples are written as
+// Boris method), and their forward-mode tangents with respect to the initial phase
+// space and the laser amplitude a0.  One lane per particle; samples are
 // r, beta, beta_dot [n_particles][n_samples][3].
 #include "lw_internal.h"
 
@@ -9,92 +10,229 @@
 namespace lw {
 namespace {
 
+// ---- dual numbers: value and ND directional derivatives --------------------------------------
+template <int ND>
+struct Dual {
+    double v;
+    double d[ND];
+    Dual() = default;
+    __device__ __forceinline__ Dual(double x) : v(x)
+    {
+#pragma unroll
+        for (int j = 0; j < ND; ++j) d[j] = 0.0;
+    }
+};
+template <int ND>
+__device__ __forceinline__ Dual<ND> operator+(Dual<ND> a, Dual<ND> b)
+{
+    Dual<ND> r;
+    r.v = a.v + b.v;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) r.d[j] = a.d[j] + b.d[j];
+    return r;
+}
+template <int ND>
+__device__ __forceinline__ Dual<ND> operator-(Dual<ND> a, Dual<ND> b)
+{
+    Dual<ND> r;
+    r.v = a.v - b.v;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) r.d[j] = a.d[j] - b.d[j];
+    return r;
+}
+template <int ND>
+__device__ __forceinline__ Dual<ND> operator-(Dual<ND> a)
+{
+    Dual<ND> r;
+    r.v = -a.v;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) r.d[j] = -a.d[j];
+    return r;
+}
+template <int ND>
+__device__ __forceinline__ Dual<ND> operator*(Dual<ND> a, Dual<ND> b)
+{
+    Dual<ND> r;
+    r.v = a.v * b.v;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) r.d[j] = a.d[j] * b.v + a.v * b.d[j];
+    return r;
+}
+template <int ND>
+__device__ __forceinline__ Dual<ND> operator/(Dual<ND> a, Dual<ND> b)
+{
+    Dual<ND> r;
+    r.v = a.v / b.v;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) r.d[j] = (a.d[j] - r.v * b.d[j]) / b.v;
+    return r;
+}
+template <int ND>
+__device__ __forceinline__ Dual<ND> operator*(double a, Dual<ND> b)
+{
+    Dual<ND> r;
+    r.v = a * b.v;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) r.d[j] = a * b.d[j];
+    return r;
+}
+template <int ND>
+__device__ __forceinline__ Dual<ND> operator*(Dual<ND> b, double a)
+{
+    return a * b;
+}
+template <int ND>
+__device__ __forceinline__ Dual<ND> operator/(Dual<ND> b, double a)
+{
+    Dual<ND> r;
+    r.v = b.v / a;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) r.d[j] = b.d[j] / a;
+    return r;
+}
+template <int ND>
+__device__ __forceinline__ Dual<ND> operator/(double a, Dual<ND> b)
+{
+    Dual<ND> r;
+    r.v = a / b.v;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) r.d[j] = -r.v * b.d[j] / b.v;
+    return r;
+}
+template <int ND>
+__device__ __forceinline__ Dual<ND> operator+(Dual<ND> a, double b)
+{
+    a.v += b;
+    return a;
+}
+template <int ND>
+__device__ __forceinline__ Dual<ND> operator+(double b, Dual<ND> a)
+{
+    a.v += b;
+    return a;
+}
+template <int ND>
+__device__ __forceinline__ Dual<ND> operator-(double b, Dual<ND> a)
+{
+    return b + (-a);
+}
+using ::exp;  // the double overloads stay visible beside the dual ones
+using ::sincos;
+using ::sqrt;
+template <int ND>
+__device__ __forceinline__ Dual<ND> sqrt(Dual<ND> a)
+{
+    Dual<ND> r;
+    r.v = ::sqrt(a.v);
+#pragma unroll
+    for (int j = 0; j < ND; ++j) r.d[j] = a.d[j] / (2.0 * r.v);
+    return r;
+}
+template <int ND>
+__device__ __forceinline__ Dual<ND> exp(Dual<ND> a)
+{
+    Dual<ND> r;
+    r.v = ::exp(a.v);
+#pragma unroll
+    for (int j = 0; j < ND; ++j) r.d[j] = a.d[j] * r.v;
+    return r;
+}
+template <int ND>
+__device__ __forceinline__ void sincos(Dual<ND> a, Dual<ND> *s, Dual<ND> *c)
+{
+    double sv, cv;
+    ::sincos(a.v, &sv, &cv);
+    s->v = sv;
+    c->v = cv;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+        s->d[j] = a.d[j] * cv;
+        c->d[j] = -a.d[j] * sv;
+    }
+}
+__device__ __forceinline__ double val(double a) { return a; }
+template <int ND>
+__device__ __forceinline__ double val(const Dual<ND> &a)
+{
+    return a.v;
+}
+
+// ---- the laser pulse and the pusher, written once for double and for dual numbers -----------
 struct LaserDev {
-    double a0, wl, w0, nc, E0;  // wl = 2 pi c / lambda, E0 = a0 m_e c wl / e
+    double a0, wl, w0, nc, e0_per_a0;  // wl = 2 pi c / lambda, E0 = a0 e0_per_a0, e0_per_a0 = m_e c wl / e
 };
 
 // Pulse written through its normalised vector potential a_x = a0 g(phi) sin(phi),
 // g = cos^2(phi/(2 nc)) on |phi| < pi nc, phi = wl (t + z/c):
 // E_x = -E0 T(rho) d(g sin)/dphi, B_y = -E_x / c, T = exp(-rho^2/w0^2) (w0 > 0).
-__device__ __forceinline__ void laser_eb(const LaserDev &L, double x, double y, double z, double t, double &Ex,
-                                         double &By)
+template <typename R>
+__device__ __forceinline__ void laser_eb(const LaserDev &L, R a0, R x, R y, R z, double t, R &Ex, R &By)
 {
-    const double phi = L.wl * (t + z / kC);
+    const R phi = L.wl * (t + z / kC);
     Ex = 0.0;
     By = 0.0;
-    if (!(fabs(phi) < kPi * L.nc)) return;
-    double sh, ch, sp, cp, s2, c2;
+    if (!(fabs(val(phi)) < kPi * L.nc)) return;
+    R sh, ch, sp, cp, s2, c2;
     sincos(phi / (2.0 * L.nc), &sh, &ch);
     sincos(phi, &sp, &cp);
     sincos(phi / L.nc, &s2, &c2);
-    const double g = ch * ch;
-    const double gp = -s2 / (2.0 * L.nc);
-    const double dS = gp * sp + g * cp;
-    double T = 1.0;
-    if (L.w0 > 0.0) T = exp(-(x * x + y * y) / (L.w0 * L.w0));
-    Ex = -L.E0 * T * dS;
-    By = -Ex / kC;
+    const R g = ch * ch;
+    const R gp = -(s2 / (2.0 * L.nc));
+    const R dS = gp * sp + g * cp;
+    R T = 1.0;
+    if (L.w0 > 0.0) T = exp(-((x * x + y * y) / (L.w0 * L.w0)));
+    Ex = -(L.e0_per_a0 * (a0 * T * dS));
+    By = -(Ex / kC);
 }
 
 // Boris update of u = gamma beta over time h for an electron, with E = (Ex,0,0), B = (0,By,0).
-__device__ __forceinline__ void kick(double &ux, double &uy, double &uz, double Ex, double By, double h)
+template <typename R>
+__device__ __forceinline__ void kick(R &ux, R &uy, R &uz, R Ex, R By, double h)
 {
     const double q = -kQe, m = kMe;
     const double a = q * h / (2.0 * m * kC);
-    double mx = ux + a * Ex, my = uy, mz = uz;
-    const double gm = sqrt(1.0 + mx * mx + my * my + mz * mz);
-    const double ty = q * h * By / (2.0 * m * gm);  // rotation vector (0, ty, 0)
-    const double sy = 2.0 * ty / (1.0 + ty * ty);
+    const R mx = ux + a * Ex, my = uy, mz = uz;
+    const R gm = sqrt(1.0 + (mx * mx + my * my + mz * mz));
+    const R ty = (q * h / (2.0 * m)) * By / gm;  // rotation vector (0, ty, 0)
+    const R sy = 2.0 * ty / (1.0 + ty * ty);
     // u' = u- + u- x t ;  u+ = u- + u' x s
-    const double px = mx - mz * ty, py = my, pz = mz + mx * ty;
-    const double nx = mx - pz * sy, ny = my, nz = mz + px * sy;
+    const R px = mx - mz * ty, pz = mz + mx * ty;
+    const R nx = mx - pz * sy, nz = mz + px * sy;
     ux = nx + a * Ex;
-    uy = ny;
+    uy = my;
     uz = nz;
 }
 
-__global__ __launch_bounds__(256) void k_boris(const double *__restrict__ init, int64_t n_particles,
-                                               int64_t n_samples, double t_start, double dt, LaserDev L,
-                                               double *__restrict__ r, double *__restrict__ beta,
-                                               double *__restrict__ beta_dot)
+// Runs the pusher of one particle and calls emit(i, r[3], beta[3], beta_dot[3]) per sample.
+template <typename R, typename Emit>
+__device__ __forceinline__ void push_particle(const LaserDev &L, R a0, const R *init, int64_t n_samples,
+                                              double t_start, double dt, Emit emit)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_particles) return;
-    double x = init[6 * k], y = init[6 * k + 1], z = init[6 * k + 2];
-    double usx = init[6 * k + 3], usy = init[6 * k + 4], usz = init[6 * k + 5];  // u at the sample time
-    double uhx = usx, uhy = usy, uhz = usz;                                      // u half a step later
-    double Ex, By;
-    laser_eb(L, x, y, z, t_start, Ex, By);
+    R x = init[0], y = init[1], z = init[2];
+    R usx = init[3], usy = init[4], usz = init[5];  // u at the sample time
+    R uhx = usx, uhy = usy, uhz = usz;              // u half a step later
+    R Ex, By;
+    laser_eb(L, a0, x, y, z, t_start, Ex, By);
     kick(uhx, uhy, uhz, Ex, By, 0.5 * dt);
     const double q = -kQe, m = kMe;
     for (int64_t i = 0; i < n_samples; ++i) {
         const double ti = t_start + (double)i * dt;
-        const double g = sqrt(1.0 + usx * usx + usy * usy + usz * usz);
-        const double bx = usx / g, by = usy / g, bz = usz / g;
-        laser_eb(L, x, y, z, ti, Ex, By);
+        const R g = sqrt(1.0 + (usx * usx + usy * usy + usz * usz));
+        const R bx = usx / g, by = usy / g, bz = usz / g;
+        laser_eb(L, a0, x, y, z, ti, Ex, By);
         // d beta/dt = q/(gamma m c) [E + c beta x B - beta (beta.E)],  E = (Ex,0,0), B = (0,By,0)
-        const double f = q / (g * m * kC);
-        const double be = bx * Ex;
-        const double ax = f * (Ex - kC * bz * By - bx * be);
-        const double ay = f * (-by * be);
-        const double az = f * (kC * bx * By - bz * be);
-        const size_t o = (size_t)(k * n_samples + i) * 3;
-        r[o] = x;
-        r[o + 1] = y;
-        r[o + 2] = z;
-        beta[o] = bx;
-        beta[o + 1] = by;
-        beta[o + 2] = bz;
-        beta_dot[o] = ax;
-        beta_dot[o + 1] = ay;
-        beta_dot[o + 2] = az;
+        const R f = (q / (m * kC)) / g;
+        const R be = bx * Ex;
+        const R rr[3] = {x, y, z}, bb[3] = {bx, by, bz};
+        const R aa[3] = {f * (Ex - kC * (bz * By) - bx * be), f * (-(by * be)), f * (kC * (bx * By) - bz * be)};
+        emit(i, rr, bb, aa);
         if (i + 1 == n_samples) break;
-        const double gh = sqrt(1.0 + uhx * uhx + uhy * uhy + uhz * uhz);
-        x += kC * uhx / gh * dt;
-        y += kC * uhy / gh * dt;
-        z += kC * uhz / gh * dt;
-        double nx = uhx, ny = uhy, nz = uhz;
-        laser_eb(L, x, y, z, t_start + (double)(i + 1) * dt, Ex, By);
+        const R gh = sqrt(1.0 + (uhx * uhx + uhy * uhy + uhz * uhz));
+        x = x + (kC * dt) * (uhx / gh);
+        y = y + (kC * dt) * (uhy / gh);
+        z = z + (kC * dt) * (uhz / gh);
+        R nx = uhx, ny = uhy, nz = uhz;
+        laser_eb(L, a0, x, y, z, t_start + (double)(i + 1) * dt, Ex, By);
         kick(nx, ny, nz, Ex, By, dt);
         usx = 0.5 * (uhx + nx);
         usy = 0.5 * (uhy + ny);
@@ -105,21 +243,95 @@ __global__ __launch_bounds__(256) void k_boris(const double *__restrict__ init, 
     }
 }
 
+__global__ __launch_bounds__(256) void k_boris(const double *__restrict__ init, int64_t n_particles,
+                                               int64_t n_samples, double t_start, double dt, LaserDev L,
+                                               double *__restrict__ r, double *__restrict__ beta,
+                                               double *__restrict__ beta_dot)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_particles) return;
+    double in[6];
+    for (int c = 0; c < 6; ++c) in[c] = init[6 * k + c];
+    push_particle<double>(L, L.a0, in, n_samples, t_start, dt,
+                          [&](int64_t i, const double *rr, const double *bb, const double *aa) {
+                              const size_t o = (size_t)(k * n_samples + i) * 3;
+                              for (int c = 0; c < 3; ++c) {
+                                  r[o + c] = rr[c];
+                                  beta[o + c] = bb[c];
+                                  beta_dot[o + c] = aa[c];
+                              }
+                          });
+}
+
+// Gradient through the pusher by forward-mode tangents: lane l handles particle k = l / 7
+// and parameter p = l % 7 (init[k][0..5], then a0), runs the pusher in dual numbers seeded
+// with d/dp = 1 and accumulates sum_i g_r.dr_i/dp + g_beta.dbeta_i/dp + g_bd.dbeta_dot_i/dp.
+// Every trajectory depends only on its own initial condition and on a0, so these seven
+// tangents per particle are the whole gradient.
+constexpr int kParams = 7;
+
+__global__ __launch_bounds__(64) void k_boris_tangent(const double *__restrict__ init, int64_t n_particles,
+                                                      int64_t n_samples, double t_start, double dt, LaserDev L,
+                                                      const double *__restrict__ g_r, const double *__restrict__ g_b,
+                                                      const double *__restrict__ g_a, double *__restrict__ grad_init,
+                                                      double *__restrict__ grad_a0)
+{
+    using D = Dual<1>;
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n_particles * kParams) return;
+    const int64_t k = l / kParams;
+    const int p = (int)(l - k * kParams);
+    D in[6];
+    for (int c = 0; c < 6; ++c) {
+        in[c] = D(init[6 * k + c]);
+        in[c].d[0] = (c == p) ? 1.0 : 0.0;
+    }
+    D a0(L.a0);
+    a0.d[0] = (p == 6) ? 1.0 : 0.0;
+    double acc = 0.0;
+    push_particle<D>(L, a0, in, n_samples, t_start, dt, [&](int64_t i, const D *rr, const D *bb, const D *aa) {
+        const size_t o = (size_t)(k * n_samples + i) * 3;
+        for (int c = 0; c < 3; ++c) acc += g_r[o + c] * rr[c].d[0] + g_b[o + c] * bb[c].d[0] + g_a[o + c] * aa[c].d[0];
+    });
+    if (p < 6)
+        grad_init[6 * k + p] = acc;
+    else
+        grad_a0[k] = acc;
+}
+
+LaserDev laser_dev(const lw_laser_t &l)
+{
+    LaserDev L;
+    L.a0 = l.a0;
+    L.wl = 2.0 * kPi * kC / l.lambda;
+    L.w0 = l.w0;
+    L.nc = l.n_cycles;
+    L.e0_per_a0 = kMe * kC * L.wl / kQe;
+    return L;
+}
+
 }  // namespace
 
 lw_status launch_boris(const lw_traj_t *t, double *r, double *beta, double *beta_dot, hipStream_t s)
 {
     if (t->n_particles == 0) return LW_OK;
-    LaserDev L;
-    L.a0 = t->laser.a0;
-    L.wl = 2.0 * kPi * kC / t->laser.lambda;
-    L.w0 = t->laser.w0;
-    L.nc = t->laser.n_cycles;
-    L.E0 = L.a0 * kMe * kC * L.wl / kQe;
+    const LaserDev L = laser_dev(t->laser);
     const int64_t blocks = (t->n_particles + 63) / 64;
     k_boris<<<(unsigned)blocks, 64, 0, s>>>(t->init, t->n_particles, t->n_samples, t->t_start, t->dt, L, r, beta,
                                            beta_dot);
     return check_launch("lw_trajectory_boris");
+}
+
+lw_status launch_boris_bwd(const lw_traj_t *t, const double *g_r, const double *g_beta, const double *g_beta_dot,
+                           double *grad_init, double *grad_a0, hipStream_t s)
+{
+    if (t->n_particles == 0) return LW_OK;
+    const LaserDev L = laser_dev(t->laser);
+    const int64_t lanes = t->n_particles * kParams;
+    const int64_t blocks = (lanes + 63) / 64;
+    k_boris_tangent<<<(unsigned)blocks, 64, 0, s>>>(t->init, t->n_particles, t->n_samples, t->t_start, t->dt, L, g_r,
+                                                   g_beta, g_beta_dot, grad_init, grad_a0);
+    return check_launch("lw_trajectory_boris_bwd");
 }
 
 }  // namespace lw

@@ -185,6 +185,27 @@ lw_status lw_trajectory_boris(const lw_traj_t *traj, double *r, double *beta, do
     return launch_boris(traj, r, beta, beta_dot, stream);
 }
 
+lw_status lw_trajectory_boris_bwd(const lw_traj_t *traj, const double *g_r, const double *g_beta,
+                                  const double *g_beta_dot, double *grad_init, double *grad_a0, hipStream_t stream)
+{
+    const char *fn = "lw_trajectory_boris_bwd";
+    if (!traj) return fail(LW_E_ARG, "%s: traj is NULL", fn);
+    if (traj->kind != LW_TRAJ_BORIS) return fail(LW_E_ARG, "%s: traj->kind must be LW_TRAJ_BORIS", fn);
+    if (traj->n_particles < 0 || traj->n_samples < 1 || traj->n_samples >= (int64_t(1) << 31) ||
+        traj->n_particles > (int64_t(1) << 28))
+        return fail(LW_E_SHAPE, "%s: bad sizes", fn);
+    if (!finite_pos(traj->dt)) return fail(LW_E_ARG, "%s: dt must be positive and finite", fn);
+    const lw_laser_t &L = traj->laser;
+    if (!finite_pos(L.lambda) || !(L.n_cycles > 0.0) || !(L.a0 >= 0.0 && L.a0 < 1e6) || !(L.w0 < 1e300))
+        return fail(LW_E_ARG, "%s: laser parameters out of range", fn);
+    if (traj->n_particles > 0 && (!traj->init || !g_r || !g_beta || !g_beta_dot || !grad_init || !grad_a0))
+        return fail(LW_E_ARG, "%s: NULL array", fn);
+    for (const void *p : {(const void *)traj->init, (const void *)g_r, (const void *)g_beta, (const void *)g_beta_dot,
+                          (const void *)grad_init, (const void *)grad_a0})
+        if (p && !aligned(p, 8)) return fail(LW_E_ALIGN, "%s: arrays must be 8-byte aligned", fn);
+    return launch_boris_bwd(traj, g_r, g_beta, g_beta_dot, grad_init, grad_a0, stream);
+}
+
 lw_status lw_spectrum_fft_bwd(const void *E, const void *dS, int64_t n_pix, int64_t n_obs, double dt_obs, int prec,
                               void *dE, void *ws, size_t ws_bytes, hipStream_t stream)
 {

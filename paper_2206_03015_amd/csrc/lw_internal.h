@@ -236,6 +236,8 @@ lw_status launch_direct_fd(const lw_traj_t *traj, const lw_grid_t *grid, const d
                            int prec, int field_mask, int geom, double *S, void *ws, size_t ws_bytes, hipStream_t s);
 size_t direct_fd_ws_bytes(int64_t n_pix, int64_t n_omega);
 lw_status launch_boris(const lw_traj_t *traj, double *r, double *beta, double *beta_dot, hipStream_t s);
+lw_status launch_boris_bwd(const lw_traj_t *traj, const double *g_r, const double *g_beta,
+                           const double *g_beta_dot, double *grad_init, double *grad_a0, hipStream_t s);
 lw_status launch_deposit_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int field_mask, int geom, const double *dE,
                              double *d_r, double *d_beta, double *d_beta_dot, hipStream_t s);
 

@@ -133,12 +133,15 @@ def pixel_positions(n_side: int, theta_max: float, D: float = 1.0) -> np.ndarray
     return np.stack([D * np.sin(tx), D * np.cos(tx) * np.sin(ty), D * np.cos(tx) * np.cos(ty)], axis=-1)
 
 
-def bunch_init(w: Workload, n_p: int | None = None) -> np.ndarray:
-    """Initial phase space [n_p][6] = x, y, z (m), u_x, u_y, u_z at t_start."""
+def bunch_init(w: Workload, n_p: int | None = None, gamma=None) -> np.ndarray:
+    """Initial phase space [n_p][6] = x, y, z (m), u_x, u_y, u_z at t_start.  ``gamma`` replaces
+    the mean Lorentz factor of the draw (the normal deviates stay the same); it may be complex,
+    which carries a complex step through the recipe."""
     n = w.n_p if n_p is None else n_p
+    gbar = w.gamma if gamma is None else gamma
     if w.trajectory == "analytic" or w.n_p == 1:
-        uz = np.sqrt(w.gamma ** 2 - 1.0)
-        bz = uz / w.gamma
+        uz = np.sqrt(gbar ** 2 - 1.0)
+        bz = uz / gbar
         return np.array([[0.0, 0.0, bz * C_LIGHT * w.t_start, 0.0, 0.0, uz]])
     rng = np.random.Generator(np.random.PCG64(1000 + w.index))
     xh = rng.standard_normal(w.n_p)
@@ -152,11 +155,46 @@ def bunch_init(w: Workload, n_p: int | None = None) -> np.ndarray:
     z = w.sig_z * zh
     ux = (w.eps_n / w.sig_x) * uxh if w.sig_x > 0 else 0.0 * uxh
     uy = (w.eps_n / w.sig_y) * uyh if w.sig_y > 0 else 0.0 * uyh
-    g = w.gamma * (1.0 + w.sig_gamma * gh)
+    g = gbar * (1.0 + w.sig_gamma * gh)
     uz = np.sqrt(g * g - 1.0 - ux * ux - uy * uy)
     t = w.t_start
-    init = np.stack([x + C_LIGHT * ux / g * t, y + C_LIGHT * uy / g * t, z + C_LIGHT * uz / g * t, ux, uy, uz], axis=-1)
+    init = np.stack([x + C_LIGHT * ux / g * t, y + C_LIGHT * uy / g * t, z + C_LIGHT * uz / g * t,
+                     ux + 0.0 * g, uy + 0.0 * g, uz], axis=-1)
     return np.ascontiguousarray(init[:n])
+
+
+def bunch_init_dgamma(w: Workload, rows=None) -> np.ndarray:
+    """d(init)/d(gamma_mean) of ``bunch_init`` [len(rows)][6] (rows: indices into the full draw,
+    default all), exact to rounding by a complex step h = 1e-30 through the recipe."""
+    h = 1e-30
+    full = bunch_init(w, gamma=w.gamma + 1j * h)
+    sel = full if rows is None else full[np.asarray(rows)]
+    return np.ascontiguousarray(sel.imag / h)
+
+
+def band_weights(w: Workload, x_det: np.ndarray, pixels=None, rel_width: float = 0.02) -> np.ndarray:
+    """Weights W [n_pix][n_obs/2+1] of the band objective J = sum_m sum_j W[m][j] S[m][j]:
+    W = d_omega on the bins with |omega_j - omega1(theta_m)| <= rel_width omega1(theta_m) of the
+    selected pixels (all if None), 0 elsewhere; omega_j = 2 pi j/(n_obs dt_obs), theta_m the polar
+    angle of pixel m, band edges at the nominal gamma and a0."""
+    x_det = np.asarray(x_det, dtype=np.float64).reshape(-1, 3)
+    n_pix = x_det.shape[0]
+    d_omega = 2.0 * np.pi / (w.n_obs * w.dt_obs)
+    omega = d_omega * np.arange(w.n_obs // 2 + 1)
+    W = np.zeros((n_pix, w.n_obs // 2 + 1))
+    sel = range(n_pix) if pixels is None else pixels
+    for m in sel:
+        th = np.arccos(np.clip(x_det[m, 2] / np.linalg.norm(x_det[m]), -1.0, 1.0))
+        w1 = w.omega1(th)
+        W[m, np.abs(omega - w1) <= rel_width * w1] = d_omega
+    return W
+
+
+def central_pixels(n_side: int, n_centre: int) -> np.ndarray:
+    """Indices m = iy n_side + ix of the central n_centre x n_centre block of the pixel grid."""
+    lo = (n_side - n_centre) // 2
+    idx = np.arange(lo, lo + n_centre)
+    return (idx[:, None] * n_side + idx[None, :]).reshape(-1)
 
 
 _PAPER_WORKLOADS = {}

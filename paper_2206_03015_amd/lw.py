@@ -59,6 +59,7 @@ _SIGS = {
     "lw_direct_fd": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), c_vp, c_i64, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_int, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "lw_trajectory_boris": (ctypes.c_int, [ctypes.POINTER(Traj), c_vp, c_vp, c_vp, c_vp]),
+    "lw_trajectory_boris_bwd": (ctypes.c_int, [ctypes.POINTER(Traj), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lw_spectrum_fft_bwd": (ctypes.c_int, [c_vp, c_vp, c_i64, c_i64, c_d, ctypes.c_int, c_vp, c_vp,
                                            ctypes.c_size_t, c_vp]),
     "lw_deposit_td_bwd": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_int,
@@ -209,9 +210,8 @@ def direct_fd(r, beta, beta_dot, t_start, dt, x_det, t0, omega, prec="mixed", fi
     return out
 
 
-def trajectory_boris(init, n_samples, t_start, dt, a0, lam, w0, n_cycles, out=None):
-    """lw_trajectory_boris.  init [n_p][6] float64 device.  Returns (r, beta, beta_dot)."""
-    lib = load()
+def make_boris_traj(init, n_samples, t_start, dt, a0, lam, w0, n_cycles):
+    """Traj struct of kind LW_TRAJ_BORIS over init [n_p][6] (float64, device)."""
     n_p = int(init.shape[0])
     _need(init, torch.float64, (n_p, 6), "init")
     tr = Traj()
@@ -223,11 +223,33 @@ def trajectory_boris(init, n_samples, t_start, dt, a0, lam, w0, n_cycles, out=No
     tr.dt = float(dt)
     tr.init = c_vp(init.data_ptr())
     tr.laser = Laser(float(a0), float(lam), float(w0), float(n_cycles))
+    return tr
+
+
+def trajectory_boris(init, n_samples, t_start, dt, a0, lam, w0, n_cycles, out=None):
+    """lw_trajectory_boris.  init [n_p][6] float64 device.  Returns (r, beta, beta_dot)."""
+    lib = load()
+    n_p = int(init.shape[0])
+    tr = make_boris_traj(init, n_samples, t_start, dt, a0, lam, w0, n_cycles)
     if out is None:
         out = tuple(torch.empty((n_p, int(n_samples), 3), dtype=torch.float64, device=init.device) for _ in range(3))
     r, b, bd = out
     _check(lib.lw_trajectory_boris(ctypes.byref(tr), _ptr(r), _ptr(b), _ptr(bd), _stream()))
     return r, b, bd
+
+
+def trajectory_boris_bwd(init, n_samples, t_start, dt, a0, lam, w0, n_cycles, g_r, g_beta, g_beta_dot):
+    """lw_trajectory_boris_bwd.  Returns (grad_init [n_p][6], grad_a0 [n_p]) (float64, device)."""
+    lib = load()
+    n_p = int(init.shape[0])
+    tr = make_boris_traj(init, n_samples, t_start, dt, a0, lam, w0, n_cycles)
+    for t, nm in ((g_r, "g_r"), (g_beta, "g_beta"), (g_beta_dot, "g_beta_dot")):
+        _need(t, torch.float64, (n_p, int(n_samples), 3), nm)
+    grad_init = torch.empty((n_p, 6), dtype=torch.float64, device=init.device)
+    grad_a0 = torch.empty((n_p,), dtype=torch.float64, device=init.device)
+    _check(lib.lw_trajectory_boris_bwd(ctypes.byref(tr), _ptr(g_r), _ptr(g_beta), _ptr(g_beta_dot), _ptr(grad_init),
+                                       _ptr(grad_a0), _stream()))
+    return grad_init, grad_a0
 
 
 def spectrum_fft_bwd(E, dS, dt_obs, prec=None, out=None, ws=None):

@@ -50,3 +50,36 @@ def synthetic(n_p=5, n_samples=700, n_pix=70, n_obs=600, seed=0, dt=2e-18):
     charge = -1.602176634e-19 * (1.0 + rng.random(n_p))
     return dict(r=r, beta=b, beta_dot=bd, t_start=0.0, dt=dt, x_det=x, t0=t0, dt_obs=dt_obs, n_obs=n_obs,
                 charge=charge)
+
+
+def smooth_directions(c, rng):
+    """Perturbation directions (v_r, v_beta, v_beta_dot) for finite-difference checks: per particle
+    and component a sinusoid over the samples with a seeded period (1/8 to 1/2 of the run) and
+    phase, of amplitude c dt_obs (positions: arrival times move by ~h grid units), max|beta_perp|
+    and max|beta_dot|.  Coherent over many samples, so the objective responds far above the
+    round-off of the arrival times (random per-sample directions mostly cancel)."""
+    n_p, ns, _ = c["r"].shape
+    i = np.arange(ns)[None, :, None]
+    out = []
+    for scale in (oracle.C_LIGHT * c["dt_obs"], np.max(np.abs(c["beta"][..., :2])), np.max(np.abs(c["beta_dot"]))):
+        per = ns / (2.0 + 6.0 * rng.random((n_p, 1, 3)))
+        ph = 2.0 * np.pi * rng.random((n_p, 1, 3))
+        out.append(scale * np.sin(2.0 * np.pi * i / per + ph))
+    return tuple(out)
+
+
+# Central-difference tolerances (relative) at h = 1e-6 along smooth_directions.  The position
+# direction is limited by round-off of the arrival times, which are differences of the sample
+# time and the path term (~1e-16 of t_i/dt_obs grid units, against h ~ 1e-6 grid units of motion).
+FD_REL_TOL = {"r": 2e-4, "beta": 1e-6, "beta_dot": 1e-6}
+
+
+# (relative step, relative tolerance) of central differences in gamma_mean and a0 through the
+# whole chain.  J is piecewise smooth: its slope jumps wherever a grid point crosses an arrival
+# time, and a step that moves the arrival times by d grid units crosses ~d of them per
+# interval, so the difference converges only linearly in the step until round-off of the
+# arrival times takes over (below ~1e-8).  A 1e-7 step in gamma_mean moves arrival times by
+# ~1e-4 grid units on the small bunch cut (measured errors 5e-5 to 1e-3 depending on the
+# weights); a0 moves them ~20x less.  The exact check of these derivatives is the comparison
+# with the oracle's complex step; this one guards against gross errors.
+PARAM_FD = {"gamma": (1e-7, 2e-3), "a0": (1e-6, 1e-3)}

@@ -32,12 +32,12 @@ def test_table2_break_even_ratio():
         gamma = E / 0.511
         n_p = Q * 1e-12 / 1.602176634e-19
         n_tu = grid.n_tu_estimate(0.0, 0.0, lz * 1e-6, T * 1e-12, gamma, lam * 1e-6, c=3e8)
-        assert 4 * n_p / n_tu == pytest.approx(ratio, rel=3e-3), name
+        assert 4 * n_p / n_tu == pytest.approx(ratio, rel=3e-3, abs=0), name
 
 
 def test_break_even_exponent():
     (c1, c2, cw, ns, npart, expo), = (list(map(float, r)) for r in rows("break_even_1pC.txt"))
-    assert grid.fd_break_even_log_exponent(cw, c2, ns, npart) == pytest.approx(expo, rel=5e-5)
+    assert grid.fd_break_even_log_exponent(cw, c2, ns, npart) == pytest.approx(expo, rel=5e-5, abs=0)
 
 
 def test_memory_ratio_criterion():
@@ -55,4 +55,4 @@ def test_t_u_min_far_field():
     r = np.array([[0.0, 0.0, 1e-6], [0.0, 0.0, -1e-6]])
     c = grid.C_LIGHT
     expected = min(-1e-15 + np.linalg.norm(xm) / c - (xm / np.linalg.norm(xm)) @ rk / c for xm in x for rk in r)
-    assert grid.t_u_min(-1e-15, x, r) == pytest.approx(expected, rel=1e-15)
+    assert grid.t_u_min(-1e-15, x, r) == pytest.approx(expected, rel=1e-15, abs=0)

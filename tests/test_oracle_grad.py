@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from oracle import gradient as og
-from cases import synthetic
+from cases import FD_REL_TOL, PARAM_FD, smooth_directions, synthetic
 
 
 @pytest.mark.parametrize("N", [8, 64, 1024])
@@ -51,12 +51,9 @@ def test_complex_step_matches_central_differences(geom):
     c = small_case(seed=2)
     rng = np.random.default_rng(5)
     W = rng.random((c["x_det"].shape[0], c["n_obs"] // 2 + 1))
-    # one direction per input family; r scaled by c dt_obs so that h = 1e-6 moves arrival
-    # times by ~1e-6 grid units (a central difference must not straddle a grid crossing)
-    vr = rng.normal(size=c["r"].shape) * oracle.C_LIGHT * c["dt_obs"]
-    vb = rng.normal(size=c["beta"].shape) * 1e-6
-    va = rng.normal(size=c["beta_dot"].shape) * np.max(np.abs(c["beta_dot"]))
-    for v in ((vr, 0 * vb, 0 * va), (0 * vr, vb, 0 * va), (0 * vr, 0 * vb, va)):
+    vr, vb, va = smooth_directions(c, rng)
+    z = 0.0 * vr
+    for name, v in (("r", (vr, z, z)), ("beta", (z, vb, z)), ("beta_dot", (z, z, va))):
         d_cs, J0 = og.directional_derivative(c["t_start"], c["dt"], c["r"], c["beta"], c["beta_dot"], *v,
                                              c["x_det"], c["t0"], c["dt_obs"], c["n_obs"], weights=W,
                                              charge=c["charge"], field_mask=3, geom=geom)
@@ -64,4 +61,123 @@ def test_complex_step_matches_central_differences(geom):
         Jp = J_real(c, c["r"] + h * v[0], c["beta"] + h * v[1], c["beta_dot"] + h * v[2], W, geom)
         Jm = J_real(c, c["r"] - h * v[0], c["beta"] - h * v[1], c["beta_dot"] - h * v[2], W, geom)
         fd = (Jp - Jm) / (2 * h)
-        assert d_cs == pytest.approx(fd, rel=1e-5)
+        assert d_cs == pytest.approx(fd, rel=FD_REL_TOL[name], abs=0), name
+
+
+# ---- the pusher's tangents and the (gamma_mean, a0) chain ----------------------------------------
+
+def boris_case():
+    from cases import small_bunch
+    return small_bunch(n_p=6, n_steps=1500, n_side=3, n_obs=1 << 11)
+
+
+def test_boris_complex_value_matches_c_oracle():
+    c = boris_case()
+    W, L = c["W"], c["W"].laser
+    r, b, bd = og.boris_complex(c["init"], W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
+    assert np.max(np.abs(r - c["r"])) <= 1e-14 * np.max(np.abs(c["r"]))
+    assert np.max(np.abs(b - c["beta"])) <= 1e-14
+    assert np.max(np.abs(bd - c["beta_dot"])) <= 1e-11 * np.max(np.abs(c["beta_dot"]))
+
+
+def test_boris_complex_step_matches_central_differences():
+    """G = sum g.(r, beta, beta_dot) with random g: its complex-step derivative along a random
+    initial-condition direction and along a0 equals the central difference of the C pusher
+    (step 1e-4 relative: the difference converges quadratically, ~2e-7 there, before round-off
+    takes over below 1e-5)."""
+    c = boris_case()
+    W, L = c["W"], c["W"].laser
+    rng = np.random.default_rng(17)
+    g = [rng.normal(size=c["r"].shape) / np.maximum(np.std(x), 1e-300) for x in (c["r"], c["beta"], c["beta_dot"])]
+
+    def G(parts):
+        return sum(np.sum(gi * pi) for gi, pi in zip(g, parts))
+
+    scale = np.array([1e-6, 1e-6, 1e-6, 0.1, 0.1, 1.0])  # metres and u = gamma beta
+    v = rng.normal(size=c["init"].shape) * scale
+    for which in ("init", "a0"):
+        h = 1e-30
+        if which == "init":
+            z = og.boris_complex(c["init"] + 1j * h * v, W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
+            eps = 1e-4
+            p = oracle.boris(c["init"] + eps * v, W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
+            m = oracle.boris(c["init"] - eps * v, W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
+        else:
+            z = og.boris_complex(c["init"], W.n_samples, W.t_start, W.dt, L.a0 + 1j * h, L.lam, L.w0, L.n_cycles)
+            eps = 1e-4 * L.a0
+            p = oracle.boris(c["init"], W.n_samples, W.t_start, W.dt, L.a0 + eps, L.lam, L.w0, L.n_cycles)
+            m = oracle.boris(c["init"], W.n_samples, W.t_start, W.dt, L.a0 - eps, L.lam, L.w0, L.n_cycles)
+        d_cs = G([x.imag for x in z]) / h
+        fd = (G(p) - G(m)) / (2 * eps)
+        assert d_cs == pytest.approx(fd, rel=2e-6, abs=0), which
+
+
+def test_boris_tangent_free_flight_closed_form():
+    """With the laser off (a0 = 0) u stays constant and r_i = r_0 + c (u/gamma) i dt, so
+    dr_i/du = c i dt (I/gamma - u u^T/gamma^3) and dbeta_i/du = I/gamma - u u^T/gamma^3."""
+    rng = np.random.default_rng(4)
+    n_p, ns, dt = 3, 50, 1e-16
+    init = np.concatenate([rng.normal(size=(n_p, 3)) * 1e-6, rng.normal(size=(n_p, 3)) * [0.1, 0.1, 1.0]], axis=1)
+    init[:, 5] += 30.0
+    h = 1e-30
+    for j in range(3):
+        e = np.zeros_like(init)
+        e[:, 3 + j] = 1.0
+        r, b, bd = og.boris_complex(init + 1j * h * e, ns, 0.0, dt, 0.0, 1e-6, 0.0, 20.0)
+        u = init[:, 3:]
+        gam = np.sqrt(1.0 + np.sum(u * u, axis=1))
+        J = np.eye(3)[None] / gam[:, None, None] - u[:, :, None] * u[:, None, :] / gam[:, None, None] ** 3
+        col = J[:, :, j]
+        i = np.arange(ns)
+        want_r = oracle.C_LIGHT * dt * i[None, :, None] * col[:, None, :]
+        assert np.max(np.abs(r.imag / h - want_r)) <= 1e-12 * np.max(np.abs(want_r))
+        assert np.max(np.abs(b.imag / h - col[:, None, :])) <= 1e-13 * np.max(np.abs(col))
+        assert np.max(np.abs(bd.imag)) == 0.0
+    # positions: dr_i/dx_0 = I
+    e = np.zeros_like(init)
+    e[:, 1] = 1.0
+    r, _, _ = og.boris_complex(init + 1j * h * e, ns, 0.0, dt, 0.0, 1e-6, 0.0, 20.0)
+    assert np.all(r.imag[:, :, 1] / h == 1.0) and np.all(r.imag[:, :, [0, 2]] == 0.0)
+
+
+def params_case():
+    from paper_2206_03015_amd import inputs
+    c = boris_case()
+    W = c["W"]
+    full_w = inputs.workload("bunch")
+    full = inputs.bunch_init(full_w)
+    zc = np.sqrt(1.0 - 1.0 / W.gamma ** 2) * inputs.C_LIGHT * W.t_start
+    rows = np.argsort(np.abs(full[:, 2] - zc))[: c["init"].shape[0]]
+    assert np.array_equal(full[rows], c["init"])
+    rng = np.random.default_rng(21)
+    Wt = np.zeros((c["x_det"].shape[0], c["n_obs"] // 2 + 1))
+    Wt[:, 20:200] = rng.random((Wt.shape[0], 180))
+    return c, (lambda g: inputs.bunch_init(full_w, gamma=g)[rows]), Wt
+
+
+
+
+@pytest.mark.parametrize("which", ["gamma", "a0"])
+def test_params_derivative_matches_central_differences(which):
+    """dJ/dgamma_mean and dJ/da0 by complex step through draw, pusher, deposit and spectrum, against
+    the central difference of the real C oracle chain."""
+    c, init_of, Wt = params_case()
+    W, L = c["W"], c["W"].laser
+    d_cs, J0 = og.params_derivative(init_of, W.gamma, L.a0, (L.lam, L.w0, L.n_cycles), W.n_samples, W.t_start, W.dt,
+                                    c["x_det"], c["t0"], c["dt_obs"], c["n_obs"], Wt, which)
+
+    def J(gamma, a0):
+        r, b, bd = oracle.boris(init_of(gamma), W.n_samples, W.t_start, W.dt, a0, L.lam, L.w0, L.n_cycles)
+        E, _ = oracle.deposit_td(W.t_start, W.dt, r, b, bd, c["x_det"], c["t0"], c["dt_obs"], c["n_obs"])
+        return np.sum(Wt * oracle.spectrum(E, c["dt_obs"]))
+
+    x0 = W.gamma if which == "gamma" else L.a0
+    rel_step, tol = PARAM_FD[which]
+    eps = rel_step * x0
+    if which == "gamma":
+        fd = (J(x0 + eps, L.a0) - J(x0 - eps, L.a0)) / (2 * eps)
+    else:
+        fd = (J(W.gamma, x0 + eps) - J(W.gamma, x0 - eps)) / (2 * eps)
+    assert J0 == pytest.approx(J(W.gamma, L.a0), rel=1e-10, abs=0)
+    assert abs(d_cs * x0 / J0) > 0.1  # the objective really depends on the parameter
+    assert d_cs == pytest.approx(fd, rel=tol, abs=0)
