@@ -37,7 +37,19 @@ METRIC = ("particle·step·pixel LW evals/s; mixed vs FP64 speedup at ≤1e-4 sp
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 CUS, CLOCK_GHZ, LANES = 256, 2.4, 64
+PEAK_F32_TFLOPS = 157.3  # vector FP32 (256 CUs x 2.4 GHz x 128 lanes x 2 flops, packed)
+PEAK_F64_TFLOPS = 78.6   # vector FP64
 PEAK_VALU_TOPS = CUS * LANES * CLOCK_GHZ * 1e9 / 1e12  # lane-ops/s (one FP64 FMA = one lane-op)
+# Algorithmic work of one (particle, sample, pixel) evaluation in mixed precision: the field
+# formula with its 1/kappa^3 factors in FP32 (68 flops) and the arrival time in FP64 (6 flops).
+# The roofline time of one evaluation is F32/P32 + F64/P64; the "peak" below is the flop rate
+# at which both units would be saturated in that proportion.
+EVAL_F32_FLOPS, EVAL_F64_FLOPS = 68, 6
+EVAL_FLOPS = EVAL_F32_FLOPS + EVAL_F64_FLOPS
+EVAL_ROOF_S = EVAL_F32_FLOPS / (PEAK_F32_TFLOPS * 1e12) + EVAL_F64_FLOPS / (PEAK_F64_TFLOPS * 1e12)
+PEAK_EVAL_TFLOPS = EVAL_FLOPS / EVAL_ROOF_S / 1e12
+DEPOSIT_SOURCES = ("paper_2206_03015_amd/csrc/deposit.hip", "paper_2206_03015_amd/csrc/lw_internal.h")
+TRAFFIC_SUMMARY = "profiles/k_deposit_bunch_mixed_exact_hbm_traffic.md"
 
 
 def parse():
@@ -50,7 +62,10 @@ def parse():
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-fd", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--no-grad", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                   help="run a plain device copy of this many GiB first (scale for HBM byte counters)")
     return p.parse_args()
 
 
@@ -84,6 +99,15 @@ def main():
     x_det = torch.as_tensor(inputs.pixel_positions(W.n_side, W.theta_max, W.D), device=dev)
     n_pix, n_obs = W.n_pix, W.n_obs
     triples = W.n_p * W.n_samples * n_pix
+
+    if args.copy_calibration_gib > 0:
+        n = int(args.copy_calibration_gib * (1 << 30)) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)  # one plain elementwise copy kernel: n*4 bytes read, n*4 written
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {n * 4} bytes read and written by one elementwise kernel")
+        del src, dst
 
     def buffers(prec):
         dt = torch.float64 if prec == "fp64" else torch.float32
@@ -155,19 +179,23 @@ def main():
     del S_mixed
     torch.cuda.empty_cache()
 
-    # ---- roofline of the dominant kernel (the deposit).  Algorithmic work per triple: the arrival
-    # time alpha_i - n.r/(c dt_obs) (3 FP64 FMA) and the crossing test (1 compare) = 4 lane-ops;
-    # the exact geometry adds its correction |r_perp|^2/(c dt_obs(|x-r| + |x| - n.r)) (11 FMA/add,
-    # one sqrt, one divide counted as 1 op each) = 17 lane-ops.  Per deposited grid point the field
-    # at both ends and the lerp are ~2 x 60 + 12 ops; they are added from the hit count.
+    # ---- roofline of the dominant kernel (the deposit): algorithmic flops of the method per
+    # evaluation (EVAL_FLOPS) x evaluations per launch / average launch time (HIP events on the
+    # stream the library launches on).  The kernel itself evaluates the field only at the ends
+    # of intervals that deposit, so it does less work than it is credited with; its own count
+    # of lane operations is reported beside it.
+    dep_s = mixed["deposit_ms"] / 1e3
+    achieved = triples * EVAL_FLOPS / dep_s / 1e12
     ops_triple = 17 if args.geom == "exact" else 4
     hits = mixed["diag"][3]
-    ops = triples * ops_triple + hits * 132
-    dep_s = mixed["deposit_ms"] / 1e3
-    achieved = ops / dep_s / 1e12
-    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "Tlane-op/s",
-            "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
-            "kernel": "k_deposit (+ pre-pass, fill)", "ops_per_triple": ops_triple, "ops_per_hit": 132}
+    lane_ops = triples * ops_triple + hits * 132
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_EVAL_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_EVAL_TFLOPS, "traffic": deposit_traffic(),
+            "kernel": "k_deposit (lw_deposit_td: pre-pass + fill + deposit)",
+            "flops_per_eval": {"f32": EVAL_F32_FLOPS, "f64": EVAL_F64_FLOPS},
+            "evals_per_launch": triples,
+            "executed_lane_ops_per_s": lane_ops / dep_s,
+            "executed_frac_of_valu_issue": lane_ops / dep_s / (PEAK_VALU_TOPS * 1e12)}
     fft_bytes = n_pix * (3 * n_obs + n_obs // 2 + 1) * 4
     fft_gbs = fft_bytes / (mixed["fft_ms"] / 1e3) / 1e9
 
@@ -201,6 +229,11 @@ def main():
               "td_speedup_per_pixel_bin": fd_per_pix_bin / td_per_pix_bin}
         log(f"[bench] direct FD {n_fd_pix} pix x {n_w} w: {fd_ms:.1f} ms")
 
+    # ---- gradient of the band objective on the differentiation workload (FP64 forward + adjoint)
+    grad = None
+    if not args.no_grad:
+        grad = grad_leg(torch, dev)
+
     # ---- FP64 CPU oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
@@ -222,11 +255,75 @@ def main():
                 "frac": fft_gbs / PEAK_HBM_GBS},
         "diag": mixed["diag"],
         "direct_fd": fd,
+        "grad": grad,
         "paper_serial_evals_per_s": 1.0 / 1.02e-7,
     }
     rec.update(out)
     print(json.dumps(rec), flush=True)
     return 0
+
+
+def grad_leg(torch, dev):
+    """d(band energy)/d(gamma_mean, a0) on the differentiation workload (1e3 e-, 1e4 steps, 32 x 32
+    pixels, 2^16 grid, objective over the central 8 x 8 pixels): seeded draw -> FP64 Boris ->
+    deposit -> FFT forward, then the three adjoints, through torch.autograd."""
+    from paper_2206_03015_amd import autograd as ag
+    from paper_2206_03015_amd import inputs
+    W = inputs.workload("grad")
+    x = inputs.pixel_positions(W.n_side, W.theta_max, W.D)
+    weights = torch.as_tensor(inputs.band_weights(W, x, inputs.central_pixels(W.n_side, 8)), device=dev)
+    x_det = torch.as_tensor(x, device=dev)
+
+    def once():
+        gamma = torch.tensor(W.gamma, dtype=torch.float64, requires_grad=True)
+        a0 = torch.tensor(W.laser.a0, dtype=torch.float64, requires_grad=True)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        init = ag.bunch_init(W, None, gamma, device=dev)
+        r, b, bd = ag.boris_trajectory(init, a0, W)
+        S, _ = ag.lw_spectrum(r, b, bd, W.t_start, W.dt, x_det, W.t0, W.dt_obs, W.n_obs, prec="fp64")
+        J = torch.sum(weights * S)
+        e[1].record()
+        J.backward()
+        e[2].record()
+        torch.cuda.synchronize()
+        return float(J), float(gamma.grad), float(a0.grad), e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+
+    once()
+    J, dg, da, fwd_ms, bwd_ms = once()
+    log(f"[bench] grad: forward {fwd_ms:.1f} ms, backward {bwd_ms:.1f} ms, dJ/dgamma {dg:.4e}, dJ/da0 {da:.4e}")
+    return {"workload": "grad: 1e3 e-, 1e4 Boris steps, 32x32 px, 2^16 grid, band objective on the central 8x8",
+            "J": J, "dJ_dgamma": dg, "dJ_da0": da, "forward_ms": fwd_ms, "backward_ms": bwd_ms,
+            "forward_evals_per_s": W.n_p * W.n_samples * W.n_pix / (fwd_ms / 1e3), "prec": "fp64"}
+
+
+def _deposit_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in DEPOSIT_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def deposit_traffic():
+    """HBM bytes per deposit launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
+    or None when the deposit sources changed since those counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != _deposit_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(W, geom, seconds):
@@ -247,9 +344,12 @@ def cpu_baseline(W, geom, seconds):
         oracle.deposit_td(W.t_start, W.dt, rr, bb, aa, xs, W.t0, W.dt_obs, W.n_obs, geom=g)
         return time.time() - t0
 
-    n_p = 2
-    t = timed(n_p)
-    n_p = int(max(2, min(W.n_p, n_p * seconds / max(t, 1e-3))))
+    # time = a + b n_p (the fixed part is the zeroed trace and thread start-up): two small
+    # calibration runs fix a and b, then the sample is sized to `seconds`
+    t4, t16 = timed(4), timed(16)
+    b = max((t16 - t4) / 12.0, 1e-6)
+    a = max(t4 - 4 * b, 0.0)
+    n_p = int(max(16, min(W.n_p, (seconds - a) / b)))
     t = timed(n_p)
     triples = n_p * W.n_samples * n_pix
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))

@@ -114,11 +114,13 @@ typedef struct {
 #define LW_WS_DIRECT_FD 3
 #define LW_WS_DEPOSIT_BWD 4
 #define LW_WS_FFT_BWD 5
+#define LW_WS_DIRECT_FD_BWD 6
 
 /*
  * Workspace (scratch device memory) that the call `which` needs, in bytes:
- * n_a = n_particles (deposit, deposit_bwd), n_pix (fft, fft_bwd, direct_fd);
- * n_b = n_samples (deposit), n_obs (fft), n_omega (direct_fd).  Returns 0 for
+ * n_a = n_particles (deposit, deposit_bwd), n_pix (fft, fft_bwd, direct_fd,
+ * direct_fd_bwd); n_b = n_samples (deposit), n_obs (fft, fft_bwd), n_omega
+ * (direct_fd, direct_fd_bwd).  Returns 0 for
  * an unknown `which`.  Larger workspaces are accepted; for the FFT a larger
  * workspace lets more pixels be transformed per pass.
  */
@@ -143,7 +145,11 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec);
  * traj:       kind must be LW_TRAJ_SAMPLES.
  * grid:       pixels and observer grid.
  * prec:       LW_PREC_FP64 (E is double) or LW_PREC_MIXED (E is float; tau and
- *             the crossing decisions are still computed in double).
+ *             the crossing decisions are still computed in double).  In the exact
+ *             geometry, a particle with max_i |r_i|^2 <= 1e-8 |x_m|^2 has its path
+ *             correction expanded in |r|/|x_m|: to third order in FP64 mode (exact to
+ *             rounding), to first order in MIXED mode (relative error of the
+ *             correction <= 1.25e-8); other particles use the square-root form.
  * field_mask: LW_FIELD_ACCEL and/or LW_FIELD_VELOCITY (non-zero).
  * geom:       LW_GEOM_EXACT or LW_GEOM_FARFIELD, optionally | LW_ACCUMULATE.
  * E:          [n_pix][3][n_obs] float or double, overwritten (or accumulated).
@@ -251,8 +257,16 @@ lw_status lw_deposit_td_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int pr
 
 /*
  * lw_direct_fd_bwd -- adjoint of lw_direct_fd with respect to the trajectory
- * samples, given dS = dJ/dS [n_pix][n_omega] (double): adds the gradient into
- * d_r, d_beta, d_beta_dot [n_particles][n_samples][3].  prec: FP64 only.
+ * samples.  With dS = dJ/dS [n_pix][n_omega] (double), F_c(w) = sum E_c kappa e^{i w t}
+ * the forward sums (recomputed here in FP64 into ws) and t = t_i + shift - t0:
+ *   dJ/d(E_c kappa) = 2f sum_w dS (Re F_c cos wt + Im F_c sin wt),
+ *   dJ/dt           = 2f sum_w dS w sum_c E_c kappa (Im F_c cos wt - Re F_c sin wt),
+ * f = dt^2/2pi, chained through the field formula, kappa = 1 - n.beta and the arrival
+ * time (dt/dr = -n/c).  Adds (accumulates) into d_r, d_beta, d_beta_dot
+ * [n_particles][n_samples][3] (double); each sample is written by one thread, no
+ * atomics.  prec: LW_PREC_FP64 only (MIXED returns LW_E_UNSUPPORTED).  Unusable
+ * samples get no gradient.  ws: >= lw_workspace_bytes(LW_WS_DIRECT_FD_BWD, n_pix,
+ * n_omega, prec) bytes, 256-byte aligned.
  */
 lw_status lw_direct_fd_bwd(const lw_traj_t *traj, const lw_grid_t *grid, const double *omega, int64_t n_omega,
                            int prec, int field_mask, int geom, const double *dS, double *d_r, double *d_beta,

@@ -15,6 +15,10 @@
   phase space or in a0 gives the exact directional derivative of the trajectory (the
   forward-mode tangent of the pusher).  Pinned against the real C oracle (real part) and
   against its central differences (imaginary part).
+* ``direct_fd_complex``: the direct frequency-domain sum (Eq. inty_dft, Algorithm 1) in
+  complex arithmetic, S(w) = (dt^2/2pi) sum_c (sum E_c kappa cos(w t))^2 + (sum E_c kappa
+  sin(w t))^2 with t = t_i + tt - t0; pinned against the C oracle's ``orc_direct_fd``
+  (value) and its central differences (derivative).
 * ``params_derivative``: dJ/dgamma_mean and dJ/da0 of the band objective by one complex
   step through the seeded bunch draw, the pusher and the chain above.
 """
@@ -43,11 +47,12 @@ def _dot(a, b):
     return np.sum(a * b, axis=-1)
 
 
-def eval_complex(x, r, b, a, q, field_mask=1, geom=0):
+def eval_complex(x, r, b, a, q, field_mask=1, geom=0, with_kappa=False):
     """Arrival shift tt (relative to t + |x|/c) and field E of samples r, b, a [n][3] (complex
     allowed) at observer x, written with the analytic (complex-differentiable) operations of
     the definitions; the exact-geometry shift uses the cancellation-free identity
-    |x - r| - |x| = -s + |r - s n|^2 / (|x - r| + |x| - s)."""
+    |x - r| - |x| = -s + |r - s n|^2 / (|x - r| + |x| - s).  With with_kappa, also
+    kappa = 1 - n.b."""
     x = np.asarray(x, dtype=np.float64)
     D = np.sqrt(x @ x)
     nm = x / D
@@ -74,6 +79,8 @@ def eval_complex(x, r, b, a, q, field_mask=1, geom=0):
         w = np.cross(nb, a)
         v = np.cross(n, w)
         E = E + (pref / (C_LIGHT * kappa ** 3))[:, None] * v / Rc
+    if with_kappa:
+        return tt, E, kappa
     return tt, E
 
 
@@ -218,4 +225,36 @@ def params_derivative(init_of_gamma, gamma, a0, laser, n_samples, t_start, dt, x
     init = init_of_gamma(g)
     r, b, bd = boris_complex(init, n_samples, t_start, dt, a, lam, w0, n_cycles)
     J = chain_complex(t_start, dt, r, b, bd, x_det, t0, dt_obs, n_obs, weights=weights, geom=geom)
+    return J.imag / h, J.real
+
+
+def direct_fd_complex(t_start, dt, r, b, a, x_det, t0, omega, charge=None, field_mask=1, geom=0):
+    """Direct FD spectra S [n_pix][n_omega] in complex arithmetic (all samples assumed usable)."""
+    r = np.asarray(r)
+    n_p, ns = r.shape[0], r.shape[1]
+    x_det = np.asarray(x_det, dtype=np.float64).reshape(-1, 3)
+    omega = np.asarray(omega, dtype=np.float64)
+    ti = t_start + np.arange(ns) * dt
+    out = []
+    for m in range(x_det.shape[0]):
+        Rc = np.zeros((3, omega.size), dtype=np.complex128)
+        Ic = np.zeros((3, omega.size), dtype=np.complex128)
+        for k in range(n_p):
+            q = -Q_E if charge is None else charge[k]
+            tt, E, kap = eval_complex(x_det[m], r[k], b[k], a[k], q, field_mask, geom, with_kappa=True)
+            t = (ti + tt) - t0
+            A = E * kap[:, None]
+            ph = omega[None, :] * t[:, None]
+            Rc += A.T @ np.cos(ph)
+            Ic += A.T @ np.sin(ph)
+        out.append((dt * dt / (2.0 * np.pi)) * np.sum(Rc * Rc + Ic * Ic, axis=0))
+    return np.array(out)
+
+
+def fd_directional_derivative(t_start, dt, r, b, a, v_r, v_b, v_a, x_det, t0, omega, dS, charge=None, field_mask=1,
+                              geom=0, h=1e-30):
+    """Complex-step derivative of J = sum(dS * S_FD) along (v_r, v_b, v_a).  Returns (dJ, J)."""
+    S = direct_fd_complex(t_start, dt, r + 1j * h * v_r, b + 1j * h * v_b, a + 1j * h * v_a, x_det, t0, omega,
+                          charge, field_mask, geom)
+    J = np.sum(np.asarray(dS) * S)
     return J.imag / h, J.real

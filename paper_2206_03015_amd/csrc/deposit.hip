@@ -10,7 +10,10 @@
 //   * a crossing appends (particle, sample, pixel) to a per-wavefront queue in LDS;
 //     whenever 64 entries are queued, all lanes take one entry each, evaluate the
 //     Lienard-Wiechert field at the interval's two ends and add the interpolated
-//     values at the crossed grid points with global atomics.
+//     values at the crossed grid points into a write-combining line of that pixel
+//     in LDS (a short run of consecutive grid points of its trace);
+//   * a line whose pixel moves past it is added to the trace with global atomics,
+//     several lines per instruction (lane l takes value l % 3N of line l / 3N).
 // The field is therefore evaluated only at samples that the interpolation reads;
 // samples whose interval holds no grid point of the window contribute nothing.
 //
@@ -28,15 +31,16 @@ namespace lw {
 namespace {
 
 constexpr int kWavesPerBlock = 4;
-constexpr int kQCap = 128;  // queue entries per wavefront (at most 63 pending + 64 appended)
-// write-combining line per pixel: 64-byte segments of the trace (16 floats or 8 doubles)
+constexpr int kBlockThreads = 64 * kWavesPerBlock;
+constexpr uint32_t kQCap = 320;  // queue ring per wavefront (at most 63 pending + 4 x 64 appended between drains)
+// write-combining line per pixel: 32-byte segments of the trace (8 floats or 4 doubles)
 template <typename T>
 struct WcLine {
     static constexpr int N = 32 / sizeof(T);   // grid points per line
     static constexpr int P = 3 * N + 1;        // LDS stride per pixel (odd: no bank conflicts)
 };
-constexpr uint64_t kWantNone = ~0ull;
-constexpr int kStage = 8;  // doubles per staged sample: alpha, x, y, z, |r|^2, pad
+constexpr uint64_t kWantNone = 0ull;  // below every request: (queue position + 1) << 32 | segment
+constexpr int kStage = 6;  // doubles per staged sample: alpha, x, y, z, |r|^2, pad
 constexpr int kTargetWaves = 16384;
 // (|r|/|x|)^2 up to which the series form of the exact-geometry arrival time is used
 constexpr double kSeriesBound = 1e-8;
@@ -188,59 +192,64 @@ struct Wave {
     double invD2max;  // wavefront maximum of 1/|x_m|^2
     int lane;
     int64_t tile, k0;
-    uint2 *q;          // queue in LDS: {sample index, (particle - k0) << 6 | lane}
+    uint2 *q;          // queue ring in LDS: {sample index, (particle - k0) << 6 | lane}
     T *wc;             // write-combining lines in LDS, [64 pixels][WcLine<T>::P] (3 components x N)
     int *wcb;          // [64] trace segment each line holds (-1: none)
-    uint64_t *want;    // [64] (queue position << 32 | segment of the grid point after the latest hit)
+    uint64_t *want;    // [64] ((queue position + 1) << 32 | segment of the grid point after the latest hit)
+    int *fpix;         // [64] pixel of the j-th line of a flush
     double *stage;     // staged sample records in LDS, [64][kStage]
-    uint32_t qn;
+    uint32_t qh, qn;   // queue ring head and length
+    // arrival-time form of series particles: the short expansion goes with single-precision fields
+    static constexpr int kSer = sizeof(T) == 4 ? kTauShort : kTauSeries;
 
     __device__ __forceinline__ bool series(int64_t k) const
     {
         return GEOM == LW_GEOM_EXACT && __longlong_as_double((long long)rmax2[k]) * invD2max <= kSeriesBound;
     }
 
-    template <bool SERIES>
+    template <int FORM>
     __device__ __forceinline__ double tau_rec(const PixGeo &g, double a, const double *p) const
     {
-        return arrival_tau<GEOM, SERIES>(g, a, p[0], p[1], p[2], GEOM == LW_GEOM_EXACT ? p[3] : 0.0, sh.inv_cdt);
+        return arrival_tau<GEOM, FORM>(g, a, p[0], p[1], p[2], GEOM == LW_GEOM_EXACT ? p[3] : 0.0, sh.inv_cdt);
     }
 
     __device__ __forceinline__ double tau_any(const PixGeo &g, bool ser, int64_t k, int64_t i) const
     {
         const double *p = src + ((size_t)k * sh.n_samples + i) * RS;
-        return ser ? tau_rec<true>(g, alpha[i], p) : tau_rec<false>(g, alpha[i], p);
+        return ser ? tau_rec<kSer>(g, alpha[i], p) : tau_rec<kTauSqrt>(g, alpha[i], p);
     }
 
-    // Add the lines of the pixels in `mask` to the trace (one coalesced atomic instruction per
-    // line: lane t handles component t / N, grid point t % N) and clear them.
+    __device__ __forceinline__ static uint32_t qwrap(uint32_t v) { return v >= kQCap ? v - kQCap : v; }
+
+    // Add the lines of the pixels in `mask` to the trace and clear them: lane l of a pass takes
+    // value l % 3N (component (l % 3N) / N, grid point l % N) of the (l / 3N)-th line.
     __device__ void flush_lines(uint64_t mask)
     {
-        constexpr int NL = WcLine<T>::N;
-        const int c = lane / NL, o = lane % NL;
-        while (mask) {
-            const int p = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            const int seg = wcb[p];
-            if (c < 3) {
-                T *line = wc + p * WcLine<T>::P + c * NL + o;
-                const T v = *line;
-                const int64_t u = (int64_t)seg * NL + o;
-                if (v != (T)0 && u < sh.n_obs) atomic_add(E + ((size_t)(tile * 64 + p) * 3 + c) * sh.n_obs + u, v);
-                *line = (T)0;
-            }
+        constexpr int NL = WcLine<T>::N, V = 3 * NL;
+        const int n = __popcll(mask);
+        if (n == 0) return;
+        if ((mask >> lane) & 1ull) fpix[lanes_below(mask)] = lane;
+        __builtin_amdgcn_wave_barrier();
+        for (int l = lane; l < n * V; l += 64) {
+            const int jj = l / V, w = l - jj * V;
+            const int p = fpix[jj];
+            const int c = w / NL, o = w - c * NL;
+            T *line = wc + p * WcLine<T>::P + w;
+            const T v = *line;
+            *line = (T)0;
+            const int64_t u = (int64_t)wcb[p] * NL + o;
+            if (v != (T)0 && u < sh.n_obs) atomic_add(E + ((size_t)(tile * 64 + p) * 3 + c) * sh.n_obs + u, v);
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
 
-    // Evaluate the first cnt queued crossings (lane j takes entry j), then move the rest down.
+    // Evaluate the cnt oldest queued crossings (lane j takes entry j).
     __device__ void drain(uint32_t cnt)
     {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if ((uint32_t)lane < cnt) {
-            const uint2 e = q[lane];
+            const uint2 e = q[qwrap(qh + (uint32_t)lane)];
             const uint32_t i = e.x, kl = e.y;
             const int64_t k = k0 + (int64_t)(kl >> 6);
             const int64_t m = tile * 64 + (int64_t)(kl & 63u);
@@ -259,7 +268,6 @@ struct Wave {
             const double nob = (double)sh.n_obs;
             const int64_t u0 = grid_count(ta, nob), u1 = grid_count(tb, nob);
             const double idt = 1.0 / (tb - ta);
-            T *Em = E + (size_t)m * 3 * sh.n_obs;
             constexpr int NL = WcLine<T>::N;
             const int ml = (int)(kl & 63u);
             const int seg = wcb[ml];
@@ -273,12 +281,13 @@ struct Wave {
                     atomicAdd(line + NL, vy);
                     atomicAdd(line + 2 * NL, vz);
                 } else {
+                    T *Em = E + (size_t)m * 3 * sh.n_obs;
                     atomic_add(Em + u, vx);
                     atomic_add(Em + sh.n_obs + u, vy);
                     atomic_add(Em + 2 * sh.n_obs + u, vz);
                 }
             }
-            if (u1 > u0) atomicMax((unsigned long long *)(want + ml), ((uint64_t)lane << 32) | (uint64_t)(u1 / NL));
+            if (u1 > u0) atomicMax((unsigned long long *)(want + ml), ((uint64_t)(lane + 1) << 32) | (uint64_t)(u1 / NL));
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -297,29 +306,26 @@ struct Wave {
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
-        const uint32_t rest = qn - cnt;
-        uint2 moved;
-        if ((uint32_t)lane < rest) moved = q[cnt + lane];
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if ((uint32_t)lane < rest) q[lane] = moved;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        qn = rest;
+        qh = qwrap(qh + cnt);
+        qn -= cnt;
     }
 
-    // Append the lanes with `hit` set; drain when 64 entries are pending.
+    // Append the lanes with `hit` set (callers drain before 4 x 64 more can arrive).
     __device__ __forceinline__ void push(bool hit, uint64_t mask, uint32_t i, uint32_t tag)
     {
-        if (hit) q[qn + lanes_below(mask)] = make_uint2(i, tag);
+        if (hit) q[qwrap(qh + qn + lanes_below(mask))] = make_uint2(i, tag);
         qn += (uint32_t)__popcll(mask);
-        if (qn >= 64) drain(64);
+    }
+
+    __device__ __forceinline__ void pump()
+    {
+        while (qn >= 64) drain(64);
     }
 
     // Fast path: tau strictly increasing, all samples usable.  Samples go through LDS in
     // chunks of 64 (lane j loads sample c0 + j with vector loads one chunk ahead); every lane
     // then reads the staged samples by broadcast, four per trip.
-    template <bool SERIES>
+    template <int FORM>
     __device__ void fast_particle(const PixGeo &g, bool lane_ok, bool pix_in, int64_t k, unsigned long long &c1,
                                   unsigned long long &c2, unsigned long long &c3)
     {
@@ -353,12 +359,12 @@ struct Wave {
             const int cnt = (int)std::min<int64_t>(64, ns - c0);
             int j = 0;
             if (c0 == 0) {
-                tau = tau0 = arrival_tau<GEOM, SERIES>(g, stage[0], stage[1], stage[2], stage[3], stage[4], sh.inv_cdt);
+                tau = tau0 = arrival_tau<GEOM, FORM>(g, stage[0], stage[1], stage[2], stage[3], stage[4], sh.inv_cdt);
                 gnext = lane_ok ? next_grid(tau, nob) : INFINITY;
                 j = 1;
             }
             auto step = [&](int jj, const double *e) {
-                tau = arrival_tau<GEOM, SERIES>(g, e[0], e[1], e[2], e[3], e[4], sh.inv_cdt);
+                tau = arrival_tau<GEOM, FORM>(g, e[0], e[1], e[2], e[3], e[4], sh.inv_cdt);
                 const bool hit = tau >= gnext;
                 const uint64_t mask = __ballot(hit);
                 if (mask) {
@@ -379,8 +385,12 @@ struct Wave {
                 step(j + 1, v[1]);
                 step(j + 2, v[2]);
                 step(j + 3, v[3]);
+                pump();
             }
-            for (; j < cnt; ++j) step(j, stage + j * kStage);
+            for (; j < cnt; ++j) {
+                step(j, stage + j * kStage);
+                pump();
+            }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
@@ -431,7 +441,10 @@ struct Wave {
                 }
             }
             const uint64_t mask = __ballot(hit);
-            if (mask) push(hit, mask, (uint32_t)i, tag);
+            if (mask) {
+                push(hit, mask, (uint32_t)i, tag);
+                pump();
+            }
             prev_ok = ok;
             tprev = tau;
         }
@@ -439,7 +452,7 @@ struct Wave {
 };
 
 template <typename T, int GEOM>
-__global__ __launch_bounds__(256) void k_deposit(const double *__restrict__ r, const double *__restrict__ beta,
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_deposit(const double *__restrict__ r, const double *__restrict__ beta,
                                                  const double *__restrict__ beta_dot,
                                                  const double *__restrict__ charge, const double *__restrict__ x_det,
                                                  const double *__restrict__ alpha, const double *__restrict__ rec,
@@ -451,6 +464,7 @@ __global__ __launch_bounds__(256) void k_deposit(const double *__restrict__ r, c
     __shared__ T wc_all[kWavesPerBlock][64 * WcLine<T>::P];
     __shared__ int wcb_all[kWavesPerBlock][64];
     __shared__ uint64_t want_all[kWavesPerBlock][64];
+    __shared__ int fpix_all[kWavesPerBlock][64];
     __shared__ double stage_all[kWavesPerBlock][64 * kStage];
     __shared__ unsigned long long red[4];
     const int lane = threadIdx.x & 63;
@@ -493,7 +507,9 @@ __global__ __launch_bounds__(256) void k_deposit(const double *__restrict__ r, c
     w.wc = wc_all[wv];
     w.wcb = wcb_all[wv];
     w.want = want_all[wv];
+    w.fpix = fpix_all[wv];
     w.stage = stage_all[wv];
+    w.qh = 0;
     w.qn = 0;
     for (int j = lane; j < 64 * WcLine<T>::P; j += 64) w.wc[j] = (T)0;
     w.wcb[lane] = -1;
@@ -505,9 +521,9 @@ __global__ __launch_bounds__(256) void k_deposit(const double *__restrict__ r, c
     for (int64_t k = wave_live ? k0 : k1; k < k1; ++k) {
         if (pflag[k] == 0) {
             if (GEOM == LW_GEOM_EXACT && w.series(k))
-                w.template fast_particle<true>(g, lane_ok, pix_in, k, c1, c2, c3);
+                w.template fast_particle<Wave<T, GEOM>::kSer>(g, lane_ok, pix_in, k, c1, c2, c3);
             else
-                w.template fast_particle<false>(g, lane_ok, pix_in, k, c1, c2, c3);
+                w.template fast_particle<kTauSqrt>(g, lane_ok, pix_in, k, c1, c2, c3);
         } else {
             w.careful_particle(g, lane_ok, pix_in, m, k, c0, c1, c2, c3);
         }
@@ -579,7 +595,7 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
     const int64_t blocks = group_slots * sh.n_tile_blocks;
     if (blocks > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: problem too large for one launch");
     unsigned long long *dg = (unsigned long long *)diag;
-    const dim3 grid((unsigned)blocks), block(64 * kWavesPerBlock);
+    const dim3 grid((unsigned)blocks), block(kBlockThreads);
 #define LW_DEPOSIT_LAUNCH(T, G)                                                                                     \
     k_deposit<T, G><<<grid, block, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge, gr->x_det, w.alpha, w.rec, w.pflag, \
                                            w.rmax2, (T *)E, dg, sh)

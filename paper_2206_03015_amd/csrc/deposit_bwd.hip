@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_deposit_bwd(const double *__restrict__ 
             const int64_t m = m0 + j;
             const PixGeo g = geo[j];
             const bool ok = usable && g.ok;
-            const double tau = ok ? arrival_tau<GEOM, false>(g, alpha, rs[0], rs[1], rs[2], rr, sh.inv_cdt) : 0.0;
+            const double tau = ok ? arrival_tau<GEOM, kTauSqrt>(g, alpha, rs[0], rs[1], rs[2], rr, sh.inv_cdt) : 0.0;
             const double tl = __shfl_up(tau, 1), tr = __shfl_down(tau, 1);
             const int okl = __shfl_up((int)ok, 1), okr = __shfl_down((int)ok, 1);
             const bool left = lane >= 1 && ok && okl && tau > tl;

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_direct_fd(const double *__restrict__ r,
                         // arrival time relative to t0 (s), formed in units of u = cdt / c
                         const double u = sh.cdt / kC;
                         const double alpha = ((sh.t_start + (double)i * sh.dt) - sh.t0) / u;
-                        ta = arrival_tau<GEOM, false>(g, alpha, r[s], r[s + 1], r[s + 2], 0.0, sh.inv_cdt) * u;
+                        ta = arrival_tau<GEOM, kTauSqrt>(g, alpha, r[s], r[s + 1], r[s + 2], 0.0, sh.inv_cdt) * u;
                         const T tk = (T)kap;
                         ex *= tk;
                         ey *= tk;
@@ -141,6 +141,122 @@ __global__ void k_fd_finish(const double *__restrict__ acc, double *__restrict__
     }
 }
 
+// Adjoint of the direct sum for FP64 inputs: with R_c, I_c the real and imaginary parts of the
+// forward sum F_c(w) (recomputed into acc) and A = E kappa, t = t_i + shift - t0 per (sample, pixel),
+//   dJ/dA_c = 2f sum_w dS(w) (R_c cos wt + I_c sin wt),
+//   dJ/dt   = 2f sum_w dS(w) w sum_c A_c (I_c cos wt - R_c sin wt),       f = dt^2 / 2pi,
+// then dJ/dE = kappa dJ/dA, dJ/dkappa = E.dJ/dA through lw_field_vjp, and dt/dr = -n/c.
+// A wavefront owns 64 consecutive samples of one particle (one per lane) and loops over every
+// pixel; the frequencies are staged 64 at a time in LDS.  Each sample is owned by one lane, so
+// the gradient is added without atomics.
+template <int GEOM>
+__global__ __launch_bounds__(256) void k_direct_fd_bwd(const double *__restrict__ r, const double *__restrict__ beta,
+                                                       const double *__restrict__ beta_dot,
+                                                       const double *__restrict__ charge,
+                                                       const double *__restrict__ x_det,
+                                                       const double *__restrict__ omega,
+                                                       const double *__restrict__ acc, const double *__restrict__ dS,
+                                                       double *__restrict__ d_r, double *__restrict__ d_beta,
+                                                       double *__restrict__ d_beta_dot, FdShape sh, double two_f)
+{
+    __shared__ double s_w[kWavesPerBlock][64][8];  // dS, w dS, R_x, I_x, R_y, I_y, R_z, I_z
+    __shared__ double s_nu[kWavesPerBlock][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+    const int64_t n_chunks = (sh.n_samples + 63) / 64;
+    const int64_t k = wave / n_chunks;
+    if (k >= sh.n_particles) return;  // whole wavefront idle; no block-level sync below
+    const int64_t i = (wave - k * n_chunks) * 64 + lane;
+    const bool in = i < sh.n_samples;
+    const size_t s = (size_t)(k * sh.n_samples + (in ? i : 0)) * 3;
+    double rs[3], bs[3], as[3];
+    for (int c = 0; c < 3; ++c) {
+        rs[c] = r[s + c];
+        bs[c] = beta[s + c];
+        as[c] = beta_dot[s + c];
+    }
+    const bool usable = in && sample_usable(rs, bs, as);
+    const double q = charge ? charge[k] : -kQe;
+    const double u = sh.cdt / kC;
+    const double alpha = ((sh.t_start + (double)i * sh.dt) - sh.t0) / u;
+    double gr[3] = {0, 0, 0}, gb[3] = {0, 0, 0}, ga[3] = {0, 0, 0};
+    for (int64_t m = 0; m < sh.n_pix; ++m) {
+        const PixGeo g = pix_geo(x_det, m);
+        const double *xm = x_det + 3 * m;
+        bool ok = usable && g.ok;
+        double ta = 0.0, kap = 0.0, E[3] = {0, 0, 0}, A[3] = {0, 0, 0};
+        if (ok) {
+            lw_field<double, GEOM>(g, xm, rs[0], rs[1], rs[2], bs[0], bs[1], bs[2], as[0], as[1], as[2], q, sh.fmask,
+                                   E[0], E[1], E[2], &kap);
+            ta = arrival_tau<GEOM, kTauSqrt>(g, alpha, rs[0], rs[1], rs[2], 0.0, sh.inv_cdt) * u;
+            for (int c = 0; c < 3; ++c) A[c] = E[c] * kap;
+            ok = isfinite(ta) && isfinite(A[0]) && isfinite(A[1]) && isfinite(A[2]);
+        }
+        double G[3] = {0, 0, 0}, K[3] = {0, 0, 0};
+        for (int64_t w0 = 0; w0 < sh.n_omega; w0 += 64) {
+            {
+                const int64_t w = w0 + lane;
+                double *row = s_w[wv][lane];
+                if (w < sh.n_omega) {
+                    const double *f = acc + ((size_t)m * sh.n_omega + w) * 6;
+                    const double d = dS[(size_t)m * sh.n_omega + w];
+                    s_nu[wv][lane] = omega[w] / (2.0 * kPi);
+                    row[0] = d;
+                    row[1] = d * omega[w];
+                    for (int c = 0; c < 6; ++c) row[2 + c] = f[c];
+                } else {
+                    s_nu[wv][lane] = 0.0;
+                    for (int c = 0; c < 8; ++c) row[c] = 0.0;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const int cnt = (int)std::min<int64_t>(64, sh.n_omega - w0);
+            if (ok) {
+                for (int j = 0; j < cnt; ++j) {
+                    const double x = s_nu[wv][j] * ta;
+                    double sn, cs;
+                    sincospi(2.0 * (x - floor(x)), &sn, &cs);
+                    const double *row = s_w[wv][j];
+                    for (int c = 0; c < 3; ++c) {
+                        const double Rc = row[2 + 2 * c], Ic = row[3 + 2 * c];
+                        G[c] = fma(row[0], fma(Rc, cs, Ic * sn), G[c]);
+                        K[c] = fma(row[1], fma(Ic, cs, -Rc * sn), K[c]);
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (ok) {
+            double gE[3], gk = 0.0, H = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                G[c] *= two_f;
+                gE[c] = kap * G[c];
+                gk = fma(E[c], G[c], gk);
+                H = fma(A[c], two_f * K[c], H);
+            }
+            lw_field_vjp<GEOM>(g, xm, rs, bs, as, q, sh.fmask, gE, gr, gb, ga, gk);
+            // t = t_i + (|x - r| - |x|)/c - t0 (exact) or t_i - n.r/c - t0 (far field): dt/dr = -n/c
+            double n[3] = {g.nx, g.ny, g.nz};
+            if (GEOM == LW_GEOM_EXACT) {
+                const double d0 = xm[0] - rs[0], d1 = xm[1] - rs[1], d2 = xm[2] - rs[2];
+                const double R = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                n[0] = d0 / R;
+                n[1] = d1 / R;
+                n[2] = d2 / R;
+            }
+            for (int c = 0; c < 3; ++c) gr[c] -= H * n[c] / kC;
+        }
+    }
+    if (in) {
+        for (int c = 0; c < 3; ++c) {
+            d_r[s + c] += gr[c];
+            d_beta[s + c] += gb[c];
+            d_beta_dot[s + c] += ga[c];
+        }
+    }
+}
+
 }  // namespace
 
 size_t direct_fd_ws_bytes(int64_t n_pix, int64_t n_omega)
@@ -198,6 +314,61 @@ lw_status launch_direct_fd(const lw_traj_t *t, const lw_grid_t *gr, const double
     const double f = t->dt * t->dt / (2.0 * kPi);
     k_fd_finish<<<(int)std::min<int64_t>((nS + 255) / 256, 65536), 256, 0, s>>>(acc, S, nS, f);
     return check_launch("lw_direct_fd");
+}
+
+lw_status launch_direct_fd_bwd(const lw_traj_t *t, const lw_grid_t *gr, const double *omega, int64_t n_omega,
+                               int fmask, int geom, const double *dS, double *d_r, double *d_beta, double *d_beta_dot,
+                               void *ws, size_t ws_bytes, hipStream_t s)
+{
+    const int64_t n_pix = gr->n_pix;
+    if (n_pix == 0 || n_omega == 0 || t->n_particles == 0) return LW_OK;
+    // forward sums F_c(w) in FP64 into the workspace (the |F|^2 pass is not needed)
+    double *acc = (double *)ws;
+    const int64_t nS = n_pix * n_omega;
+    k_fd_zero<<<(int)std::min<int64_t>((6 * nS + 255) / 256, 65536), 256, 0, s>>>(acc, 6 * nS);
+    FdShape sh;
+    sh.n_particles = t->n_particles;
+    sh.n_samples = t->n_samples;
+    sh.n_pix = n_pix;
+    sh.n_omega = n_omega;
+    sh.n_wblocks = (n_omega + 63) / 64;
+    const int64_t base = n_pix * sh.n_wblocks;
+    int64_t groups = std::max<int64_t>(1, (8192 + base - 1) / base);
+    groups = std::min<int64_t>(groups, t->n_particles);
+    sh.parts_per_group = (t->n_particles + groups - 1) / groups;
+    sh.n_groups = (t->n_particles + sh.parts_per_group - 1) / sh.parts_per_group;
+    sh.t_start = t->t_start;
+    sh.dt = t->dt;
+    sh.t0 = gr->t0;
+    sh.cdt = kC * t->dt;
+    sh.inv_cdt = 1.0 / sh.cdt;
+    sh.fmask = fmask;
+    {
+        const int64_t waves = base * sh.n_groups;
+        const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+        if (blocks > 0x7fffffff) return fail(LW_E_SHAPE, "lw_direct_fd_bwd: problem too large for one launch");
+        if (geom == LW_GEOM_EXACT)
+            k_direct_fd<double, LW_GEOM_EXACT><<<(unsigned)blocks, 256, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge,
+                                                                              gr->x_det, omega, acc, sh);
+        else
+            k_direct_fd<double, LW_GEOM_FARFIELD><<<(unsigned)blocks, 256, 0, s>>>(
+                t->r, t->beta, t->beta_dot, t->charge, gr->x_det, omega, acc, sh);
+    }
+    {
+        const int64_t waves = t->n_particles * ((t->n_samples + 63) / 64);
+        const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+        if (blocks > 0x7fffffff) return fail(LW_E_SHAPE, "lw_direct_fd_bwd: problem too large for one launch");
+        const double two_f = 2.0 * t->dt * t->dt / (2.0 * kPi);
+        if (geom == LW_GEOM_EXACT)
+            k_direct_fd_bwd<LW_GEOM_EXACT><<<(unsigned)blocks, 256, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge,
+                                                                         gr->x_det, omega, acc, dS, d_r, d_beta,
+                                                                         d_beta_dot, sh, two_f);
+        else
+            k_direct_fd_bwd<LW_GEOM_FARFIELD><<<(unsigned)blocks, 256, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge,
+                                                                            gr->x_det, omega, acc, dS, d_r, d_beta,
+                                                                            d_beta_dot, sh, two_f);
+    }
+    return check_launch("lw_direct_fd_bwd");
 }
 
 }  // namespace lw

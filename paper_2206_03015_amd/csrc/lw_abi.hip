@@ -98,6 +98,7 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec)
     case LW_WS_FFT_BWD:
         return fft_ws_bytes(n_a, n_b, prec);
     case LW_WS_DIRECT_FD:
+    case LW_WS_DIRECT_FD_BWD:
         return direct_fd_ws_bytes(n_a, n_b);
     default:
         return 0;
@@ -245,10 +246,31 @@ lw_status lw_deposit_td_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int pr
     return launch_deposit_bwd(traj, grid, field_mask, geom, (const double *)dE, d_r, d_beta, d_beta_dot, stream);
 }
 
-lw_status lw_direct_fd_bwd(const lw_traj_t *, const lw_grid_t *, const double *, int64_t, int, int, int,
-                           const double *, double *, double *, double *, void *, size_t, hipStream_t)
+lw_status lw_direct_fd_bwd(const lw_traj_t *traj, const lw_grid_t *grid, const double *omega, int64_t n_omega,
+                           int prec, int field_mask, int geom, const double *dS, double *d_r, double *d_beta,
+                           double *d_beta_dot, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    return fail(LW_E_UNSUPPORTED, "lw_direct_fd_bwd: not built yet");
+    const char *fn = "lw_direct_fd_bwd";
+    lw_status st = check_traj_samples(traj, fn);
+    if (st != LW_OK) return st;
+    if ((st = check_grid(grid, fn, false)) != LW_OK) return st;
+    if (prec == LW_PREC_MIXED) return fail(LW_E_UNSUPPORTED, "%s: only LW_PREC_FP64 is supported", fn);
+    if (prec != LW_PREC_FP64) return fail(LW_E_ARG, "%s: unknown prec %d", fn, prec);
+    if (field_mask <= 0 || (field_mask & ~(LW_FIELD_ACCEL | LW_FIELD_VELOCITY)))
+        return fail(LW_E_ARG, "%s: field_mask must be a non-empty combination of LW_FIELD_*", fn);
+    if (geom != LW_GEOM_EXACT && geom != LW_GEOM_FARFIELD) return fail(LW_E_ARG, "%s: unknown geometry %d", fn, geom);
+    if (n_omega < 0) return fail(LW_E_SHAPE, "%s: n_omega < 0", fn);
+    const bool work = n_omega > 0 && grid->n_pix > 0 && traj->n_particles > 0;
+    if (work && (!omega || !dS || !d_r || !d_beta || !d_beta_dot)) return fail(LW_E_ARG, "%s: NULL array", fn);
+    for (const void *p : {(const void *)omega, (const void *)dS, (const void *)d_r, (const void *)d_beta,
+                          (const void *)d_beta_dot})
+        if (p && !aligned(p, 8)) return fail(LW_E_ALIGN, "%s: arrays must be 8-byte aligned", fn);
+    if (ws && !aligned(ws, 256)) return fail(LW_E_ALIGN, "%s: ws must be 256-byte aligned", fn);
+    const size_t need = direct_fd_ws_bytes(grid->n_pix, n_omega);
+    if (work && (!ws || ws_bytes < need))
+        return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes < %zu needed", fn, ws_bytes, need);
+    return launch_direct_fd_bwd(traj, grid, omega, n_omega, field_mask, geom, dS, d_r, d_beta, d_beta_dot, ws,
+                                ws_bytes, stream);
 }
 
 }  // extern "C"

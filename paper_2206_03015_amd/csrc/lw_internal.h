@@ -52,19 +52,29 @@ __device__ __forceinline__ PixGeo pix_geo(const double *x_det, int64_t m)
 //   exact (Eq. advanced_condition):     tau = alpha - s/(c dt_obs) + |r_perp|^2 / (c dt_obs (|x - r| + |x| - s))
 // with alpha = (t_i - t0)/dt_obs and r_perp = r - s n.  The exact correction is the identity
 // |x - r| - |x| = -s + |r_perp|^2/(|x - r| + |x| - s), free of cancellation.
-// SERIES (valid when |r| <= 1e-4 |x|, checked by the caller): with x = s/|x| and
-// q = |r_perp|^2/(|x| - s)^2,  1/(|x| - s) = (1 + x + x^2 + x^3 + O(x^4))/|x|  and
-// 1/(|x - r| + |x| - s) = (1/(|x| - s)) (1/2 - q/8 + O(q^2)); |r_perp|^2 = |r|^2 - s^2.
-// Truncation is below 1e-16 relative under that bound.  Otherwise the sqrt/divide form is used.
+// FORM (exact geometry only):
+//   kTauSqrt    the correction with its square root and divide;
+//   kTauSeries  (valid when |r| <= 1e-4 |x|, checked by the caller) with x = s/|x| and
+//               q = |r_perp|^2/(|x| - s)^2:  1/(|x| - s) = (1 + x + x^2 + x^3 + O(x^4))/|x|,
+//               1/(|x - r| + |x| - s) = (1/(|x| - s)) (1/2 - q/8 + O(q^2)), |r_perp|^2 = |r|^2 - s^2;
+//               truncation below 1e-16 relative under that bound;
+//   kTauShort   the same expansion to first order, |r_perp|^2 (1 + x)/(2 |x|): it drops x^2 + q/4
+//               <= 1.25e-8 of the correction under the bound (used with single-precision fields).
 // Written with explicit fma so that every evaluation of the same (pixel, sample) gives the same bits.
-template <int GEOM, bool SERIES>
+constexpr int kTauSqrt = 0, kTauSeries = 1, kTauShort = 2;
+template <int GEOM, int FORM>
 __device__ __forceinline__ double arrival_tau(const PixGeo &g, double alpha, double rx, double ry, double rz, double rr,
                                               double inv_cdt)
 {
     const double s = fma(g.nz, rz, fma(g.ny, ry, g.nx * rx));
     double tau = fma(-s, inv_cdt, alpha);
     if (GEOM == LW_GEOM_EXACT) {
-        if (SERIES) {
+        if (FORM == kTauShort) {
+            const double p2 = fma(-s, s, rr);
+            const double k1 = 0.5 * inv_cdt * g.invD;  // loop invariants
+            const double k2 = k1 * g.invD;
+            tau = fma(p2, fma(s, k2, k1), tau);
+        } else if (FORM == kTauSeries) {
             const double p2 = fma(-s, s, rr);
             const double x = s * g.invD;
             const double h = fma(x, fma(x, x + 1.0, 1.0), 1.0);
@@ -140,11 +150,12 @@ __device__ __forceinline__ void lw_field(const PixGeo &g, const double *xm, doub
 // Vector-Jacobian product of lw_field (double): given g = dJ/dE at one (sample, pixel), adds
 // dJ/dr, dJ/dbeta, dJ/dbeta_dot to gr, gb, ga.  Reverse mode written from the field formula
 // E = P [F_vel (1-b^2)(n-b)/(kappa^3 R^2) + F_acc n x ((n-b) x a)/(c kappa^3 R)], kappa = 1 - n.b,
-// with n = (x - r)/R, R = |x - r| (exact geometry) or n, R fixed (far field).
+// with n = (x - r)/R, R = |x - r| (exact geometry) or n, R fixed (far field).  g_kappa adds a
+// gradient with respect to kappa itself (used where kappa multiplies E outside the field).
 template <int GEOM>
 __device__ __forceinline__ void lw_field_vjp(const PixGeo &g, const double *xm, const double *r, const double *b,
                                              const double *a, double q, int fmask, const double *gE, double *gr,
-                                             double *gb, double *ga)
+                                             double *gb, double *ga, double g_kappa = 0.0)
 {
     double n[3], R;
     if (GEOM == LW_GEOM_EXACT) {
@@ -170,7 +181,7 @@ __device__ __forceinline__ void lw_field_vjp(const PixGeo &g, const double *xm, 
     const double P = q * kCoulomb;
     const double k3 = kappa * kappa * kappa;
     const double nb[3] = {n[0] - b[0], n[1] - b[1], n[2] - b[2]};
-    double gn[3] = {0, 0, 0}, gnb[3] = {0, 0, 0}, gk = 0.0, gR = 0.0, gbb[3] = {0, 0, 0};
+    double gn[3] = {0, 0, 0}, gnb[3] = {0, 0, 0}, gk = g_kappa, gR = 0.0, gbb[3] = {0, 0, 0};
     if (fmask & LW_FIELD_ACCEL) {
         const double w[3] = {nb[1] * a[2] - nb[2] * a[1], nb[2] * a[0] - nb[0] * a[2], nb[0] * a[1] - nb[1] * a[0]};
         const double v[3] = {n[1] * w[2] - n[2] * w[1], n[2] * w[0] - n[0] * w[2], n[0] * w[1] - n[1] * w[0]};
@@ -234,6 +245,9 @@ lw_status launch_fft_bwd(const void *E, const void *dS, int64_t n_pix, int64_t n
                          void *dE, void *ws, size_t ws_bytes, hipStream_t s);
 lw_status launch_direct_fd(const lw_traj_t *traj, const lw_grid_t *grid, const double *omega, int64_t n_omega,
                            int prec, int field_mask, int geom, double *S, void *ws, size_t ws_bytes, hipStream_t s);
+lw_status launch_direct_fd_bwd(const lw_traj_t *traj, const lw_grid_t *grid, const double *omega, int64_t n_omega,
+                               int field_mask, int geom, const double *dS, double *d_r, double *d_beta,
+                               double *d_beta_dot, void *ws, size_t ws_bytes, hipStream_t s);
 size_t direct_fd_ws_bytes(int64_t n_pix, int64_t n_omega);
 lw_status launch_boris(const lw_traj_t *traj, double *r, double *beta, double *beta_dot, hipStream_t s);
 lw_status launch_boris_bwd(const lw_traj_t *traj, const double *g_r, const double *g_beta,

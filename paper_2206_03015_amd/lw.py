@@ -23,7 +23,7 @@ GEOM = {"exact": 0, "farfield": 1}
 ACCUMULATE = 1 << 8
 TRAJ_SAMPLES = 0
 TRAJ_BORIS = 1
-WS_DEPOSIT, WS_FFT, WS_DIRECT_FD, WS_DEPOSIT_BWD, WS_FFT_BWD = 1, 2, 3, 4, 5
+WS_DEPOSIT, WS_FFT, WS_DIRECT_FD, WS_DEPOSIT_BWD, WS_FFT_BWD, WS_DIRECT_FD_BWD = 1, 2, 3, 4, 5, 6
 
 c_d = ctypes.c_double
 c_i64 = ctypes.c_int64
@@ -285,4 +285,26 @@ def deposit_td_bwd(r, beta, beta_dot, t_start, dt, x_det, t0, dt_obs, n_obs, dE,
         _need(t, torch.float64, tuple(r.shape), nm)
     _check(lib.lw_deposit_td_bwd(ctypes.byref(tr), ctypes.byref(gr), PREC["fp64"], int(field_mask), GEOM[geom],
                                  _ptr(dE), _ptr(d_r), _ptr(d_b), _ptr(d_bd), None, 0, _stream()))
+    return d_r, d_b, d_bd
+
+
+def direct_fd_bwd(r, beta, beta_dot, t_start, dt, x_det, t0, omega, dS, field_mask=FIELD_ACCEL, geom="exact",
+                  charge=None, out=None, ws=None):
+    """lw_direct_fd_bwd (FP64): adds dJ/d(r, beta, beta_dot) for J = sum(dS * S_FD) into `out` (zeros if None)."""
+    lib = load()
+    tr = make_traj(r, beta, beta_dot, t_start, dt, charge)
+    gr = make_grid(x_det, t0, 1.0, 1)
+    n_w = int(omega.shape[0])
+    _need(omega, torch.float64, (n_w,), "omega")
+    _need(dS, torch.float64, (gr.n_pix, n_w), "dS")
+    if out is None:
+        out = tuple(torch.zeros_like(r) for _ in range(3))
+    d_r, d_b, d_bd = out
+    for t, nm in ((d_r, "d_r"), (d_b, "d_beta"), (d_bd, "d_beta_dot")):
+        _need(t, torch.float64, tuple(r.shape), nm)
+    if ws is None:
+        ws = _workspace(workspace_bytes(WS_DIRECT_FD_BWD, gr.n_pix, n_w, "fp64"), r.device)
+    _check(lib.lw_direct_fd_bwd(ctypes.byref(tr), ctypes.byref(gr), _ptr(omega), n_w, PREC["fp64"], int(field_mask),
+                                GEOM[geom], _ptr(dS), _ptr(d_r), _ptr(d_b), _ptr(d_bd), _ptr(ws), ws.numel(),
+                                _stream()))
     return d_r, d_b, d_bd

@@ -53,6 +53,7 @@ def test_workspace_sizes(lib):
     fft = lw.workspace_bytes(lw.WS_FFT, 7, 1 << 12, "fp64")
     assert fft >= 3 * (1 << 12) * 16 and fft % (3 * (1 << 12) * 16) == 0
     assert lw.workspace_bytes(lw.WS_DIRECT_FD, 3, 5) >= 3 * 5 * 6 * 8
+    assert lw.workspace_bytes(lw.WS_DIRECT_FD_BWD, 3, 5, "fp64") == lw.workspace_bytes(lw.WS_DIRECT_FD, 3, 5)
     assert lib.lw_workspace_bytes(999, 1, 1, 0) == 0
 
 
@@ -89,4 +90,18 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert lib.lw_spectrum_fft(None, 1, 64, 1e-20, 7, None, None, 0, None) == -1
     # misaligned pointers are refused
     assert lib.lw_spectrum_fft(ctypes.c_void_p(8), 1, 64, 1e-20, 0, ctypes.c_void_p(16), None, 0, None) == -3
+    # adjoints: FP64 only
+    tr.kind = lw.TRAJ_SAMPLES
+    p = ctypes.c_void_p(256)
+    tr.r = tr.beta = tr.beta_dot = p
+    gr.x_det = p
+    assert lib.lw_deposit_td_bwd(ctypes.byref(tr), ctypes.byref(gr), 1, 1, 0, p, p, p, p, None, 0, None) == -6
+    assert lib.lw_direct_fd_bwd(ctypes.byref(tr), ctypes.byref(gr), p, 4, 1, 1, 0, p, p, p, p, None, 0, None) == -6
+    assert lib.lw_direct_fd_bwd(ctypes.byref(tr), ctypes.byref(gr), p, 4, 0, 1, 0, p, p, p, p, None, 0, None) == -4
+    tb = lw.Traj()
+    tb.kind = lw.TRAJ_SAMPLES
+    tb.n_particles = 1
+    tb.n_samples = 10
+    tb.dt = 1e-18
+    assert lib.lw_trajectory_boris_bwd(ctypes.byref(tb), p, p, p, p, p, None) == -1  # kind must be BORIS
     assert lib.lw_version().startswith(b"liblw")

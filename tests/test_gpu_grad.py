@@ -230,3 +230,47 @@ def test_lw_spectrum_autograd_matches_entry_points():
     for auto, ref in ((r.grad, gr), (b.grad, gb), (bd.grad, ga)):
         a = auto.cpu().numpy()
         assert np.max(np.abs(a - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def fd_case(n_omega):
+    c = synthetic(n_p=3, n_samples=300, n_pix=5, n_obs=256, seed=2)
+    tau, _, _ = oracle.eval_samples(c["t_start"], c["dt"], c["r"], c["beta"], c["beta_dot"], c["x_det"][:1], 0.0, 1.0)
+    w1 = 2 * np.pi / (np.ptp(tau) / 30)
+    return c, np.linspace(0.2, 2.0, n_omega) * w1
+
+
+@pytest.mark.parametrize("geom", ["exact", "farfield"])
+@pytest.mark.parametrize("n_omega", [37, 100])
+def test_direct_fd_bwd(geom, n_omega):
+    """lw_direct_fd_bwd against complex-step derivatives of the oracle's direct sum (random
+    directions) and central differences of the GPU forward in FP64 (smooth directions)."""
+    from paper_2206_03015_amd import lw
+    c, omega = fd_case(n_omega)
+    rng = np.random.default_rng(n_omega)
+    dS = rng.random((c["x_det"].shape[0], n_omega))
+    gr, gb, ga = (x.cpu().numpy() for x in lw.direct_fd_bwd(
+        T(c["r"]), T(c["beta"]), T(c["beta_dot"]), c["t_start"], c["dt"], T(c["x_det"]), c["t0"], T(omega), T(dS),
+        field_mask=3, geom=geom, charge=T(c["charge"])))
+    vr, vb, va = directions(c, rng)
+    for w in ((vr, 0 * vb, 0 * va), (0 * vr, vb, 0 * va), (0 * vr, 0 * vb, va)):
+        d_cs, _ = og.fd_directional_derivative(c["t_start"], c["dt"], c["r"], c["beta"], c["beta_dot"], *w,
+                                               c["x_det"], c["t0"], omega, dS, charge=c["charge"], field_mask=3,
+                                               geom=GEOMS[geom])
+        d_gpu = np.sum(gr * w[0]) + np.sum(gb * w[1]) + np.sum(ga * w[2])
+        print(f"{geom} n_omega {n_omega}: complex-step {d_cs:.9e} gpu {d_gpu:.9e}")
+        assert d_gpu == pytest.approx(d_cs, rel=1e-8, abs=0)
+
+    def J(r, b, a):
+        S = lw.direct_fd(T(r), T(b), T(a), c["t_start"], c["dt"], T(c["x_det"]), c["t0"], T(omega), prec="fp64",
+                         field_mask=3, geom=geom, charge=T(c["charge"]))
+        return float(torch.sum(T(dS) * S).cpu())
+
+    vr, vb, va = smooth_directions(c, rng)
+    z = 0.0 * vr
+    for name, w in (("r", (vr, z, z)), ("beta", (z, vb, z)), ("beta_dot", (z, z, va))):
+        h = 1e-4
+        fd = (J(c["r"] + h * w[0], c["beta"] + h * w[1], c["beta_dot"] + h * w[2]) -
+              J(c["r"] - h * w[0], c["beta"] - h * w[1], c["beta_dot"] - h * w[2])) / (2 * h)
+        d_gpu = np.sum(gr * w[0]) + np.sum(gb * w[1]) + np.sum(ga * w[2])
+        print(f"{geom} {name}: gpu-adjoint {d_gpu:.9e} gpu-fd {fd:.9e}")
+        assert fd == pytest.approx(d_gpu, rel=1e-6, abs=0)

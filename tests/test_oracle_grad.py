@@ -181,3 +181,39 @@ def test_params_derivative_matches_central_differences(which):
     assert J0 == pytest.approx(J(W.gamma, L.a0), rel=1e-10, abs=0)
     assert abs(d_cs * x0 / J0) > 0.1  # the objective really depends on the parameter
     assert d_cs == pytest.approx(fd, rel=tol, abs=0)
+
+
+# ---- the direct frequency-domain sum in complex arithmetic -------------------------------------
+
+def fd_case(seed=2):
+    c = small_case(seed=seed, n_pix=4)
+    tau, _, _ = oracle.eval_samples(c["t_start"], c["dt"], c["r"], c["beta"], c["beta_dot"], c["x_det"][:1], 0.0, 1.0)
+    w1 = 2 * np.pi / (np.ptp(tau) / 30)  # ~30 periods over the arrival-time span
+    return c, np.linspace(0.2, 2.0, 37) * w1
+
+
+@pytest.mark.parametrize("geom", [0, 1])
+def test_direct_fd_complex_matches_c_oracle_and_differences(geom):
+    """Value equals orc_direct_fd; the complex-step derivative equals its central differences
+    (the FD sum is smooth in the samples: step 1e-4 along smooth directions)."""
+    c, omega = fd_case()
+    args = (c["t_start"], c["dt"])
+    So = oracle.direct_fd(*args, c["r"], c["beta"], c["beta_dot"], c["x_det"], c["t0"], omega, charge=c["charge"],
+                          field_mask=3, geom=geom)
+    Sc = og.direct_fd_complex(*args, c["r"], c["beta"], c["beta_dot"], c["x_det"], c["t0"], omega,
+                              charge=c["charge"], field_mask=3, geom=geom)
+    assert np.max(np.abs(Sc.imag)) == 0.0
+    assert np.max(np.abs(Sc.real - So)) <= 1e-12 * np.max(So)
+    rng = np.random.default_rng(1)
+    dS = rng.random(So.shape)
+    vr, vb, va = smooth_directions(c, rng)
+    z = 0.0 * vr
+    for name, v in (("r", (vr, z, z)), ("beta", (z, vb, z)), ("beta_dot", (z, z, va))):
+        d, J = og.fd_directional_derivative(*args, c["r"], c["beta"], c["beta_dot"], *v, c["x_det"], c["t0"], omega,
+                                            dS, charge=c["charge"], field_mask=3, geom=geom)
+        h = 1e-4
+        Jp = np.sum(dS * oracle.direct_fd(*args, c["r"] + h * v[0], c["beta"] + h * v[1], c["beta_dot"] + h * v[2],
+                                          c["x_det"], c["t0"], omega, charge=c["charge"], field_mask=3, geom=geom))
+        Jm = np.sum(dS * oracle.direct_fd(*args, c["r"] - h * v[0], c["beta"] - h * v[1], c["beta_dot"] - h * v[2],
+                                          c["x_det"], c["t0"], omega, charge=c["charge"], field_mask=3, geom=geom))
+        assert d == pytest.approx((Jp - Jm) / (2 * h), rel=1e-6, abs=0), name
