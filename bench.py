@@ -169,12 +169,12 @@ def main():
             den = torch.linalg.vector_norm(bb, dim=1)
             ok = den > 0
             errs.append((num[ok] / den[ok]).cpu().numpy())
-        errs = np.concatenate(errs) if errs else np.zeros(1)
+        errs = np.concatenate(errs) if errs else np.zeros(0)
         out["fp64"] = {"ms_per_step": res64["ms_per_step"], "deposit_ms": res64["deposit_ms"],
                        "fft_ms": res64["fft_ms"]}
         out["mixed_vs_fp64_speedup"] = res64["ms_per_step"] / mixed["ms_per_step"]
-        out["mixed_vs_fp64_band_l2_err"] = {"max": float(errs.max()), "median": float(np.median(errs)),
-                                           "pixels": int(errs.size)}
+        out["mixed_vs_fp64_band_l2_err"] = ({"max": float(errs.max()), "median": float(np.median(errs)),
+                                            "pixels": int(errs.size)} if errs.size else None)
         del S64
     del S_mixed
     torch.cuda.empty_cache()

@@ -58,6 +58,15 @@ __device__ __forceinline__ int64_t grid_count(double tau, double n_obs)
     return (int64_t)fmin(fmax(floor(tau) + 1.0, 0.0), n_obs);
 }
 
+// Atomic add into LDS through an LDS-qualified pointer, so that the compiler cannot merge it
+// with a global atomic on another path into one flat (address-space generic) atomic.
+template <typename T>
+__device__ __forceinline__ void lds_add(T *p, T v)
+{
+    typedef __attribute__((address_space(3))) T lds_t;
+    __hip_atomic_fetch_add((lds_t *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -277,9 +286,9 @@ struct Wave {
                 const T vx = w1 * eax + w * ebx, vy = w1 * eay + w * eby, vz = w1 * eaz + w * ebz;
                 if (u / NL == seg) {
                     T *line = wc + ml * WcLine<T>::P + (int)(u % NL);
-                    atomicAdd(line, vx);
-                    atomicAdd(line + NL, vy);
-                    atomicAdd(line + 2 * NL, vz);
+                    lds_add(line, vx);
+                    lds_add(line + NL, vy);
+                    lds_add(line + 2 * NL, vz);
                 } else {
                     T *Em = E + (size_t)m * 3 * sh.n_obs;
                     atomic_add(Em + u, vx);
