@@ -2,11 +2,13 @@
 // Sec. "Interpolation"), forward pass.
 //
 // Work decomposition (one GPU's share of the paper's detector decomposition):
-//   * a wavefront owns 64 pixels (one per lane) and a group of particles;
-//   * for each particle it streams the trajectory samples through scalar loads
-//     (wavefront-uniform), forms every (particle, sample, pixel) arrival time in
-//     double and tests whether the interval (tau_{i-1}, tau_i] crosses the next
-//     grid point of that pixel's window;
+//   * a wavefront owns 64 x kPPL pixels (kPPL per lane) and a group of particles;
+//   * for each particle it stages 64 samples at a time in LDS (lane j loads sample j),
+//     every lane reads each staged sample once (a broadcast) and uses it for each of its
+//     pixels: it forms the (particle, sample, pixel) arrival time in double and tests
+//     whether the interval (tau_{i-1}, tau_i] crosses the next grid point of that
+//     pixel's window.  The broadcast reads bound this loop (LDS returns 128 B per
+//     clock), so kPPL pixels per lane divide their cost by kPPL;
 //   * a crossing appends (particle, sample, pixel) to a per-wavefront queue in LDS;
 //     whenever 64 entries are queued, all lanes take one entry each, evaluate the
 //     Lienard-Wiechert field at the interval's two ends and add the interpolated
@@ -30,16 +32,20 @@
 namespace lw {
 namespace {
 
-constexpr int kWavesPerBlock = 4;
+constexpr int kPPL = 2;                // pixels per lane
+constexpr int kTilePix = 64 * kPPL;     // pixels per wavefront
+constexpr int kPixBits = kPPL == 1 ? 6 : kPPL == 2 ? 7 : 8;
+static_assert((1 << kPixBits) == kTilePix, "kPPL must be 1, 2 or 4");
+constexpr int kWavesPerBlock = 1;
 constexpr int kBlockThreads = 64 * kWavesPerBlock;
-constexpr uint32_t kQCap = 320;  // queue ring per wavefront (at most 63 pending + 4 x 64 appended between drains)
-// write-combining line per pixel: 32-byte segments of the trace (8 floats or 4 doubles)
+constexpr uint32_t kQCap = 64 + 2 * 64 * kPPL;  // queue ring per wavefront (63 pending + 2 x kTilePix appended between drains)
+// write-combining line per pixel: 16-byte segments of the trace (4 floats or 2 doubles)
 template <typename T>
 struct WcLine {
-    static constexpr int N = 32 / sizeof(T);   // grid points per line
+    static constexpr int N = 16 / sizeof(T);   // grid points per line
     static constexpr int P = 3 * N + 1;        // LDS stride per pixel (odd: no bank conflicts)
 };
-constexpr uint64_t kWantNone = 0ull;  // below every request: (queue position + 1) << 32 | segment
+constexpr uint32_t kWantNone = 0u;  // below every request (segment + 1)
 constexpr int kStage = 6;  // doubles per staged sample: alpha, x, y, z, |r|^2, pad
 constexpr int kTargetWaves = 16384;
 // (|r|/|x|)^2 up to which the series form of the exact-geometry arrival time is used
@@ -201,12 +207,13 @@ struct Wave {
     double invD2max;  // wavefront maximum of 1/|x_m|^2
     int lane;
     int64_t tile, k0;
-    uint2 *q;          // queue ring in LDS: {sample index, (particle - k0) << 6 | lane}
-    T *wc;             // write-combining lines in LDS, [64 pixels][WcLine<T>::P] (3 components x N)
-    int *wcb;          // [64] trace segment each line holds (-1: none)
-    uint64_t *want;    // [64] ((queue position + 1) << 32 | segment of the grid point after the latest hit)
-    int *fpix;         // [64] pixel of the j-th line of a flush
+    uint2 *q;          // queue ring in LDS: {sample index, (particle - k0) << kPixBits | pixel in tile}
+    T *wc;             // write-combining lines in LDS, [kTilePix][WcLine<T>::P] (3 components x N)
+    int *wcb;          // [kTilePix] trace segment each line holds (-1: none)
+    uint32_t *want;    // [kTilePix] 1 + the furthest segment holding the grid point after a hit in this drain
+    int *fpix;         // [64] pixel (in tile) of the j-th line of a flush
     double *stage;     // staged sample records in LDS, [64][kStage]
+    PixGeo gl[kPPL];   // geometry of this lane's pixels (lane + 64 h)
     uint32_t qh, qn;   // queue ring head and length
     // arrival-time form of series particles: the short expansion goes with single-precision fields
     static constexpr int kSer = sizeof(T) == 4 ? kTauShort : kTauSeries;
@@ -230,14 +237,14 @@ struct Wave {
 
     __device__ __forceinline__ static uint32_t qwrap(uint32_t v) { return v >= kQCap ? v - kQCap : v; }
 
-    // Add the lines of the pixels in `mask` to the trace and clear them: lane l of a pass takes
-    // value l % 3N (component (l % 3N) / N, grid point l % N) of the (l / 3N)-th line.
-    __device__ void flush_lines(uint64_t mask)
+    // Add the lines of pixels 64 h + (bits of `mask`) to the trace and clear them: lane l of a pass
+    // takes value l % 3N (component (l % 3N) / N, grid point l % N) of the (l / 3N)-th line.
+    __device__ void flush_lines(uint64_t mask, int h)
     {
         constexpr int NL = WcLine<T>::N, V = 3 * NL;
         const int n = __popcll(mask);
         if (n == 0) return;
-        if ((mask >> lane) & 1ull) fpix[lanes_below(mask)] = lane;
+        if ((mask >> lane) & 1ull) fpix[lanes_below(mask)] = lane + 64 * h;
         __builtin_amdgcn_wave_barrier();
         for (int l = lane; l < n * V; l += 64) {
             const int jj = l / V, w = l - jj * V;
@@ -247,7 +254,7 @@ struct Wave {
             const T v = *line;
             *line = (T)0;
             const int64_t u = (int64_t)wcb[p] * NL + o;
-            if (v != (T)0 && u < sh.n_obs) atomic_add(E + ((size_t)(tile * 64 + p) * 3 + c) * sh.n_obs + u, v);
+            if (v != (T)0 && u < sh.n_obs) atomic_add(E + ((size_t)(tile * kTilePix + p) * 3 + c) * sh.n_obs + u, v);
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -257,12 +264,30 @@ struct Wave {
     {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        if ((uint32_t)lane < cnt) {
-            const uint2 e = q[qwrap(qh + (uint32_t)lane)];
+        const bool act = (uint32_t)lane < cnt;
+        const uint2 e = act ? q[qwrap(qh + (uint32_t)lane)] : make_uint2(1u, 0u);
+        const int ml0 = (int)(e.y & (uint32_t)(kTilePix - 1));
+        // the entry's pixel geometry from the lane that owns the pixel (all lanes take part)
+        PixGeo g;
+        {
+            const int own = ml0 & 63, hh = ml0 >> 6;
+            auto pick = [&](double v0, double v1) {
+                const double a = __shfl(v0, own);
+                const double b = kPPL > 1 ? __shfl(v1, own) : a;
+                return hh ? b : a;
+            };
+            g.nx = pick(gl[0].nx, gl[kPPL - 1].nx);
+            g.ny = pick(gl[0].ny, gl[kPPL - 1].ny);
+            g.nz = pick(gl[0].nz, gl[kPPL - 1].nz);
+            g.D = pick(gl[0].D, gl[kPPL - 1].D);
+            g.invD = pick(gl[0].invD, gl[kPPL - 1].invD);
+            g.ok = true;
+        }
+        if (act) {
             const uint32_t i = e.x, kl = e.y;
-            const int64_t k = k0 + (int64_t)(kl >> 6);
-            const int64_t m = tile * 64 + (int64_t)(kl & 63u);
-            const PixGeo g = pix_geo(x_det, m);
+            const int64_t k = k0 + (int64_t)(kl >> kPixBits);
+            const int ml = ml0;
+            const int64_t m = tile * kTilePix + ml;
             const bool ser = series(k);
             const double ta = tau_any(g, ser, k, (int64_t)i - 1);
             const double tb = tau_any(g, ser, k, (int64_t)i);
@@ -278,7 +303,6 @@ struct Wave {
             const int64_t u0 = grid_count(ta, nob), u1 = grid_count(tb, nob);
             const double idt = 1.0 / (tb - ta);
             constexpr int NL = WcLine<T>::N;
-            const int ml = (int)(kl & 63u);
             const int seg = wcb[ml];
             for (int64_t u = u0; u < u1; ++u) {
                 const double wd = ((double)u - ta) * idt;
@@ -296,22 +320,24 @@ struct Wave {
                     atomic_add(Em + 2 * sh.n_obs + u, vz);
                 }
             }
-            if (u1 > u0) atomicMax((unsigned long long *)(want + ml), ((uint64_t)(lane + 1) << 32) | (uint64_t)(u1 / NL));
+            if (u1 > u0) atomicMax(want + ml, (uint32_t)(u1 / NL) + 1u);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         // steer each pixel's line to the segment of its next grid point; flush lines that move
-        {
-            const uint64_t wnt = want[lane];
-            want[lane] = kWantNone;
-            const int cur = wcb[lane];
-            const int nxt = wnt == kWantNone ? cur : (int)(uint32_t)wnt;
+#pragma unroll
+        for (int h = 0; h < kPPL; ++h) {
+            const int p = lane + 64 * h;
+            const uint32_t wnt = want[p];
+            want[p] = kWantNone;
+            const int cur = wcb[p];
+            const int nxt = wnt == kWantNone ? cur : (int)(wnt - 1u);
             const bool move = nxt != cur && nxt * (int64_t)WcLine<T>::N < sh.n_obs;
             const uint64_t fm = __ballot(move && cur >= 0);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            flush_lines(fm);
-            if (move) wcb[lane] = nxt;
+            flush_lines(fm, h);
+            if (move) wcb[p] = nxt;
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
@@ -319,7 +345,7 @@ struct Wave {
         qn -= cnt;
     }
 
-    // Append the lanes with `hit` set (callers drain before 4 x 64 more can arrive).
+    // Append the lanes with `hit` set (callers drain before 2 x kTilePix more can arrive).
     __device__ __forceinline__ void push(bool hit, uint64_t mask, uint32_t i, uint32_t tag)
     {
         if (hit) q[qwrap(qh + qn + lanes_below(mask))] = make_uint2(i, tag);
@@ -333,15 +359,15 @@ struct Wave {
 
     // Fast path: tau strictly increasing, all samples usable.  Samples go through LDS in
     // chunks of 64 (lane j loads sample c0 + j with vector loads one chunk ahead); every lane
-    // then reads the staged samples by broadcast, four per trip.
+    // then reads the staged samples by broadcast, two per trip, each for its kPPL pixels.
     template <int FORM>
-    __device__ void fast_particle(const PixGeo &g, bool lane_ok, bool pix_in, int64_t k, unsigned long long &c1,
-                                  unsigned long long &c2, unsigned long long &c3)
+    __device__ void fast_particle(const PixGeo *g, const bool *lane_ok, const bool *pix_in, int64_t k,
+                                  unsigned long long &c1, unsigned long long &c2, unsigned long long &c3)
     {
         const int64_t ns = sh.n_samples;
         const double nob = (double)sh.n_obs;
         const double *s0 = src + (size_t)k * ns * RS;
-        const uint32_t tag = ((uint32_t)(k - k0) << 6) | (uint32_t)lane;
+        const uint32_t tag0 = ((uint32_t)(k - k0) << kPixBits) | (uint32_t)lane;
         double pa, px, py, pz, prr;
         // unconditional (clamped) loads, so that they stay in flight until the next chunk
         auto fetch = [&](int64_t c0) {
@@ -354,7 +380,7 @@ struct Wave {
             prr = GEOM == LW_GEOM_EXACT ? p[3] : 0.0;
         };
         fetch(0);
-        double tau = 0.0, tau0 = 0.0, gnext = INFINITY;
+        double tau[kPPL], tau0[kPPL], gnext[kPPL];
         for (int64_t c0 = 0; c0 < ns; c0 += 64) {
             double *st = stage + lane * kStage;
             st[0] = pa;
@@ -368,32 +394,37 @@ struct Wave {
             const int cnt = (int)std::min<int64_t>(64, ns - c0);
             int j = 0;
             if (c0 == 0) {
-                tau = tau0 = arrival_tau<GEOM, FORM>(g, stage[0], stage[1], stage[2], stage[3], stage[4], sh.inv_cdt);
-                gnext = lane_ok ? next_grid(tau, nob) : INFINITY;
+#pragma unroll
+                for (int h = 0; h < kPPL; ++h) {
+                    tau[h] = tau0[h] =
+                        arrival_tau<GEOM, FORM>(g[h], stage[0], stage[1], stage[2], stage[3], stage[4], sh.inv_cdt);
+                    gnext[h] = lane_ok[h] ? next_grid(tau[h], nob) : INFINITY;
+                }
                 j = 1;
             }
             auto step = [&](int jj, const double *e) {
-                tau = arrival_tau<GEOM, FORM>(g, e[0], e[1], e[2], e[3], e[4], sh.inv_cdt);
-                const bool hit = tau >= gnext;
-                const uint64_t mask = __ballot(hit);
-                if (mask) {
-                    if (hit) {
-                        const double f = floor(tau) + 1.0;
-                        gnext = f >= nob ? INFINITY : f;
+#pragma unroll
+                for (int h = 0; h < kPPL; ++h) {
+                    tau[h] = arrival_tau<GEOM, FORM>(g[h], e[0], e[1], e[2], e[3], e[4], sh.inv_cdt);
+                    const bool hit = tau[h] >= gnext[h];
+                    const uint64_t mask = __ballot(hit);
+                    if (mask) {
+                        if (hit) {
+                            const double f = floor(tau[h]) + 1.0;
+                            gnext[h] = f >= nob ? INFINITY : f;
+                        }
+                        push(hit, mask, (uint32_t)(c0 + jj), tag0 + 64u * (uint32_t)h);
                     }
-                    push(hit, mask, (uint32_t)(c0 + jj), tag);
                 }
             };
-            for (; j + 3 < cnt; j += 4) {
-                double v[4][5];
+            for (; j + 1 < cnt; j += 2) {
+                double v[2][5];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < 2; ++u)
 #pragma unroll
                     for (int c = 0; c < 5; ++c) v[u][c] = stage[(j + u) * kStage + c];
                 step(j, v[0]);
                 step(j + 1, v[1]);
-                step(j + 2, v[2]);
-                step(j + 3, v[3]);
                 pump();
             }
             for (; j < cnt; ++j) {
@@ -403,17 +434,20 @@ struct Wave {
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
-        if (lane_ok) {
-            const int64_t inside = grid_count(tau, nob) - grid_count(tau0, nob);
-            c3 += (unsigned long long)inside;
-            c2 += (unsigned long long)((int64_t)(floor(tau) - floor(tau0)) - inside);
-        } else if (pix_in) {
-            c1 += (unsigned long long)(ns - 1);
+#pragma unroll
+        for (int h = 0; h < kPPL; ++h) {
+            if (lane_ok[h]) {
+                const int64_t inside = grid_count(tau[h], nob) - grid_count(tau0[h], nob);
+                c3 += (unsigned long long)inside;
+                c2 += (unsigned long long)((int64_t)(floor(tau[h]) - floor(tau0[h])) - inside);
+            } else if (pix_in[h]) {
+                c1 += (unsigned long long)(ns - 1);
+            }
         }
     }
 
     // Careful path: the skip rules of lw_deposit_td interval by interval.
-    __device__ void careful_particle(const PixGeo &g, bool lane_ok, bool pix_in, int64_t m, int64_t k,
+    __device__ void careful_particle(const PixGeo &g, bool lane_ok, bool pix_in, int64_t m, int h, int64_t k,
                                      unsigned long long &c0, unsigned long long &c1, unsigned long long &c2,
                                      unsigned long long &c3)
     {
@@ -423,7 +457,7 @@ struct Wave {
         const double q = charge ? charge[k] : -kQe;
         bool prev_ok = false;
         double tprev = 0.0;
-        const uint32_t tag = ((uint32_t)(k - k0) << 6) | (uint32_t)lane;
+        const uint32_t tag = ((uint32_t)(k - k0) << kPixBits) | (uint32_t)(lane + 64 * h);
         for (int64_t i = 0; i < ns; ++i) {
             const size_t s = (size_t)k * ns + i;
             bool ok = lane_ok && sample_usable(r + 3 * s, beta + 3 * s, beta_dot + 3 * s);
@@ -470,9 +504,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
                                                  unsigned long long *__restrict__ diag, DepShape sh)
 {
     __shared__ uint2 q_all[kWavesPerBlock][kQCap];
-    __shared__ T wc_all[kWavesPerBlock][64 * WcLine<T>::P];
-    __shared__ int wcb_all[kWavesPerBlock][64];
-    __shared__ uint64_t want_all[kWavesPerBlock][64];
+    __shared__ T wc_all[kWavesPerBlock][kTilePix * WcLine<T>::P];
+    __shared__ int wcb_all[kWavesPerBlock][kTilePix];
+    __shared__ uint32_t want_all[kWavesPerBlock][kTilePix];
     __shared__ int fpix_all[kWavesPerBlock][64];
     __shared__ double stage_all[kWavesPerBlock][64 * kStage];
     __shared__ unsigned long long red[4];
@@ -486,15 +520,22 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     const int64_t xcd = b & 7, slot = b >> 3;
     const int64_t grp = (slot / sh.n_tile_blocks) * 8 + xcd;
     const int64_t tile = (slot % sh.n_tile_blocks) * kWavesPerBlock + wv;
-    const int64_t m = tile * 64 + lane;
-    const bool pix_in = tile < sh.n_tiles && m < sh.n_pix;
     const int64_t k0 = grp * sh.parts_per_group;
     const int64_t k1 = grp < sh.n_groups ? std::min(k0 + sh.parts_per_group, sh.n_particles) : k0;
     const bool wave_live = tile < sh.n_tiles;
 
-    const PixGeo g = pix_geo(x_det, pix_in ? m : 0);
-    const bool lane_ok = pix_in && g.ok;
-    double id2 = lane_ok ? g.invD * g.invD : 0.0;
+    int64_t m[kPPL];
+    bool pix_in[kPPL], lane_ok[kPPL];
+    PixGeo g[kPPL];
+    double id2 = 0.0;
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h) {
+        m[h] = tile * kTilePix + 64 * h + lane;
+        pix_in[h] = wave_live && m[h] < sh.n_pix;
+        g[h] = pix_geo(x_det, pix_in[h] ? m[h] : 0);
+        lane_ok[h] = pix_in[h] && g[h].ok;
+        if (lane_ok[h]) id2 = fmax(id2, g[h].invD * g[h].invD);
+    }
     for (int off = 32; off > 0; off >>= 1) id2 = fmax(id2, __shfl_xor(id2, off));
 
     Wave<T, GEOM> w;
@@ -518,11 +559,15 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     w.want = want_all[wv];
     w.fpix = fpix_all[wv];
     w.stage = stage_all[wv];
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h) w.gl[h] = g[h];
     w.qh = 0;
     w.qn = 0;
-    for (int j = lane; j < 64 * WcLine<T>::P; j += 64) w.wc[j] = (T)0;
-    w.wcb[lane] = -1;
-    w.want[lane] = kWantNone;
+    for (int j = lane; j < kTilePix * WcLine<T>::P; j += 64) w.wc[j] = (T)0;
+    for (int p = lane; p < kTilePix; p += 64) {
+        w.wcb[p] = -1;
+        w.want[p] = kWantNone;
+    }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 
@@ -534,11 +579,13 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
             else
                 w.template fast_particle<kTauSqrt>(g, lane_ok, pix_in, k, c1, c2, c3);
         } else {
-            w.careful_particle(g, lane_ok, pix_in, m, k, c0, c1, c2, c3);
+#pragma unroll
+            for (int h = 0; h < kPPL; ++h) w.careful_particle(g[h], lane_ok[h], pix_in[h], m[h], h, k, c0, c1, c2, c3);
         }
     }
     while (w.qn > 0) w.drain(w.qn < 64 ? w.qn : 64);
-    w.flush_lines(__ballot(w.wcb[lane] >= 0));
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h) w.flush_lines(__ballot(w.wcb[lane + 64 * h] >= 0), h);
 
     // counters: block reduction in LDS, then one global atomic per counter
     if (c0) atomicAdd(&red[0], c0);
@@ -592,7 +639,7 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
     sh.n_samples = ns;
     sh.n_pix = n_pix;
     sh.n_obs = n_obs;
-    sh.n_tiles = (n_pix + 63) / 64;
+    sh.n_tiles = (n_pix + kTilePix - 1) / kTilePix;
     sh.n_tile_blocks = (sh.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     int64_t groups = std::max<int64_t>(1, (kTargetWaves + sh.n_tiles - 1) / sh.n_tiles);
     groups = std::min<int64_t>(groups, n_p);

@@ -100,37 +100,40 @@ __device__ __forceinline__ void lw_field(const PixGeo &g, const double *xm, doub
                                          double bx, double by, double bz, double ax, double ay, double az, double q,
                                          int fmask, T &Ex, T &Ey, T &Ez, double *kappa_out = nullptr)
 {
-    double nx, ny, nz, R;
+    double nx, ny, nz, R, iR;
     if (GEOM == LW_GEOM_EXACT) {
         double dx = xm[0] - rx, dy = xm[1] - ry, dz = xm[2] - rz;
         R = sqrt(dx * dx + dy * dy + dz * dz);
-        nx = dx / R;
-        ny = dy / R;
-        nz = dz / R;
+        iR = 1.0 / R;
+        nx = dx * iR;
+        ny = dy * iR;
+        nz = dz * iR;
     } else {
         nx = g.nx;
         ny = g.ny;
         nz = g.nz;
         R = g.D;
+        iR = g.invD;
     }
     double b2 = bx * bx + by * by + bz * bz;
     double bn = sqrt(b2);
     double kappa = 1.0;
     if (bn > 0.0) {
+        // 1 - n.b = (1 - |b|) + |b| |n - b/|b||^2 / 2 for a unit n, with no cancellation of
+        // the O(1/gamma^2) result against O(1) terms
         double ib = 1.0 / bn;
         double dx = nx - bx * ib, dy = ny - by * ib, dz = nz - bz * ib;
-        kappa = (1.0 - b2) / (1.0 + bn) + 0.5 * bn * (dx * dx + dy * dy + dz * dz);
+        kappa = (1.0 - bn) + 0.5 * bn * (dx * dx + dy * dy + dz * dz);
     }
     if (kappa_out) *kappa_out = kappa;
-    T k = (T)kappa;
-    T ik3 = (T)1 / (k * k * k);
-    T pref = (T)(q * kCoulomb);
+    const double ik = 1.0 / kappa;
+    const double pk = q * kCoulomb * ik * ik * ik;  // q/(4 pi eps0 kappa^3)
     T tnx = (T)nx, tny = (T)ny, tnz = (T)nz;
     // n - beta in double: n_z - beta_z ~ 1/(2 gamma^2) would lose most of its bits in float
     T mx = (T)(nx - bx), my = (T)(ny - by), mz = (T)(nz - bz);
     Ex = Ey = Ez = (T)0;
     if (fmask & LW_FIELD_VELOCITY) {
-        T f = pref * (T)(1.0 - b2) * ik3 / (T)(R * R);
+        T f = (T)(pk * (1.0 - b2) * iR * iR);
         Ex += f * mx;
         Ey += f * my;
         Ez += f * mz;
@@ -140,7 +143,7 @@ __device__ __forceinline__ void lw_field(const PixGeo &g, const double *xm, doub
         // w = (n - b) x bd ; v = n x w
         T wx = my * taz - mz * tay, wy = mz * tax - mx * taz, wz = mx * tay - my * tax;
         T vx = tny * wz - tnz * wy, vy = tnz * wx - tnx * wz, vz = tnx * wy - tny * wx;
-        T f = pref * ik3 / (T)(kC * R);
+        T f = (T)(pk * iR / kC);
         Ex += f * vx;
         Ey += f * vy;
         Ez += f * vz;
