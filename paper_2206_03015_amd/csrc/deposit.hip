@@ -301,12 +301,12 @@ struct Wave {
                               beta_dot[sb], beta_dot[sb + 1], beta_dot[sb + 2], q, sh.fmask, ebx, eby, ebz);
             const double nob = (double)sh.n_obs;
             const int64_t u0 = grid_count(ta, nob), u1 = grid_count(tb, nob);
-            const double idt = 1.0 / (tb - ta);
+            // interpolation weight w = (u - ta)/(tb - ta), in the precision of the trace
+            const T idt = sizeof(T) == 4 ? (T)__builtin_amdgcn_rcpf((float)(tb - ta)) : (T)(1.0 / (tb - ta));
             constexpr int NL = WcLine<T>::N;
             const int seg = wcb[ml];
             for (int64_t u = u0; u < u1; ++u) {
-                const double wd = ((double)u - ta) * idt;
-                const T w = (T)wd, w1 = (T)(1.0 - wd);
+                const T w = (T)((double)u - ta) * idt, w1 = (T)1 - w;
                 const T vx = w1 * eax + w * ebx, vy = w1 * eay + w * eby, vz = w1 * eaz + w * ebz;
                 if (u / NL == seg) {
                     T *line = wc + ml * WcLine<T>::P + (int)(u % NL);

@@ -26,6 +26,19 @@ inline bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintp
 
 // ---------------------------------------------------------------------------------------------
 // Pixel geometry, shared by the arrival-time and field evaluations.
+// 1/sqrt(x) for positive normal x to double precision: the hardware estimate refined by two
+// Newton steps y <- y (3 - x y^2)/2 (each squares the relative error).
+__device__ __forceinline__ double rsqrt_fp64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
 struct PixGeo {
     double nx, ny, nz;  // unit direction x_m / |x_m|
     double D, invD;     // |x_m|, 1/|x_m|
@@ -100,11 +113,10 @@ __device__ __forceinline__ void lw_field(const PixGeo &g, const double *xm, doub
                                          double bx, double by, double bz, double ax, double ay, double az, double q,
                                          int fmask, T &Ex, T &Ey, T &Ez, double *kappa_out = nullptr)
 {
-    double nx, ny, nz, R, iR;
+    double nx, ny, nz, iR;
     if (GEOM == LW_GEOM_EXACT) {
         double dx = xm[0] - rx, dy = xm[1] - ry, dz = xm[2] - rz;
-        R = sqrt(dx * dx + dy * dy + dz * dz);
-        iR = 1.0 / R;
+        iR = rsqrt_fp64(dx * dx + dy * dy + dz * dz);
         nx = dx * iR;
         ny = dy * iR;
         nz = dz * iR;
@@ -112,16 +124,14 @@ __device__ __forceinline__ void lw_field(const PixGeo &g, const double *xm, doub
         nx = g.nx;
         ny = g.ny;
         nz = g.nz;
-        R = g.D;
         iR = g.invD;
     }
     double b2 = bx * bx + by * by + bz * bz;
-    double bn = sqrt(b2);
     double kappa = 1.0;
-    if (bn > 0.0) {
+    if (b2 > 0.0) {
         // 1 - n.b = (1 - |b|) + |b| |n - b/|b||^2 / 2 for a unit n, with no cancellation of
         // the O(1/gamma^2) result against O(1) terms
-        double ib = 1.0 / bn;
+        const double ib = rsqrt_fp64(b2), bn = b2 * ib;
         double dx = nx - bx * ib, dy = ny - by * ib, dz = nz - bz * ib;
         kappa = (1.0 - bn) + 0.5 * bn * (dx * dx + dy * dy + dz * dz);
     }
