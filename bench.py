@@ -287,7 +287,7 @@ def grad_leg(torch, dev):
         J.backward()
         e[2].record()
         torch.cuda.synchronize()
-        return float(J), float(gamma.grad), float(a0.grad), e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+        return float(J.detach()), float(gamma.grad), float(a0.grad), e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
 
     once()
     J, dg, da, fwd_ms, bwd_ms = once()
