@@ -115,12 +115,17 @@ typedef struct {
 #define LW_WS_DEPOSIT_BWD 4
 #define LW_WS_FFT_BWD 5
 #define LW_WS_DIRECT_FD_BWD 6
+#define LW_WS_DEPOSIT_BORIS 7
+#define LW_WS_DEPOSIT_BWD_BORIS 8
 
 /*
  * Workspace (scratch device memory) that the call `which` needs, in bytes:
- * n_a = n_particles (deposit, deposit_bwd), n_pix (fft, fft_bwd, direct_fd,
- * direct_fd_bwd); n_b = n_samples (deposit), n_obs (fft, fft_bwd), n_omega
- * (direct_fd, direct_fd_bwd).  Returns 0 for
+ * n_a = n_particles (deposit, deposit_bwd, deposit_boris, deposit_bwd_boris), n_pix
+ * (fft, fft_bwd, direct_fd, direct_fd_bwd); n_b = n_samples (deposit*), n_obs
+ * (fft, fft_bwd), n_omega (direct_fd, direct_fd_bwd).  LW_WS_DEPOSIT_BORIS and
+ * LW_WS_DEPOSIT_BWD_BORIS size the trajectory batches of LW_TRAJ_BORIS calls (at
+ * most ~4 GiB by default; any workspace that holds one particle's batch is
+ * accepted and sets the batch size).  Returns 0 for
  * an unknown `which`.  Larger workspaces are accepted; for the FFT a larger
  * workspace lets more pixels be transformed per pass.
  */
@@ -142,7 +147,11 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec);
  * tau_0); an interval with tau_i <= tau_{i-1} is skipped; an interval touching a
  * sample with a non-finite value or |beta| >= 1 is skipped.
  *
- * traj:       kind must be LW_TRAJ_SAMPLES.
+ * traj:       LW_TRAJ_SAMPLES, or LW_TRAJ_BORIS: the samples are then recomputed
+ *             inside the call by the FP64 Boris pusher of lw_trajectory_boris, batch
+ *             by batch of particles into the workspace (never the whole set), each
+ *             batch deposited and discarded; ws then needs
+ *             lw_workspace_bytes(LW_WS_DEPOSIT_BORIS, n_particles, n_samples, prec).
  * grid:       pixels and observer grid.
  * prec:       LW_PREC_FP64 (E is double) or LW_PREC_MIXED (E is float; tau and
  *             the crossing decisions are still computed in double).  In the exact
@@ -254,6 +263,22 @@ lw_status lw_spectrum_fft_bwd(const void *E, const void *dS, int64_t n_pix, int6
 lw_status lw_deposit_td_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom,
                             const void *dE, double *d_r, double *d_beta, double *d_beta_dot, void *ws,
                             size_t ws_bytes, hipStream_t stream);
+
+/*
+ * lw_deposit_td_bwd_boris -- adjoint of lw_deposit_td for LW_TRAJ_BORIS
+ * trajectories with respect to the initial conditions and the laser amplitude:
+ * given dE = dJ/dE_tot (double [n_pix][3][n_obs]), writes
+ *   grad_init[k][c] = dJ/d init[k][c]   [n_particles][6]  (overwritten)
+ *   grad_a0[k]      = particle k's part of dJ/d a0 [n_particles] (overwritten)
+ * For each batch of particles it recomputes the samples (lw_trajectory_boris),
+ * runs the sample adjoint (lw_deposit_td_bwd) into the workspace and contracts it
+ * with the pusher's tangents (lw_trajectory_boris_bwd).  prec: FP64 only.
+ * ws: >= lw_workspace_bytes(LW_WS_DEPOSIT_BWD_BORIS, n_particles, n_samples, prec)
+ * bytes, or any size that holds one particle's batch.
+ */
+lw_status lw_deposit_td_bwd_boris(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom,
+                                  const void *dE, double *grad_init, double *grad_a0, void *ws, size_t ws_bytes,
+                                  hipStream_t stream);
 
 /*
  * lw_direct_fd_bwd -- adjoint of lw_direct_fd with respect to the trajectory

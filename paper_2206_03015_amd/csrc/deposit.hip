@@ -73,6 +73,9 @@ __device__ __forceinline__ void lds_add(T *p, T v)
     __hip_atomic_fetch_add((lds_t *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// |r|^2 with the operation order of the pre-pass
+__device__ __forceinline__ double sq3(double x, double y, double z) { return fma(z, z, fma(y, y, x * x)); }
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -92,7 +95,6 @@ struct DepWs {
     int *pflag;                 // [n_p] 0 = fast path
     unsigned long long *rmax2;  // [n_p] bits of max_i |r_i|^2 (non-negative doubles order as integers)
     double *alpha;              // [n_s] (t_i - t0)/dt_obs
-    double *rec;                // [n_p][n_s][4] x, y, z, |r|^2 (exact geometry)
 };
 
 DepWs carve(void *ws, int64_t n_p, int64_t ns)
@@ -104,8 +106,6 @@ DepWs carve(void *ws, int64_t n_p, int64_t ns)
     w.rmax2 = (unsigned long long *)p;
     p += align_up((size_t)std::max<int64_t>(n_p, 1) * sizeof(unsigned long long), 256);
     w.alpha = (double *)p;
-    p += align_up((size_t)std::max<int64_t>(ns, 1) * sizeof(double), 256);
-    w.rec = (double *)p;
     return w;
 }
 
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void k_prepass(const double *__restrict__ r, c
                                                  const double *__restrict__ beta_dot, int64_t n_samples,
                                                  double t_start, double dt, double t0, double dt_obs, double inv_cdt,
                                                  double *__restrict__ alpha, int *__restrict__ pflag,
-                                                 unsigned long long *__restrict__ rmax2, double *__restrict__ rec)
+                                                 unsigned long long *__restrict__ rmax2)
 {
     __shared__ unsigned long long s_max[4];
     __shared__ int s_bad[4];
@@ -132,13 +132,7 @@ __global__ __launch_bounds__(256) void k_prepass(const double *__restrict__ r, c
         if (k == 0) alpha[i] = ai;
         const double *ri = r + 3 * s, *bi = beta + 3 * s, *di = beta_dot + 3 * s;
         const double x = ri[0], y = ri[1], z = ri[2];
-        const double rr = fma(z, z, fma(y, y, x * x));
-        if (rec) {
-            rec[4 * s] = x;
-            rec[4 * s + 1] = y;
-            rec[4 * s + 2] = z;
-            rec[4 * s + 3] = rr;
-        }
+        const double rr = sq3(x, y, z);
         bool b = !sample_usable(ri, bi, di);
         if (!b) {
             mx = fmax(mx, rr);
@@ -193,14 +187,13 @@ struct DepShape {
 // Per-wavefront state of the deposit kernel.
 template <typename T, int GEOM>
 struct Wave {
-    static constexpr int RS = GEOM == LW_GEOM_EXACT ? 4 : 3;  // doubles per streamed sample record
+
     const double *__restrict__ r;
     const double *__restrict__ beta;
     const double *__restrict__ beta_dot;
     const double *__restrict__ charge;
     const double *__restrict__ x_det;
     const double *__restrict__ alpha;
-    const double *__restrict__ src;  // streamed records: rec (exact) or r (far field)
     const unsigned long long *__restrict__ rmax2;
     T *__restrict__ E;
     DepShape sh;
@@ -226,12 +219,12 @@ struct Wave {
     template <int FORM>
     __device__ __forceinline__ double tau_rec(const PixGeo &g, double a, const double *p) const
     {
-        return arrival_tau<GEOM, FORM>(g, a, p[0], p[1], p[2], GEOM == LW_GEOM_EXACT ? p[3] : 0.0, sh.inv_cdt);
+        return arrival_tau<GEOM, FORM>(g, a, p[0], p[1], p[2], sq3(p[0], p[1], p[2]), sh.inv_cdt);
     }
 
     __device__ __forceinline__ double tau_any(const PixGeo &g, bool ser, int64_t k, int64_t i) const
     {
-        const double *p = src + ((size_t)k * sh.n_samples + i) * RS;
+        const double *p = r + ((size_t)k * sh.n_samples + i) * 3;
         return ser ? tau_rec<kSer>(g, alpha[i], p) : tau_rec<kTauSqrt>(g, alpha[i], p);
     }
 
@@ -366,18 +359,18 @@ struct Wave {
     {
         const int64_t ns = sh.n_samples;
         const double nob = (double)sh.n_obs;
-        const double *s0 = src + (size_t)k * ns * RS;
+        const double *s0 = r + (size_t)k * ns * 3;
         const uint32_t tag0 = ((uint32_t)(k - k0) << kPixBits) | (uint32_t)lane;
         double pa, px, py, pz, prr;
         // unconditional (clamped) loads, so that they stay in flight until the next chunk
         auto fetch = [&](int64_t c0) {
             const int64_t idx = std::min<int64_t>(c0 + lane, ns - 1);
-            const double *p = s0 + (size_t)idx * RS;
+            const double *p = s0 + (size_t)idx * 3;
             pa = alpha[idx];
             px = p[0];
             py = p[1];
             pz = p[2];
-            prr = GEOM == LW_GEOM_EXACT ? p[3] : 0.0;
+            prr = GEOM == LW_GEOM_EXACT ? sq3(px, py, pz) : 0.0;
         };
         fetch(0);
         double tau[kPPL], tau0[kPPL], gnext[kPPL];
@@ -498,7 +491,7 @@ template <typename T, int GEOM>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_deposit(const double *__restrict__ r, const double *__restrict__ beta,
                                                  const double *__restrict__ beta_dot,
                                                  const double *__restrict__ charge, const double *__restrict__ x_det,
-                                                 const double *__restrict__ alpha, const double *__restrict__ rec,
+                                                 const double *__restrict__ alpha,
                                                  const int *__restrict__ pflag,
                                                  const unsigned long long *__restrict__ rmax2, T *__restrict__ E,
                                                  unsigned long long *__restrict__ diag, DepShape sh)
@@ -545,7 +538,6 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     w.charge = charge;
     w.x_det = x_det;
     w.alpha = alpha;
-    w.src = GEOM == LW_GEOM_EXACT ? rec : r;
     w.rmax2 = rmax2;
     w.E = E;
     w.sh = sh;
@@ -602,7 +594,7 @@ size_t deposit_ws_bytes(int64_t n_particles, int64_t n_samples)
 {
     const size_t np = (size_t)std::max<int64_t>(n_particles, 1), ns = (size_t)std::max<int64_t>(n_samples, 1);
     return align_up(np * sizeof(int), 256) + align_up(np * sizeof(unsigned long long), 256) +
-           align_up(ns * sizeof(double), 256) + align_up(np * ns * 4 * sizeof(double), 256);
+           align_up(ns * sizeof(double), 256);
 }
 
 lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int fmask, int geom, bool accumulate,
@@ -632,7 +624,7 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
         if (n_p > 0x7fffffff || chunks > 65535) return fail(LW_E_SHAPE, "lw_deposit_td: too many samples");
         k_prepass<<<dim3((unsigned)n_p, (unsigned)chunks), 256, 0, s>>>(
             t->r, t->beta, t->beta_dot, ns, t->t_start, t->dt, gr->t0, gr->dt_obs, inv_cdt, w.alpha, w.pflag,
-            w.rmax2, geom == LW_GEOM_EXACT ? w.rec : nullptr);
+            w.rmax2);
     }
     DepShape sh;
     sh.n_particles = n_p;
@@ -653,7 +645,7 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
     unsigned long long *dg = (unsigned long long *)diag;
     const dim3 grid((unsigned)blocks), block(kBlockThreads);
 #define LW_DEPOSIT_LAUNCH(T, G)                                                                                     \
-    k_deposit<T, G><<<grid, block, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge, gr->x_det, w.alpha, w.rec, w.pflag, \
+    k_deposit<T, G><<<grid, block, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge, gr->x_det, w.alpha, w.pflag,       \
                                            w.rmax2, (T *)E, dg, sh)
     if (f64) {
         if (geom == LW_GEOM_EXACT)

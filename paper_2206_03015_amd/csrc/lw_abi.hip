@@ -76,6 +76,24 @@ lw_status check_grid(const lw_grid_t *g, const char *fn, bool need_grid)
 
 bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+lw_status check_traj_boris(const lw_traj_t *t, const char *fn)
+{
+    if (!t) return fail(LW_E_ARG, "%s: traj is NULL", fn);
+    if (t->kind != LW_TRAJ_BORIS) return fail(LW_E_ARG, "%s: traj->kind must be LW_TRAJ_BORIS", fn);
+    if (t->reserved != 0) return fail(LW_E_ARG, "%s: traj->reserved must be 0", fn);
+    if (t->n_particles < 0 || t->n_particles > (int64_t(1) << 28) || t->n_samples < 1 || t->n_samples >= kMaxSamples)
+        return fail(LW_E_SHAPE, "%s: bad sizes", fn);
+    if (!finite_pos(t->dt) || !(t->t_start > -1e300 && t->t_start < 1e300))
+        return fail(LW_E_ARG, "%s: dt must be positive and finite, t_start finite", fn);
+    const lw_laser_t &L = t->laser;
+    if (!finite_pos(L.lambda) || !(L.n_cycles > 0.0) || !(L.a0 >= 0.0 && L.a0 < 1e6) || !(L.w0 < 1e300))
+        return fail(LW_E_ARG, "%s: laser parameters out of range", fn);
+    if (t->n_particles > 0 && !t->init) return fail(LW_E_ARG, "%s: init is NULL", fn);
+    if ((t->init && !aligned(t->init, 8)) || (t->charge && !aligned(t->charge, 8)))
+        return fail(LW_E_ALIGN, "%s: init and charge must be 8-byte aligned", fn);
+    return LW_OK;
+}
+
 }  // namespace
 }  // namespace lw
 
@@ -100,6 +118,10 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec)
     case LW_WS_DIRECT_FD:
     case LW_WS_DIRECT_FD_BWD:
         return direct_fd_ws_bytes(n_a, n_b);
+    case LW_WS_DEPOSIT_BORIS:
+        return boris_stream_ws_bytes(n_a, n_b, boris_batch_default(n_a, n_b, 3), 3);
+    case LW_WS_DEPOSIT_BWD_BORIS:
+        return boris_stream_ws_bytes(n_a, n_b, boris_batch_default(n_a, n_b, 6), 6);
     default:
         return 0;
     }
@@ -109,7 +131,8 @@ lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, 
                         int64_t *diag, void *ws, size_t ws_bytes, hipStream_t stream)
 {
     const char *fn = "lw_deposit_td";
-    lw_status st = check_traj_samples(traj, fn);
+    const bool boris = traj && traj->kind == LW_TRAJ_BORIS;
+    lw_status st = boris ? check_traj_boris(traj, fn) : check_traj_samples(traj, fn);
     if (st != LW_OK) return st;
     if ((st = check_grid(grid, fn, true)) != LW_OK) return st;
     if (prec != LW_PREC_FP64 && prec != LW_PREC_MIXED) return fail(LW_E_ARG, "%s: unknown prec %d", fn, prec);
@@ -123,10 +146,17 @@ lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, 
     if (diag && !aligned(diag, 8)) return fail(LW_E_ALIGN, "%s: diag must be 8-byte aligned", fn);
     if (grid->n_pix > (int64_t(1) << 31) || traj->n_particles > (int64_t(1) << 40))
         return fail(LW_E_SHAPE, "%s: too many pixels or particles", fn);
+    if (ws && !aligned(ws, 256)) return fail(LW_E_ALIGN, "%s: workspace must be 256-byte aligned", fn);
+    if (boris) {
+        const bool work = traj->n_particles > 0 && grid->n_pix > 0;
+        if (work && (!ws || boris_batch_fit(traj->n_particles, traj->n_samples, ws_bytes, 3) < 1))
+            return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes holds no batch (one particle needs %zu)", fn,
+                        ws_bytes, boris_stream_ws_bytes(1, traj->n_samples, 1, 3));
+        return launch_deposit_boris(traj, grid, prec, field_mask, g, acc, E, diag, ws, ws_bytes, stream);
+    }
     const size_t need = deposit_ws_bytes(traj->n_particles, traj->n_samples);
     if (traj->n_particles > 0 && grid->n_pix > 0 && (!ws || ws_bytes < need))
         return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes < %zu needed", fn, ws_bytes, need);
-    if (ws && !aligned(ws, 256)) return fail(LW_E_ALIGN, "%s: workspace must be 256-byte aligned", fn);
     return launch_deposit(traj, grid, prec, field_mask, g, acc, E, diag, ws, ws_bytes, stream);
 }
 
@@ -244,6 +274,31 @@ lw_status lw_deposit_td_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int pr
         (d_beta_dot && !aligned(d_beta_dot, 8)))
         return fail(LW_E_ALIGN, "%s: misaligned pointer", fn);
     return launch_deposit_bwd(traj, grid, field_mask, geom, (const double *)dE, d_r, d_beta, d_beta_dot, stream);
+}
+
+lw_status lw_deposit_td_bwd_boris(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom,
+                                  const void *dE, double *grad_init, double *grad_a0, void *ws, size_t ws_bytes,
+                                  hipStream_t stream)
+{
+    const char *fn = "lw_deposit_td_bwd_boris";
+    lw_status st = check_traj_boris(traj, fn);
+    if (st != LW_OK) return st;
+    if ((st = check_grid(grid, fn, true)) != LW_OK) return st;
+    if (prec == LW_PREC_MIXED) return fail(LW_E_UNSUPPORTED, "%s: only LW_PREC_FP64 is supported", fn);
+    if (prec != LW_PREC_FP64) return fail(LW_E_ARG, "%s: unknown prec %d", fn, prec);
+    if (field_mask <= 0 || (field_mask & ~(LW_FIELD_ACCEL | LW_FIELD_VELOCITY)))
+        return fail(LW_E_ARG, "%s: field_mask must be a non-empty combination of LW_FIELD_*", fn);
+    if (geom != LW_GEOM_EXACT && geom != LW_GEOM_FARFIELD) return fail(LW_E_ARG, "%s: unknown geometry %d", fn, geom);
+    const bool work = traj->n_particles > 0;
+    if (work && (!grad_init || !grad_a0 || (grid->n_pix > 0 && !dE))) return fail(LW_E_ARG, "%s: NULL array", fn);
+    if ((dE && !aligned(dE, 16)) || (grad_init && !aligned(grad_init, 8)) || (grad_a0 && !aligned(grad_a0, 8)) ||
+        (ws && !aligned(ws, 256)))
+        return fail(LW_E_ALIGN, "%s: misaligned pointer", fn);
+    if (work && (!ws || boris_batch_fit(traj->n_particles, traj->n_samples, ws_bytes, 6) < 1))
+        return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes holds no batch (one particle needs %zu)", fn, ws_bytes,
+                    boris_stream_ws_bytes(1, traj->n_samples, 1, 6));
+    return launch_deposit_bwd_boris(traj, grid, field_mask, geom, (const double *)dE, grad_init, grad_a0, ws, ws_bytes,
+                                    stream);
 }
 
 lw_status lw_direct_fd_bwd(const lw_traj_t *traj, const lw_grid_t *grid, const double *omega, int64_t n_omega,

@@ -267,5 +267,14 @@ lw_status launch_boris_bwd(const lw_traj_t *traj, const double *g_r, const doubl
                            const double *g_beta_dot, double *grad_init, double *grad_a0, hipStream_t s);
 lw_status launch_deposit_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int field_mask, int geom, const double *dE,
                              double *d_r, double *d_beta, double *d_beta_dot, hipStream_t s);
+// trajectories recomputed batch by batch from LW_TRAJ_BORIS initial conditions (boris_stream.hip);
+// `arrays` = 3 for the forward batch buffers (r, beta, beta_dot), 6 for the adjoint (plus gradients)
+int64_t boris_batch_default(int64_t n_p, int64_t ns, int arrays);
+size_t boris_stream_ws_bytes(int64_t n_p, int64_t ns, int64_t batch, int arrays);
+int64_t boris_batch_fit(int64_t n_p, int64_t ns, size_t ws_bytes, int arrays);
+lw_status launch_deposit_boris(const lw_traj_t *t, const lw_grid_t *gr, int prec, int fmask, int geom,
+                               bool accumulate, void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s);
+lw_status launch_deposit_bwd_boris(const lw_traj_t *t, const lw_grid_t *gr, int fmask, int geom, const double *dE,
+                                   double *grad_init, double *grad_a0, void *ws, size_t ws_bytes, hipStream_t s);
 
 }  // namespace lw

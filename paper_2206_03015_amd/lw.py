@@ -24,6 +24,7 @@ ACCUMULATE = 1 << 8
 TRAJ_SAMPLES = 0
 TRAJ_BORIS = 1
 WS_DEPOSIT, WS_FFT, WS_DIRECT_FD, WS_DEPOSIT_BWD, WS_FFT_BWD, WS_DIRECT_FD_BWD = 1, 2, 3, 4, 5, 6
+WS_DEPOSIT_BORIS, WS_DEPOSIT_BWD_BORIS = 7, 8
 
 c_d = ctypes.c_double
 c_i64 = ctypes.c_int64
@@ -64,6 +65,8 @@ _SIGS = {
                                            ctypes.c_size_t, c_vp]),
     "lw_deposit_td_bwd": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "lw_deposit_td_bwd_boris": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_int, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "lw_direct_fd_bwd": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), c_vp, c_i64, ctypes.c_int,
                                         ctypes.c_int, ctypes.c_int, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t,
                                         c_vp]),
@@ -308,3 +311,51 @@ def direct_fd_bwd(r, beta, beta_dot, t_start, dt, x_det, t0, omega, dS, field_ma
                                 GEOM[geom], _ptr(dS), _ptr(d_r), _ptr(d_b), _ptr(d_bd), _ptr(ws), ws.numel(),
                                 _stream()))
     return d_r, d_b, d_bd
+
+
+def deposit_td_boris(init, n_samples, t_start, dt, a0, lam, w0, n_cycles, x_det, t0, dt_obs, n_obs, prec="mixed",
+                     field_mask=FIELD_ACCEL, geom="exact", charge=None, out=None, accumulate=False, diag=None, ws=None):
+    """lw_deposit_td with LW_TRAJ_BORIS: trajectories recomputed inside the call from init [n_p][6]
+    in batches.  Returns (E, diag)."""
+    lib = load()
+    tr = make_boris_traj(init, n_samples, t_start, dt, a0, lam, w0, n_cycles)
+    if charge is not None:
+        _need(charge, torch.float64, (int(init.shape[0]),), "charge")
+        tr.charge = c_vp(charge.data_ptr())
+    else:
+        tr.charge = None
+    gr = make_grid(x_det, t0, dt_obs, n_obs)
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    if out is None:
+        out = torch.empty((gr.n_pix, 3, int(n_obs)), dtype=dtype, device=init.device)
+    _need(out, dtype, (gr.n_pix, 3, int(n_obs)), "E")
+    if diag is None:
+        diag = torch.zeros(4, dtype=torch.int64, device=init.device)
+    if ws is None:
+        ws = _workspace(workspace_bytes(WS_DEPOSIT_BORIS, tr.n_particles, tr.n_samples, prec), init.device)
+    flags = GEOM[geom] | (ACCUMULATE if accumulate else 0)
+    _check(lib.lw_deposit_td(ctypes.byref(tr), ctypes.byref(gr), PREC[prec], int(field_mask), flags, _ptr(out),
+                             _ptr(diag), _ptr(ws), ws.numel(), _stream()))
+    return out, diag
+
+
+def deposit_td_bwd_boris(init, n_samples, t_start, dt, a0, lam, w0, n_cycles, x_det, t0, dt_obs, n_obs, dE,
+                         field_mask=FIELD_ACCEL, geom="exact", charge=None, ws=None):
+    """lw_deposit_td_bwd_boris (FP64): returns (grad_init [n_p][6], grad_a0 [n_p])."""
+    lib = load()
+    n_p = int(init.shape[0])
+    tr = make_boris_traj(init, n_samples, t_start, dt, a0, lam, w0, n_cycles)
+    if charge is not None:
+        _need(charge, torch.float64, (n_p,), "charge")
+        tr.charge = c_vp(charge.data_ptr())
+    else:
+        tr.charge = None
+    gr = make_grid(x_det, t0, dt_obs, n_obs)
+    _need(dE, torch.float64, (gr.n_pix, 3, int(n_obs)), "dE")
+    grad_init = torch.empty((n_p, 6), dtype=torch.float64, device=init.device)
+    grad_a0 = torch.empty((n_p,), dtype=torch.float64, device=init.device)
+    if ws is None:
+        ws = _workspace(workspace_bytes(WS_DEPOSIT_BWD_BORIS, n_p, tr.n_samples, "fp64"), init.device)
+    _check(lib.lw_deposit_td_bwd_boris(ctypes.byref(tr), ctypes.byref(gr), PREC["fp64"], int(field_mask), GEOM[geom],
+                                       _ptr(dE), _ptr(grad_init), _ptr(grad_a0), _ptr(ws), ws.numel(), _stream()))
+    return grad_init, grad_a0

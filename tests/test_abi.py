@@ -54,6 +54,12 @@ def test_workspace_sizes(lib):
     assert fft >= 3 * (1 << 12) * 16 and fft % (3 * (1 << 12) * 16) == 0
     assert lw.workspace_bytes(lw.WS_DIRECT_FD, 3, 5) >= 3 * 5 * 6 * 8
     assert lw.workspace_bytes(lw.WS_DIRECT_FD_BWD, 3, 5, "fp64") == lw.workspace_bytes(lw.WS_DIRECT_FD, 3, 5)
+    # Boris batches: the whole set when small, capped near 4 GiB when large
+    small = lw.workspace_bytes(lw.WS_DEPOSIT_BORIS, 10, 1000)
+    assert small >= 10 * 1000 * 72
+    big = lw.workspace_bytes(lw.WS_DEPOSIT_BORIS, 100000, 20001)
+    assert 3.5 * 2**30 < big < 4.5 * 2**30
+    assert lw.workspace_bytes(lw.WS_DEPOSIT_BWD_BORIS, 10, 1000) >= 10 * 1000 * 144
     assert lib.lw_workspace_bytes(999, 1, 1, 0) == 0
 
 
@@ -81,8 +87,8 @@ def test_host_validation_rejects_bad_arguments(lib):
     tr.n_samples = 0
     assert lib.lw_deposit_td(ctypes.byref(tr), ctypes.byref(gr), 0, 1, 0, None, None, None, 0, None) == -2
     tr.n_samples = 10
-    tr.kind = lw.TRAJ_BORIS
-    assert lib.lw_deposit_td(ctypes.byref(tr), ctypes.byref(gr), 0, 1, 0, None, None, None, 0, None) == -6
+    tr.kind = lw.TRAJ_BORIS  # accepted kind, but init is NULL
+    assert lib.lw_deposit_td(ctypes.byref(tr), ctypes.byref(gr), 0, 1, 0, None, None, None, 0, None) == -1
     # spectrum: n_obs must be a power of two >= 4
     assert lib.lw_spectrum_fft(None, 1, 100, 1e-20, 0, None, None, 0, None) == -2
     assert lib.lw_spectrum_fft(None, 1, 2, 1e-20, 0, None, None, 0, None) == -2
