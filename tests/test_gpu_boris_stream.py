@@ -1,6 +1,8 @@
 """LW_TRAJ_BORIS: lw_deposit_td recomputing the trajectories batch by batch inside the call,
 and lw_deposit_td_bwd_boris, against the same computation on stored trajectories and
-against the oracle (the large workload's shape: gamma = 100, 64 x 64 pixels, 2^20 grid)."""
+against the oracle at the shapes of the large workload (gamma = 100, 64 x 64 pixels, 2^20
+grid) and of the precision workload (gamma = 200, a0 = 1, 128 x 128 pixels, 2^18 grid at 16
+samples per period, harmonics 1..5)."""
 import numpy as np
 import pytest
 import torch
@@ -66,14 +68,23 @@ def test_stream_adjoint_equals_chained_adjoints(per_batch):
     assert np.max(np.abs(ga - ga2)) <= 1e-12 * np.max(np.abs(ga2))
 
 
-def large_cut(n_p):
-    """The large workload's beam, pulse, pixels and 2^20 grid with the n_p particles nearest the
-    bunch centre (the full run has 1e5)."""
-    W = inputs.workload("large")
+def centre_cut(name, n_p):
+    """A workload's beam, pulse, pixels and grid with the n_p particles nearest the bunch
+    centre (the full runs have 1e5)."""
+    W = inputs.workload(name)
     full = inputs.bunch_init(W)
     zc = np.sqrt(1.0 - 1.0 / W.gamma ** 2) * inputs.C_LIGHT * W.t_start
     init = np.ascontiguousarray(full[np.argsort(np.abs(full[:, 2] - zc))[:n_p]])
     return W.scaled(n_p=n_p), init
+
+
+def fp64_bound(W, r):
+    """Max relative spectral error that rounding of the arrival times alone allows: an arrival
+    time of magnitude M grid units carries ~eps M in any operation order, which moves a line
+    sampled s_p times per period by 2 pi/s_p of it (never below 1e-10)."""
+    M = np.max(np.abs((W.t_start + np.arange(W.n_samples) * W.dt - W.t0) / W.dt_obs)) + \
+        np.max(np.linalg.norm(r, axis=-1)) / (inputs.C_LIGHT * W.dt_obs)
+    return max(1e-10, (2 * np.pi / W.samples_per_period) * np.finfo(float).eps * M)
 
 
 def test_large_workload_shape_against_oracle():
@@ -82,7 +93,7 @@ def test_large_workload_shape_against_oracle():
     (band-L2 around the first harmonic <= 1e-4) and with the GPU FP64 path (max relative error
     within the rounding bound of the arrival times, 1e-10 or more)."""
     from paper_2206_03015_amd import lw
-    W, init_np = large_cut(16)
+    W, init_np = centre_cut("large", 16)
     L = W.laser
     x = inputs.pixel_positions(W.n_side, W.theta_max, W.D)
     args = (W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
@@ -97,12 +108,8 @@ def test_large_workload_shape_against_oracle():
     Eo, do = oracle.deposit_td(W.t_start, W.dt, r, b, bd, x[sel], W.t0, W.dt_obs, W.n_obs)
     So = oracle.spectrum(Eo, W.dt_obs)
     assert d64.tolist() == list(do)
-    # FP64 bound: an arrival time of magnitude M grid units carries rounding ~eps M in any
-    # operation order (here M ~ 1.5e7: the path term |n.r|/(c dt_obs) with |r| up to ~60 um at
-    # dt_obs = 13.7 zs), which moves a line sampled s_p = 8 times per period by 2 pi/s_p of it
-    M = np.max(np.abs((W.t_start + np.arange(W.n_samples) * W.dt - W.t0) / W.dt_obs)) + \
-        np.max(np.linalg.norm(r, axis=-1)) / (inputs.C_LIGHT * W.dt_obs)
-    tol64 = max(1e-10, (2 * np.pi / W.samples_per_period) * np.finfo(float).eps * M)
+    # here M ~ 1.5e7: the path term |n.r|/(c dt_obs) with |r| up to ~60 um at dt_obs = 13.7 zs
+    tol64 = fp64_bound(W, r)
     w = 2 * np.pi * np.arange(W.n_obs // 2 + 1) / (W.n_obs * W.dt_obs)
     for j, m in enumerate(sel):
         th = np.arccos(x[m, 2] / np.linalg.norm(x[m]))
@@ -115,3 +122,50 @@ def test_large_workload_shape_against_oracle():
         print(f"pixel {m}: FP64 max rel {err64:.2e} (bound {tol64:.1e}), mixed band L2 {errm:.2e}")
         assert err64 <= tol64
         assert errm <= 1e-4
+
+
+def test_precision_workload_shape_per_harmonic():
+    """Mixed forward on all 16384 pixels of the precision workload (gamma = 200, a0 = 1, 2^18
+    grid at 16 samples per first-harmonic period), compared on eight sampled pixels with the
+    FP64 oracle and the GPU FP64 path: FP64 within the arrival-time rounding bound, mixed
+    within 1e-4 band-L2 in each harmonic band [(h - 0.3) w1, (h + 0.1) w1], h = 1..5, that
+    holds a share of the pixel's energy above the FP32 floor (see below)."""
+    from paper_2206_03015_amd import lw
+    W, init_np = centre_cut("precision", 16)
+    L = W.laser
+    x = inputs.pixel_positions(W.n_side, W.theta_max, W.D)
+    args = (W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
+    init = T(init_np)
+    Em, dm = lw.deposit_td_boris(init, *args, T(x), W.t0, W.dt_obs, W.n_obs, prec="mixed")
+    sel = np.array([0, 2000, 5000, 8127, 8256, 8300, 12000, 16383])
+    Sm = lw.spectrum_fft(Em[T(sel)].contiguous(), W.dt_obs, "mixed").double().cpu().numpy()
+    del Em
+    E64, d64 = lw.deposit_td_boris(init, *args, T(x[sel]), W.t0, W.dt_obs, W.n_obs, prec="fp64")
+    S64 = lw.spectrum_fft(E64, W.dt_obs, "fp64").cpu().numpy()
+    r, b, bd = oracle.boris(init_np, *args)
+    Eo, do = oracle.deposit_td(W.t_start, W.dt, r, b, bd, x[sel], W.t0, W.dt_obs, W.n_obs)
+    So = oracle.spectrum(Eo, W.dt_obs)
+    assert d64.tolist() == list(do)
+    assert int(dm[3]) > 0
+    tol64 = fp64_bound(W, r)
+    w = 2 * np.pi * np.arange(W.n_obs // 2 + 1) / (W.n_obs * W.dt_obs)
+    checked = 0
+    for j, m in enumerate(sel):
+        err64 = np.max(np.abs(S64[j] - So[j])) / np.max(So[j])
+        assert err64 <= tol64, (m, err64, tol64)
+        th = np.arccos(x[m, 2] / np.linalg.norm(x[m]))
+        w1 = W.omega1(th)
+        total = np.sum(So[j])
+        line = []
+        for h in range(1, 6):
+            band = (w >= (h - 0.3) * w1) & (w <= (h + 0.1) * w1)
+            ref = np.linalg.norm(So[j][band])
+            share = np.sum(So[j][band]) / total
+            errm = np.linalg.norm(Sm[j][band] - So[j][band]) / ref
+            errm64 = np.linalg.norm(Sm[j][band] - S64[j][band]) / np.linalg.norm(S64[j][band])
+            line.append(f"h{h} share {share:.1e} err {errm:.1e}/{errm64:.1e}")
+            if share >= 1e-3:
+                assert errm <= 1e-4, (m, h, share, errm)
+                checked += 1
+        print(f"pixel {m}: FP64 max rel {err64:.2e} (bound {tol64:.1e}); " + "; ".join(line))
+    assert checked >= len(sel)
