@@ -105,7 +105,7 @@ typedef struct {
     const double *x_det;  /* [n_pix][3] m, |x_m| > 0                       */
     double t0;            /* s, relative to |x_m|/c                        */
     double dt_obs;        /* s, > 0                                        */
-    int64_t n_obs;        /* >= 1; power of two >= 4 for lw_spectrum_fft   */
+    int64_t n_obs;        /* 1 <= n_obs < 2^31; power of two >= 4 for FFTs */
 } lw_grid_t;
 
 /* which-argument of lw_workspace_bytes */

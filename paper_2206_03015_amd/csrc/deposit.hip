@@ -281,36 +281,48 @@ struct Wave {
             const int64_t k = k0 + (int64_t)(kl >> kPixBits);
             const int ml = ml0;
             const int64_t m = tile * kTilePix + ml;
-            const bool ser = series(k);
-            const double ta = tau_any(g, ser, k, (int64_t)i - 1);
-            const double tb = tau_any(g, ser, k, (int64_t)i);
+            // both samples of the interval, each value loaded once (all loads issued first)
+            const size_t sa = ((size_t)k * sh.n_samples + i - 1) * 3;
+            const double *ra = r + sa, *ba = beta + sa, *da = beta_dot + sa;
+            const double rax = ra[0], ray = ra[1], raz = ra[2], rbx = ra[3], rby = ra[4], rbz = ra[5];
+            const double bax = ba[0], bay = ba[1], baz = ba[2], bbx = ba[3], bby = ba[4], bbz = ba[5];
+            const double dax = da[0], day = da[1], daz = da[2], dbx = da[3], dby = da[4], dbz = da[5];
+            const double ala = alpha[i - 1], alb = alpha[i];
             const double q = charge ? charge[k] : -kQe;
-            const size_t sa = ((size_t)k * sh.n_samples + i - 1) * 3, sb = sa + 3;
             const double *xm = x_det + 3 * m;
+            // arrival times in the form and operation order of the scan (same bits)
+            double ta, tb;
+            if (series(k)) {
+                ta = arrival_tau<GEOM, kSer>(g, ala, rax, ray, raz, sq3(rax, ray, raz), sh.inv_cdt);
+                tb = arrival_tau<GEOM, kSer>(g, alb, rbx, rby, rbz, sq3(rbx, rby, rbz), sh.inv_cdt);
+            } else {
+                ta = arrival_tau<GEOM, kTauSqrt>(g, ala, rax, ray, raz, sq3(rax, ray, raz), sh.inv_cdt);
+                tb = arrival_tau<GEOM, kTauSqrt>(g, alb, rbx, rby, rbz, sq3(rbx, rby, rbz), sh.inv_cdt);
+            }
             T eax, eay, eaz, ebx, eby, ebz;
-            lw_field<T, GEOM>(g, xm, r[sa], r[sa + 1], r[sa + 2], beta[sa], beta[sa + 1], beta[sa + 2],
-                              beta_dot[sa], beta_dot[sa + 1], beta_dot[sa + 2], q, sh.fmask, eax, eay, eaz);
-            lw_field<T, GEOM>(g, xm, r[sb], r[sb + 1], r[sb + 2], beta[sb], beta[sb + 1], beta[sb + 2],
-                              beta_dot[sb], beta_dot[sb + 1], beta_dot[sb + 2], q, sh.fmask, ebx, eby, ebz);
+            lw_field<T, GEOM>(g, xm, rax, ray, raz, bax, bay, baz, dax, day, daz, q, sh.fmask, eax, eay, eaz);
+            lw_field<T, GEOM>(g, xm, rbx, rby, rbz, bbx, bby, bbz, dbx, dby, dbz, q, sh.fmask, ebx, eby, ebz);
+            // grid indices fit in 32 bits (n_obs < 2^31, checked on the host)
             const double nob = (double)sh.n_obs;
-            const int64_t u0 = grid_count(ta, nob), u1 = grid_count(tb, nob);
+            const int u0 = (int)fmin(fmax(floor(ta) + 1.0, 0.0), nob);
+            const int u1 = (int)fmin(fmax(floor(tb) + 1.0, 0.0), nob);
             // interpolation weight w = (u - ta)/(tb - ta), in the precision of the trace
             const T idt = sizeof(T) == 4 ? (T)__builtin_amdgcn_rcpf((float)(tb - ta)) : (T)(1.0 / (tb - ta));
             constexpr int NL = WcLine<T>::N;
             const int seg = wcb[ml];
-            for (int64_t u = u0; u < u1; ++u) {
+            for (int u = u0; u < u1; ++u) {
                 const T w = (T)((double)u - ta) * idt, w1 = (T)1 - w;
                 const T vx = w1 * eax + w * ebx, vy = w1 * eay + w * eby, vz = w1 * eaz + w * ebz;
                 if (u / NL == seg) {
-                    T *line = wc + ml * WcLine<T>::P + (int)(u % NL);
+                    T *line = wc + ml * WcLine<T>::P + (u % NL);
                     lds_add(line, vx);
                     lds_add(line + NL, vy);
                     lds_add(line + 2 * NL, vz);
                 } else {
-                    T *Em = E + (size_t)m * 3 * sh.n_obs;
-                    atomic_add(Em + u, vx);
-                    atomic_add(Em + sh.n_obs + u, vy);
-                    atomic_add(Em + 2 * sh.n_obs + u, vz);
+                    T *Em = E + (size_t)m * 3 * sh.n_obs + u;
+                    atomic_add(Em, vx);
+                    atomic_add(Em + sh.n_obs, vy);
+                    atomic_add(Em + 2 * sh.n_obs, vz);
                 }
             }
             if (u1 > u0) atomicMax(want + ml, (uint32_t)(u1 / NL) + 1u);
@@ -334,15 +346,15 @@ struct Wave {
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
-        qh = qwrap(qh + cnt);
-        qn -= cnt;
+        qh = __builtin_amdgcn_readfirstlane(qwrap(qh + cnt));
+        qn = __builtin_amdgcn_readfirstlane(qn - cnt);
     }
 
     // Append the lanes with `hit` set (callers drain before 2 x kTilePix more can arrive).
     __device__ __forceinline__ void push(bool hit, uint64_t mask, uint32_t i, uint32_t tag)
     {
         if (hit) q[qwrap(qh + qn + lanes_below(mask))] = make_uint2(i, tag);
-        qn += (uint32_t)__popcll(mask);
+        qn = __builtin_amdgcn_readfirstlane(qn + (uint32_t)__popcll(mask));  // wavefront-uniform
     }
 
     __device__ __forceinline__ void pump()
@@ -603,6 +615,7 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
     const int64_t n_p = t->n_particles, ns = t->n_samples, n_pix = gr->n_pix, n_obs = gr->n_obs;
     const size_t trace_elems = (size_t)n_pix * 3 * (size_t)n_obs;
     const bool f64 = prec == LW_PREC_FP64;
+    if (n_obs > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: n_obs must be below 2^31");
     if (!accumulate) {
         if (trace_elems) {
             const int blocks = (int)std::min<size_t>((trace_elems + 255) / 256, 65536);

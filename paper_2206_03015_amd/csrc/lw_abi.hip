@@ -69,7 +69,7 @@ lw_status check_grid(const lw_grid_t *g, const char *fn, bool need_grid)
     if (!(g->t0 > -1e300 && g->t0 < 1e300)) return fail(LW_E_ARG, "%s: t0 must be finite", fn);
     if (need_grid) {
         if (!finite_pos(g->dt_obs)) return fail(LW_E_ARG, "%s: dt_obs must be positive and finite", fn);
-        if (g->n_obs < 1 || g->n_obs > (int64_t(1) << 40)) return fail(LW_E_SHAPE, "%s: n_obs out of range", fn);
+        if (g->n_obs < 1 || g->n_obs > 0x7fffffff) return fail(LW_E_SHAPE, "%s: n_obs out of range [1, 2^31)", fn);
     }
     return LW_OK;
 }

@@ -16,6 +16,7 @@ constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kMe = 9.1093837015e-31;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kCoulomb = 1.0 / (4.0 * kPi * kEps0);
+constexpr double kInvC = 1.0 / kC;
 
 // error reporting (thread-local message, see lw_last_error)
 void set_error(const char *fmt, ...);
@@ -28,16 +29,19 @@ inline bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintp
 // Pixel geometry, shared by the arrival-time and field evaluations.
 // 1/sqrt(x) for positive normal x to double precision: the hardware estimate refined by two
 // Newton steps y <- y (3 - x y^2)/2 (each squares the relative error).
-__device__ __forceinline__ double rsqrt_fp64(double x)
+// rsqrt_nr<1> (one step) is used where the result feeds single-precision fields only.
+template <int STEPS>
+__device__ __forceinline__ double rsqrt_nr(double x)
 {
     double y = __builtin_amdgcn_rsq(x);
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < STEPS; ++it) {
         const double e = fma(-x * y, y, 1.0);
         y = fma(0.5 * y, e, y);
     }
     return y;
 }
+__device__ __forceinline__ double rsqrt_fp64(double x) { return rsqrt_nr<2>(x); }
 
 struct PixGeo {
     double nx, ny, nz;  // unit direction x_m / |x_m|
@@ -113,10 +117,13 @@ __device__ __forceinline__ void lw_field(const PixGeo &g, const double *xm, doub
                                          double bx, double by, double bz, double ax, double ay, double az, double q,
                                          int fmask, T &Ex, T &Ey, T &Ez, double *kappa_out = nullptr)
 {
+    // single-precision fields need one Newton step of the reciprocal square roots (relative
+    // error ~1e-13, far below float rounding of n - beta and kappa); double fields take two
+    constexpr int kNR = sizeof(T) == 4 ? 1 : 2;
     double nx, ny, nz, iR;
     if (GEOM == LW_GEOM_EXACT) {
         double dx = xm[0] - rx, dy = xm[1] - ry, dz = xm[2] - rz;
-        iR = rsqrt_fp64(dx * dx + dy * dy + dz * dz);
+        iR = rsqrt_nr<kNR>(dx * dx + dy * dy + dz * dz);
         nx = dx * iR;
         ny = dy * iR;
         nz = dz * iR;
@@ -131,19 +138,29 @@ __device__ __forceinline__ void lw_field(const PixGeo &g, const double *xm, doub
     if (b2 > 0.0) {
         // 1 - n.b = (1 - |b|) + |b| |n - b/|b||^2 / 2 for a unit n, with no cancellation of
         // the O(1/gamma^2) result against O(1) terms
-        const double ib = rsqrt_fp64(b2), bn = b2 * ib;
+        const double ib = rsqrt_nr<kNR>(b2), bn = b2 * ib;
         double dx = nx - bx * ib, dy = ny - by * ib, dz = nz - bz * ib;
         kappa = (1.0 - bn) + 0.5 * bn * (dx * dx + dy * dy + dz * dz);
     }
     if (kappa_out) *kappa_out = kappa;
-    const double ik = 1.0 / kappa;
-    const double pk = q * kCoulomb * ik * ik * ik;  // q/(4 pi eps0 kappa^3)
+    T pk;  // q/(4 pi eps0 kappa^3)
+    if constexpr (sizeof(T) == 4) {
+        // kappa is exact to double rounding here; its reciprocal in float: hardware estimate
+        // and one Newton step (~1 ulp)
+        const float kf = (float)kappa;
+        float ikf = __builtin_amdgcn_rcpf(kf);
+        ikf = fmaf(fmaf(-kf, ikf, 1.0f), ikf, ikf);
+        pk = (float)(q * kCoulomb) * (ikf * ikf * ikf);
+    } else {
+        const double ik = 1.0 / kappa;
+        pk = q * kCoulomb * ik * ik * ik;
+    }
     T tnx = (T)nx, tny = (T)ny, tnz = (T)nz;
     // n - beta in double: n_z - beta_z ~ 1/(2 gamma^2) would lose most of its bits in float
     T mx = (T)(nx - bx), my = (T)(ny - by), mz = (T)(nz - bz);
     Ex = Ey = Ez = (T)0;
     if (fmask & LW_FIELD_VELOCITY) {
-        T f = (T)(pk * (1.0 - b2) * iR * iR);
+        T f = pk * (T)((1.0 - b2) * iR * iR);
         Ex += f * mx;
         Ey += f * my;
         Ez += f * mz;
@@ -153,7 +170,7 @@ __device__ __forceinline__ void lw_field(const PixGeo &g, const double *xm, doub
         // w = (n - b) x bd ; v = n x w
         T wx = my * taz - mz * tay, wy = mz * tax - mx * taz, wz = mx * tay - my * tax;
         T vx = tny * wz - tnz * wy, vy = tnz * wx - tnx * wz, vz = tnx * wy - tny * wx;
-        T f = (T)(pk * iR / kC);
+        T f = pk * (T)(iR * kInvC);
         Ex += f * vx;
         Ey += f * vy;
         Ez += f * vz;
