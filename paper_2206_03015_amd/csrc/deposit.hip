@@ -46,6 +46,9 @@ struct WcLine {
     static constexpr int P = 3 * N + 1;        // LDS stride per pixel (odd: no bank conflicts)
 };
 constexpr uint32_t kWantNone = 0u;  // below every request (segment + 1)
+// queue entry tag: (particle - first particle of the group) << kPixBits | pixel in tile, and this
+// bit when the particle's arrival times take the series form
+constexpr uint32_t kSerBit = 1u << 31;
 constexpr int kStage = 6;  // doubles per staged sample: alpha, x, y, z, |r|^2, pad
 constexpr int kTargetWaves = 16384;
 // (|r|/|x|)^2 up to which the series form of the exact-geometry arrival time is used
@@ -278,7 +281,7 @@ struct Wave {
         }
         if (act) {
             const uint32_t i = e.x, kl = e.y;
-            const int64_t k = k0 + (int64_t)(kl >> kPixBits);
+            const int64_t k = k0 + (int64_t)((kl & ~kSerBit) >> kPixBits);
             const int ml = ml0;
             const int64_t m = tile * kTilePix + ml;
             // both samples of the interval, each value loaded once (all loads issued first)
@@ -292,7 +295,7 @@ struct Wave {
             const double *xm = x_det + 3 * m;
             // arrival times in the form and operation order of the scan (same bits)
             double ta, tb;
-            if (series(k)) {
+            if (kl & kSerBit) {
                 ta = arrival_tau<GEOM, kSer>(g, ala, rax, ray, raz, sq3(rax, ray, raz), sh.inv_cdt);
                 tb = arrival_tau<GEOM, kSer>(g, alb, rbx, rby, rbz, sq3(rbx, rby, rbz), sh.inv_cdt);
             } else {
@@ -372,7 +375,7 @@ struct Wave {
         const int64_t ns = sh.n_samples;
         const double nob = (double)sh.n_obs;
         const double *s0 = r + (size_t)k * ns * 3;
-        const uint32_t tag0 = ((uint32_t)(k - k0) << kPixBits) | (uint32_t)lane;
+        const uint32_t tag0 = ((uint32_t)(k - k0) << kPixBits) | (uint32_t)lane | (FORM == kTauSqrt ? 0u : kSerBit);
         double pa, px, py, pz, prr;
         // unconditional (clamped) loads, so that they stay in flight until the next chunk
         auto fetch = [&](int64_t c0) {
@@ -462,7 +465,7 @@ struct Wave {
         const double q = charge ? charge[k] : -kQe;
         bool prev_ok = false;
         double tprev = 0.0;
-        const uint32_t tag = ((uint32_t)(k - k0) << kPixBits) | (uint32_t)(lane + 64 * h);
+        const uint32_t tag = ((uint32_t)(k - k0) << kPixBits) | (uint32_t)(lane + 64 * h) | (ser ? kSerBit : 0u);
         for (int64_t i = 0; i < ns; ++i) {
             const size_t s = (size_t)k * ns + i;
             bool ok = lane_ok && sample_usable(r + 3 * s, beta + 3 * s, beta_dot + 3 * s);
@@ -616,6 +619,25 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
     const size_t trace_elems = (size_t)n_pix * 3 * (size_t)n_obs;
     const bool f64 = prec == LW_PREC_FP64;
     if (n_obs > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: n_obs must be below 2^31");
+    DepShape sh;
+    sh.n_particles = n_p;
+    sh.n_samples = ns;
+    sh.n_pix = n_pix;
+    sh.n_obs = n_obs;
+    sh.n_tiles = (n_pix + kTilePix - 1) / kTilePix;
+    sh.n_tile_blocks = (sh.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    int64_t groups = std::max<int64_t>(1, (kTargetWaves + std::max<int64_t>(sh.n_tiles, 1) - 1) /
+                                              std::max<int64_t>(sh.n_tiles, 1));
+    groups = std::max<int64_t>(1, std::min<int64_t>(groups, n_p));
+    sh.parts_per_group = std::max<int64_t>(1, (n_p + groups - 1) / groups);
+    sh.n_groups = (n_p + sh.parts_per_group - 1) / sh.parts_per_group;
+    sh.fmask = fmask;
+    const int64_t chunks = (ns + kPrepassChunk - 1) / kPrepassChunk;
+    const int64_t blocks = (sh.n_groups + 7) / 8 * 8 * sh.n_tile_blocks;
+    if (sh.parts_per_group >= (int64_t(1) << (31 - kPixBits)))
+        return fail(LW_E_SHAPE, "lw_deposit_td: too many particles per pixel tile group");
+    if (n_p > 0x7fffffff || chunks > 65535) return fail(LW_E_SHAPE, "lw_deposit_td: too many samples");
+    if (blocks > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: problem too large for one launch");
     if (!accumulate) {
         if (trace_elems) {
             const int blocks = (int)std::min<size_t>((trace_elems + 255) / 256, 65536);
@@ -629,32 +651,15 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
     if (n_p == 0 || n_pix == 0 || ns == 0) return check_launch("deposit fill");
     const DepWs w = carve(ws, n_p, ns);
     const double inv_cdt = 1.0 / (kC * gr->dt_obs);
+    sh.inv_cdt = inv_cdt;
     const int fill_blocks = (int)std::min<int64_t>((n_p + 255) / 256, 65536);
     k_fill<int><<<fill_blocks, 256, 0, s>>>(w.pflag, n_p);
     k_fill<unsigned long long><<<fill_blocks, 256, 0, s>>>(w.rmax2, n_p);
     {
-        const int64_t chunks = (ns + kPrepassChunk - 1) / kPrepassChunk;
-        if (n_p > 0x7fffffff || chunks > 65535) return fail(LW_E_SHAPE, "lw_deposit_td: too many samples");
         k_prepass<<<dim3((unsigned)n_p, (unsigned)chunks), 256, 0, s>>>(
             t->r, t->beta, t->beta_dot, ns, t->t_start, t->dt, gr->t0, gr->dt_obs, inv_cdt, w.alpha, w.pflag,
             w.rmax2);
     }
-    DepShape sh;
-    sh.n_particles = n_p;
-    sh.n_samples = ns;
-    sh.n_pix = n_pix;
-    sh.n_obs = n_obs;
-    sh.n_tiles = (n_pix + kTilePix - 1) / kTilePix;
-    sh.n_tile_blocks = (sh.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    int64_t groups = std::max<int64_t>(1, (kTargetWaves + sh.n_tiles - 1) / sh.n_tiles);
-    groups = std::min<int64_t>(groups, n_p);
-    sh.parts_per_group = (n_p + groups - 1) / groups;
-    sh.n_groups = (n_p + sh.parts_per_group - 1) / sh.parts_per_group;
-    sh.inv_cdt = inv_cdt;
-    sh.fmask = fmask;
-    const int64_t group_slots = (sh.n_groups + 7) / 8 * 8;
-    const int64_t blocks = group_slots * sh.n_tile_blocks;
-    if (blocks > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: problem too large for one launch");
     unsigned long long *dg = (unsigned long long *)diag;
     const dim3 grid((unsigned)blocks), block(kBlockThreads);
 #define LW_DEPOSIT_LAUNCH(T, G)                                                                                     \
