@@ -39,7 +39,6 @@ PEAK_HBM_GBS = 8000.0
 CUS, CLOCK_GHZ, LANES = 256, 2.4, 64
 PEAK_F32_TFLOPS = 157.3  # vector FP32 (256 CUs x 2.4 GHz x 128 lanes x 2 flops, packed)
 PEAK_F64_TFLOPS = 78.6   # vector FP64
-PEAK_VALU_TOPS = CUS * LANES * CLOCK_GHZ * 1e9 / 1e12  # lane-ops/s (one FP64 FMA = one lane-op)
 # Algorithmic work of one (particle, sample, pixel) evaluation in mixed precision: the field
 # formula with its 1/kappa^3 factors in FP32 (68 flops) and the arrival time in FP64 (6 flops).
 # The roofline time of one evaluation is F32/P32 + F64/P64; the "peak" below is the flop rate
@@ -50,6 +49,7 @@ EVAL_ROOF_S = EVAL_F32_FLOPS / (PEAK_F32_TFLOPS * 1e12) + EVAL_F64_FLOPS / (PEAK
 PEAK_EVAL_TFLOPS = EVAL_FLOPS / EVAL_ROOF_S / 1e12
 DEPOSIT_SOURCES = ("paper_2206_03015_amd/csrc/deposit.hip", "paper_2206_03015_amd/csrc/lw_internal.h")
 TRAFFIC_SUMMARY = "profiles/k_deposit_bunch_mixed_exact_hbm_traffic.md"
+VALU_SUMMARY = "profiles/k_deposit_bunch_mixed_exact_valu.md"
 
 
 def parse():
@@ -183,19 +183,21 @@ def main():
     # evaluation (EVAL_FLOPS) x evaluations per launch / average launch time (HIP events on the
     # stream the library launches on).  The kernel itself evaluates the field only at the ends
     # of intervals that deposit, so it does less work than it is credited with; its own count
-    # of lane operations is reported beside it.
+    # count of VALU instructions (rocprofv3 SQ_INSTS_VALU, committed summary) is reported beside
+    # it as the share of the VALU issue slots it fills (one wavefront instruction occupies a
+    # SIMD for 4 clocks).
     dep_s = mixed["deposit_ms"] / 1e3
     achieved = triples * EVAL_FLOPS / dep_s / 1e12
-    ops_triple = 17 if args.geom == "exact" else 4
-    hits = mixed["diag"][3]
-    lane_ops = triples * ops_triple + hits * 132
+    profiled = args.geom == "exact" and args.particles is None  # the configuration of the summaries
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_EVAL_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_EVAL_TFLOPS, "traffic": deposit_traffic(),
+            "frac": achieved / PEAK_EVAL_TFLOPS, "traffic": deposit_traffic() if profiled else None,
             "kernel": "k_deposit (lw_deposit_td: pre-pass + fill + deposit)",
             "flops_per_eval": {"f32": EVAL_F32_FLOPS, "f64": EVAL_F64_FLOPS},
-            "evals_per_launch": triples,
-            "executed_lane_ops_per_s": lane_ops / dep_s,
-            "executed_frac_of_valu_issue": lane_ops / dep_s / (PEAK_VALU_TOPS * 1e12)}
+            "evals_per_launch": triples}
+    valu = deposit_valu_insts() if profiled else None
+    if valu is not None:
+        roof["executed_valu_insts_per_launch"] = valu
+        roof["valu_issue_frac"] = valu * 4 / (CUS * 4 * CLOCK_GHZ * 1e9 * dep_s)
     fft_bytes = n_pix * (3 * n_obs + n_obs // 2 + 1) * 4
     fft_gbs = fft_bytes / (mixed["fft_ms"] / 1e3) / 1e9
 
@@ -306,10 +308,10 @@ def _deposit_source_hash():
     return h.hexdigest()
 
 
-def deposit_traffic():
-    """HBM bytes per deposit launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
-    or None when the deposit sources changed since those counters were taken."""
-    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+def _profile_figures(path):
+    """The "- key: `value`" figures of a committed rocprofv3 summary, or None when the deposit
+    sources changed since its counters were taken."""
+    path = os.path.join(ROOT, path)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -320,8 +322,24 @@ def deposit_traffic():
                 vals[k.strip()] = v.strip().strip("`")
     if vals.get("source_sha256") != _deposit_source_hash():
         return None
+    return vals
+
+
+def deposit_traffic():
+    """HBM bytes per deposit launch from the committed FETCH_SIZE / WRITE_SIZE summary."""
+    vals = _profile_figures(TRAFFIC_SUMMARY)
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["hbm_bytes_per_launch"]) if vals else None
+    except (KeyError, ValueError):
+        return None
+
+
+def deposit_valu_insts():
+    """Executed VALU instructions (wavefront level) per deposit launch from the committed
+    SQ_INSTS_VALU summary."""
+    vals = _profile_figures(VALU_SUMMARY)
+    try:
+        return float(vals["valu_insts_per_launch"]) if vals else None
     except (KeyError, ValueError):
         return None
 
