@@ -44,6 +44,9 @@ PEAK_F64_TFLOPS = 78.6   # vector FP64
 # The roofline time of one evaluation is F32/P32 + F64/P64; the "peak" below is the flop rate
 # at which both units would be saturated in that proportion.
 EVAL_F32_FLOPS, EVAL_F64_FLOPS = 68, 6
+# Direct FD: ~18 FP32 flops per (particle, sample, pixel, frequency) term (phase, sin/cos,
+# three complex multiply-accumulates)
+FD_TERM_FLOPS = 18
 EVAL_FLOPS = EVAL_F32_FLOPS + EVAL_F64_FLOPS
 EVAL_ROOF_S = EVAL_F32_FLOPS / (PEAK_F32_TFLOPS * 1e12) + EVAL_F64_FLOPS / (PEAK_F64_TFLOPS * 1e12)
 PEAK_EVAL_TFLOPS = EVAL_FLOPS / EVAL_ROOF_S / 1e12
@@ -64,6 +67,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-grad", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--cost-model", action="store_true",
+                   help="instead of the headline step: refit the wall-clock model constants C1_t, C2_t, C_w "
+                        "by single-variate sweeps and time the TD/FD crossover in the particle count")
     p.add_argument("--copy-calibration-gib", type=float, default=0.0,
                    help="run a plain device copy of this many GiB first (scale for HBM byte counters)")
     return p.parse_args()
@@ -84,6 +90,9 @@ def main():
 
     lw.load()
     dev = torch.device("cuda:0")
+    if args.cost_model:
+        print(json.dumps(cost_model(torch, dev)), flush=True)
+        return 0
     W = inputs.workload("bunch")
     if args.particles:
         W = W.scaled(n_p=args.particles)
@@ -227,8 +236,11 @@ def main():
         terms = W.n_p * W.n_samples * n_fd_pix * n_w
         fd_per_pix_bin = fd_ms / (n_fd_pix * n_w)
         td_per_pix_bin = mixed["ms_per_step"] / (n_pix * (n_obs // 2 + 1))
+        fd_tflops = terms * FD_TERM_FLOPS / (fd_ms / 1e3) / 1e12
         fd = {"pixels": n_fd_pix, "n_omega": n_w, "ms": fd_ms, "terms_per_s": terms / (fd_ms / 1e3),
-              "td_speedup_per_pixel_bin": fd_per_pix_bin / td_per_pix_bin}
+              "td_speedup_per_pixel_bin": fd_per_pix_bin / td_per_pix_bin,
+              "roofline": {"bound": "alu", "achieved": fd_tflops, "peak": PEAK_F32_TFLOPS, "unit": "TFLOP/s",
+                           "frac": fd_tflops / PEAK_F32_TFLOPS, "flops_per_term": FD_TERM_FLOPS}}
         log(f"[bench] direct FD {n_fd_pix} pix x {n_w} w: {fd_ms:.1f} ms")
 
     # ---- gradient of the band objective on the differentiation workload (FP64 forward + adjoint)
@@ -263,6 +275,158 @@ def main():
     rec.update(out)
     print(json.dumps(rec), flush=True)
     return 0
+
+
+def fit_leading_constant(sweeps):
+    """The paper's fit of a wall-clock model t = C * x (x: the product of the sizes): one
+    least-squares constant per single-variate sweep, C = sum(x t)/sum(x^2), then their mean.
+    sweeps: {name: [(x, t), ...]}.  Returns (C, {name: C_name})."""
+    per = {}
+    for name, pts in sweeps.items():
+        x = np.array([p[0] for p in pts], dtype=float)
+        t = np.array([p[1] for p in pts], dtype=float)
+        per[name] = float(np.dot(x, t) / np.dot(x, x))
+    return float(np.mean(list(per.values()))), per
+
+
+def crossover(n_p, t_td, t_fd):
+    """Smallest particle count from which the time-domain method is faster than the
+    frequency-domain one for every larger count measured (None if it never is)."""
+    n_p, t_td, t_fd = (np.asarray(v, dtype=float) for v in (n_p, t_td, t_fd))
+    order = np.argsort(n_p)
+    n_p, faster = n_p[order], (t_td < t_fd)[order]
+    for i in range(len(n_p)):
+        if faster[i:].all():
+            return float(n_p[i])
+    return None
+
+
+def _timed(torch, fn, reps=5, warmup=2):
+    """Median wall time (s) of fn() on the current stream, HIP events around each call."""
+    for _ in range(warmup):
+        fn()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    return float(np.median(ts))
+
+
+def cost_model(torch, dev):
+    """GPU refit of the wall-clock model of Sec. "Performance" (time-domain W1_t = C1_t N_s N_p
+    N_obs and W2_t = C2_t N_obs N_Tu log2 N_Tu, frequency-domain W_w = C_w N_s N_p N_obs N_w)
+    by single-variate sweeps around a base point sized for the GPU, and the TD/FD crossover
+    experiment (100 um uniform bunch, 5 periods of a 1 um plane wave, N_s = 100, one observer,
+    N_Tu = 2^20, N_w = 100).  Mixed precision, exact geometry, acceleration field."""
+    from paper_2206_03015_amd import inputs, lw
+    out = {"metric": "wall-clock model constants (s per unit of the model)", "prec": "mixed", "geom": "exact"}
+    base = inputs.workload("bunch")
+    L = base.laser
+
+    def bunch(n_p, n_steps, n_side):
+        W = base.scaled(n_p=n_p, n_steps=n_steps, n_side=n_side)
+        init = torch.as_tensor(inputs.bunch_init(W), device=dev)
+        r, b, bd = lw.trajectory_boris(init, W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
+        x = torch.as_tensor(inputs.pixel_positions(W.n_side, W.theta_max, W.D), device=dev)
+        return W, r, b, bd, x
+
+    # ---- W1_t: deposit time; base 1000 particles x 20001 samples x 32 x 32 pixels, 2^18 grid
+    sw1 = {"N_s": [], "N_p": [], "N_obs": []}
+    pts = [("N_s", 1000, s_, 32) for s_ in (5000, 10000, 20000, 40000)] + \
+          [("N_p", p_, 20000, 32) for p_ in (250, 500, 1000, 2000)] + \
+          [("N_obs", 1000, 20000, n_) for n_ in (16, 23, 32, 45)]
+    for name, n_p, n_steps, n_side in pts:
+        W, r, b, bd, x = bunch(n_p, n_steps, n_side)
+        E = torch.empty((W.n_pix, 3, W.n_obs), dtype=torch.float32, device=dev)
+        ws = torch.empty(lw.workspace_bytes(lw.WS_DEPOSIT, W.n_p, W.n_samples, "mixed"), dtype=torch.uint8,
+                         device=dev)
+        t = _timed(torch, lambda: lw.deposit_td(r, b, bd, W.t_start, W.dt, x, W.t0, W.dt_obs, W.n_obs,
+                                               prec="mixed", out=E, ws=ws))
+        sw1[name].append((W.n_samples * W.n_p * W.n_pix, t))
+        log(f"[cost] W1 {name}: N_s={W.n_samples} N_p={W.n_p} N_obs={W.n_pix}: {t * 1e3:.2f} ms")
+        del E, ws, r, b, bd
+    c1, c1_per = fit_leading_constant(sw1)
+
+    # ---- W2_t: FFT time; base 1024 pixels x 2^18 points
+    sw2 = {"N_obs": [], "N_Tu": []}
+    for name, n_pix, lg in [("N_obs", n_, 18) for n_ in (256, 512, 1024, 2048)] + \
+                           [("N_Tu", 1024, lg_) for lg_ in (16, 17, 18, 19, 20)]:
+        n_obs = 1 << lg
+        E = torch.randn((n_pix, 3, n_obs), dtype=torch.float32, device=dev)
+        S = torch.empty((n_pix, n_obs // 2 + 1), dtype=torch.float32, device=dev)
+        ws = torch.empty(lw.workspace_bytes(lw.WS_FFT, n_pix, n_obs, "mixed"), dtype=torch.uint8, device=dev)
+        t = _timed(torch, lambda: lw.spectrum_fft(E, 1e-20, "mixed", out=S, ws=ws))
+        sw2[name].append((n_pix * n_obs * math.log2(n_obs), t))
+        log(f"[cost] W2 {name}: N_obs={n_pix} N_Tu=2^{lg}: {t * 1e3:.3f} ms")
+        del E, S, ws
+    c2, c2_per = fit_leading_constant(sw2)
+
+    # ---- W_w: direct FD time; base 100 particles x 2001 samples x 8 pixels x 1024 frequencies
+    sww = {"N_s": [], "N_p": [], "N_obs": [], "N_w": []}
+    pts = [("N_s", 100, s_, 8, 1024) for s_ in (1000, 2000, 4000, 8000)] + \
+          [("N_p", p_, 2000, 8, 1024) for p_ in (50, 100, 200, 400)] + \
+          [("N_obs", 100, 2000, n_, 1024) for n_ in (4, 8, 16, 32)] + \
+          [("N_w", 100, 2000, 8, w_) for w_ in (256, 512, 1024, 2048)]
+    for name, n_p, n_steps, n_pix, n_w in pts:
+        W, r, b, bd, x = bunch(n_p, n_steps, 8)
+        xs = x[:n_pix].contiguous()
+        w1 = W.omega1()
+        omega = torch.as_tensor(np.linspace(0.7 * w1, 1.1 * w1, n_w), device=dev)
+        ws = torch.empty(lw.workspace_bytes(lw.WS_DIRECT_FD, n_pix, n_w, "mixed"), dtype=torch.uint8, device=dev)
+        Sfd = torch.empty((n_pix, n_w), dtype=torch.float64, device=dev)
+        t = _timed(torch, lambda: lw.direct_fd(r, b, bd, W.t_start, W.dt, xs, W.t0, omega, prec="mixed",
+                                              out=Sfd, ws=ws))
+        sww[name].append((W.n_samples * W.n_p * n_pix * n_w, t))
+        log(f"[cost] Ww {name}: N_s={W.n_samples} N_p={W.n_p} N_obs={n_pix} N_w={n_w}: {t * 1e3:.3f} ms")
+        del ws, Sfd, r, b, bd
+    cw, cw_per = fit_leading_constant(sww)
+    out["constants"] = {"C1_t": c1, "C2_t": c2, "C_w": cw, "log": "log2",
+                        "per_sweep": {"C1_t": c1_per, "C2_t": c2_per, "C_w": cw_per},
+                        "paper_cpu_serial": {"C1_t": 1.02e-7, "C2_t": 8.61e-9, "C_w": 1.17e-7}}
+
+    # ---- crossover: 100 um uniform line bunch, 5 periods of a 1 um plane wave, N_s = 100
+    gamma, a0, n_cycles, lb = 5.0, 0.5, 5.0, 100e-6
+    n_steps, n_obs, n_w = 100, 1 << 20, 100
+    t_sim = (lb + n_cycles * L.lam) / (2.0 * inputs.C_LIGHT)
+    t_start, dt = -0.5 * t_sim, t_sim / n_steps
+    x1 = torch.as_tensor(np.array([[0.0, 0.0, base.D]]), device=dev)
+    rows = []
+    for n_p in (1, 2, 5, 10, 20, 40, 80, 160, 320, 640, 1280, 2560, 5120):
+        init = torch.as_tensor(inputs.uniform_line_init(n_p, lb, gamma, t_start), device=dev)
+        r, b, bd = lw.trajectory_boris(init, n_steps + 1, t_start, dt, a0, L.lam, 0.0, n_cycles)
+        # observer window: the whole arrival-time span on axis, N_Tu points
+        span = (t_sim * (1.0 + a0 * a0 / 2.0) / (4 * gamma * gamma) + lb / inputs.C_LIGHT)
+        dt_obs = 1.2 * span / n_obs
+        t0 = -0.6 * span
+        E = torch.empty((1, 3, n_obs), dtype=torch.float32, device=dev)
+        S = torch.empty((1, n_obs // 2 + 1), dtype=torch.float32, device=dev)
+        ws_d = torch.empty(lw.workspace_bytes(lw.WS_DEPOSIT, n_p, n_steps + 1, "mixed"), dtype=torch.uint8,
+                           device=dev)
+        ws_f = torch.empty(lw.workspace_bytes(lw.WS_FFT, 1, n_obs, "mixed"), dtype=torch.uint8, device=dev)
+        w1 = 4 * gamma ** 2 * 2 * np.pi * inputs.C_LIGHT / L.lam / (1 + a0 * a0 / 2)
+        omega = torch.as_tensor(np.linspace(0.5 * w1, 1.5 * w1, n_w), device=dev)
+        ws_w = torch.empty(lw.workspace_bytes(lw.WS_DIRECT_FD, 1, n_w, "mixed"), dtype=torch.uint8, device=dev)
+        Sfd = torch.empty((1, n_w), dtype=torch.float64, device=dev)
+
+        def td():
+            lw.deposit_td(r, b, bd, t_start, dt, x1, t0, dt_obs, n_obs, prec="mixed", out=E, ws=ws_d)
+            lw.spectrum_fft(E, dt_obs, "mixed", out=S, ws=ws_f)
+
+        def fd():
+            lw.direct_fd(r, b, bd, t_start, dt, x1, t0, omega, prec="mixed", out=Sfd, ws=ws_w)
+
+        t_td, t_fd = _timed(torch, td, reps=21), _timed(torch, fd, reps=21)
+        rows.append((n_p, t_td, t_fd))
+        log(f"[cost] crossover N_p={n_p}: TD {t_td * 1e6:.1f} us, FD {t_fd * 1e6:.1f} us")
+    out["crossover"] = {"setup": "100 um uniform line bunch, gamma 5, plane wave a0 0.5, 5 periods of 1 um, "
+                                 "N_s 100, one on-axis observer, TD N_Tu 2^20, FD N_w 100",
+                        "n_p": [x[0] for x in rows], "td_s": [x[1] for x in rows], "fd_s": [x[2] for x in rows],
+                        "td_faster_from_n_p": crossover(*zip(*rows)), "paper_cpu_serial_td_faster_from_n_p": 41}
+    return out
 
 
 def grad_leg(torch, dev):

@@ -49,6 +49,8 @@ constexpr uint32_t kWantNone = 0u;  // below every request (segment + 1)
 // queue entry tag: (particle - first particle of the group) << kPixBits | pixel in tile, and this
 // bit when the particle's arrival times take the series form
 constexpr uint32_t kSerBit = 1u << 31;
+// intervals with more grid points than this are deposited by the whole wavefront
+constexpr int kLongRun = 8;
 constexpr int kStage = 6;  // doubles per staged sample: alpha, x, y, z, |r|^2, pad
 constexpr int kTargetWaves = 16384;
 // (|r|/|x|)^2 up to which the series form of the exact-geometry arrival time is used
@@ -83,6 +85,20 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
+
+// value of lane src (wavefront-uniform src) of a double / float / double register
+__device__ __forceinline__ double readlane_double(double v, int src)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, src);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), src);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ float readlane_t(float v, int src)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double readlane_t(double v, int src) { return readlane_double(v, src); }
 
 __device__ __forceinline__ double uniform_double(double v)
 {
@@ -279,6 +295,11 @@ struct Wave {
             g.invD = pick(gl[0].invD, gl[kPPL - 1].invD);
             g.ok = true;
         }
+        // the entry's interval: arrival times, fields at both ends and grid points [u0, u1)
+        double ta = 0.0;
+        int u0 = 0, u1 = 0;
+        T idt = (T)0, eax = (T)0, eay = (T)0, eaz = (T)0, ebx = (T)0, eby = (T)0, ebz = (T)0;
+        constexpr int NL = WcLine<T>::N;
         if (act) {
             const uint32_t i = e.x, kl = e.y;
             const int64_t k = k0 + (int64_t)((kl & ~kSerBit) >> kPixBits);
@@ -294,7 +315,7 @@ struct Wave {
             const double q = charge ? charge[k] : -kQe;
             const double *xm = x_det + 3 * m;
             // arrival times in the form and operation order of the scan (same bits)
-            double ta, tb;
+            double tb;
             if (kl & kSerBit) {
                 ta = arrival_tau<GEOM, kSer>(g, ala, rax, ray, raz, sq3(rax, ray, raz), sh.inv_cdt);
                 tb = arrival_tau<GEOM, kSer>(g, alb, rbx, rby, rbz, sq3(rbx, rby, rbz), sh.inv_cdt);
@@ -302,33 +323,53 @@ struct Wave {
                 ta = arrival_tau<GEOM, kTauSqrt>(g, ala, rax, ray, raz, sq3(rax, ray, raz), sh.inv_cdt);
                 tb = arrival_tau<GEOM, kTauSqrt>(g, alb, rbx, rby, rbz, sq3(rbx, rby, rbz), sh.inv_cdt);
             }
-            T eax, eay, eaz, ebx, eby, ebz;
             lw_field<T, GEOM>(g, xm, rax, ray, raz, bax, bay, baz, dax, day, daz, q, sh.fmask, eax, eay, eaz);
             lw_field<T, GEOM>(g, xm, rbx, rby, rbz, bbx, bby, bbz, dbx, dby, dbz, q, sh.fmask, ebx, eby, ebz);
             // grid indices fit in 32 bits (n_obs < 2^31, checked on the host)
             const double nob = (double)sh.n_obs;
-            const int u0 = (int)fmin(fmax(floor(ta) + 1.0, 0.0), nob);
-            const int u1 = (int)fmin(fmax(floor(tb) + 1.0, 0.0), nob);
+            u0 = (int)fmin(fmax(floor(ta) + 1.0, 0.0), nob);
+            u1 = (int)fmin(fmax(floor(tb) + 1.0, 0.0), nob);
             // interpolation weight w = (u - ta)/(tb - ta), in the precision of the trace
-            const T idt = sizeof(T) == 4 ? (T)__builtin_amdgcn_rcpf((float)(tb - ta)) : (T)(1.0 / (tb - ta));
-            constexpr int NL = WcLine<T>::N;
-            const int seg = wcb[ml];
-            for (int u = u0; u < u1; ++u) {
-                const T w = (T)((double)u - ta) * idt, w1 = (T)1 - w;
-                const T vx = w1 * eax + w * ebx, vy = w1 * eay + w * eby, vz = w1 * eaz + w * ebz;
-                if (u / NL == seg) {
-                    T *line = wc + ml * WcLine<T>::P + (u % NL);
-                    lds_add(line, vx);
-                    lds_add(line + NL, vy);
-                    lds_add(line + 2 * NL, vz);
-                } else {
-                    T *Em = E + (size_t)m * 3 * sh.n_obs + u;
-                    atomic_add(Em, vx);
-                    atomic_add(Em + sh.n_obs, vy);
-                    atomic_add(Em + 2 * sh.n_obs, vz);
+            idt = sizeof(T) == 4 ? (T)__builtin_amdgcn_rcpf((float)(tb - ta)) : (T)(1.0 / (tb - ta));
+            if (u1 - u0 <= kLongRun) {
+                const int seg = wcb[ml];
+                for (int u = u0; u < u1; ++u) {
+                    const T w = (T)((double)u - ta) * idt, w1 = (T)1 - w;
+                    const T vx = w1 * eax + w * ebx, vy = w1 * eay + w * eby, vz = w1 * eaz + w * ebz;
+                    if (u / NL == seg) {
+                        T *line = wc + ml * WcLine<T>::P + (u % NL);
+                        lds_add(line, vx);
+                        lds_add(line + NL, vy);
+                        lds_add(line + 2 * NL, vz);
+                    } else {
+                        T *Em = E + (size_t)m * 3 * sh.n_obs + u;
+                        atomic_add(Em, vx);
+                        atomic_add(Em + sh.n_obs, vy);
+                        atomic_add(Em + 2 * sh.n_obs, vz);
+                    }
                 }
             }
             if (u1 > u0) atomicMax(want + ml, (uint32_t)(u1 / NL) + 1u);
+        }
+        // intervals holding many grid points (a grid much finer than the sample spacing): the
+        // whole wavefront deposits them one at a time, 64 consecutive grid points per pass
+        uint64_t longm = __ballot(act && u1 - u0 > kLongRun);
+        while (longm) {
+            const int src = (int)__builtin_ctzll(longm);
+            longm &= longm - 1;
+            const double sta = readlane_double(ta, src);
+            const int su0 = __builtin_amdgcn_readlane(u0, src), su1 = __builtin_amdgcn_readlane(u1, src);
+            const int sml = __builtin_amdgcn_readlane(ml0, src);
+            const T sidt = readlane_t(idt, src);
+            const T sax = readlane_t(eax, src), say = readlane_t(eay, src), saz = readlane_t(eaz, src);
+            const T sbx = readlane_t(ebx, src), sby = readlane_t(eby, src), sbz = readlane_t(ebz, src);
+            T *Em = E + (size_t)(tile * kTilePix + sml) * 3 * sh.n_obs;
+            for (int u = su0 + lane; u < su1; u += 64) {
+                const T w = (T)((double)u - sta) * sidt, w1 = (T)1 - w;
+                atomic_add(Em + u, w1 * sax + w * sbx);
+                atomic_add(Em + sh.n_obs + u, w1 * say + w * sby);
+                atomic_add(Em + 2 * sh.n_obs + u, w1 * saz + w * sbz);
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();

@@ -163,6 +163,19 @@ def bunch_init(w: Workload, n_p: int | None = None, gamma=None) -> np.ndarray:
     return np.ascontiguousarray(init[:n])
 
 
+def uniform_line_init(n_p: int, length: float, gamma: float, t_start: float) -> np.ndarray:
+    """Initial phase space [n_p][6] of a line bunch: n_p electrons evenly spaced over ``length``
+    along z (cell centres, centred on z = 0 at t = 0), on axis, all with Lorentz factor gamma
+    along +z, moved back ballistically to t_start (the crossover setting of Sec. "Performance")."""
+    uz = np.sqrt(gamma * gamma - 1.0)
+    bz = uz / gamma
+    z = -0.5 * length + (np.arange(n_p) + 0.5) * (length / n_p) + bz * C_LIGHT * t_start
+    init = np.zeros((n_p, 6))
+    init[:, 2] = z
+    init[:, 5] = uz
+    return init
+
+
 def bunch_init_dgamma(w: Workload, rows=None) -> np.ndarray:
     """d(init)/d(gamma_mean) of ``bunch_init`` [len(rows)][6] (rows: indices into the full draw,
     default all), exact to rounding by a complex step h = 1e-30 through the recipe."""

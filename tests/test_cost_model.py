@@ -1,0 +1,43 @@
+"""Host logic of the wall-clock model refit in bench.py (no GPU): the single-variate fits of
+Sec. "Performance" recover a known leading constant, and the crossover finder."""
+import os
+import sys
+
+import numpy as np
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+
+
+def test_fit_recovers_constant_of_exact_data():
+    C = 3.7e-13
+    sweeps = {"a": [(x, C * x) for x in (1e9, 2e9, 4e9)], "b": [(x, C * x) for x in (5e8, 3e9)]}
+    c, per = bench.fit_leading_constant(sweeps)
+    assert abs(c - C) <= 1e-15 * C * 10
+    assert set(per) == {"a", "b"}
+
+
+def test_fit_is_least_squares_per_sweep_then_mean():
+    # sweep a: t = 2x except one point off; least squares through the origin by hand
+    a = [(1.0, 2.0), (2.0, 4.0), (3.0, 7.0)]
+    b = [(1.0, 1.0), (2.0, 2.0)]
+    c, per = bench.fit_leading_constant({"a": a, "b": b})
+    ca = (1 * 2 + 2 * 4 + 3 * 7) / (1 + 4 + 9)
+    assert per["a"] == ca and per["b"] == 1.0
+    assert c == (ca + 1.0) / 2
+
+
+def test_crossover():
+    n = [1, 2, 5, 10, 20]
+    assert bench.crossover(n, [5, 5, 5, 5, 5], [1, 2, 4, 8, 16]) == 10.0
+    assert bench.crossover(n, [5, 5, 5, 5, 5], [1, 1, 1, 1, 1]) is None
+    # a faster TD point below a slower one does not count
+    assert bench.crossover(n, [1, 5, 5, 5, 5], [2, 2, 6, 6, 6]) == 5.0
+
+
+def test_uniform_line_bunch():
+    from paper_2206_03015_amd import inputs
+    init = inputs.uniform_line_init(4, 100e-6, 5.0, 0.0)
+    assert np.allclose(init[:, 2], [-37.5e-6, -12.5e-6, 12.5e-6, 37.5e-6], rtol=0, atol=1e-18)
+    assert np.all(init[:, :2] == 0) and np.all(init[:, 3:5] == 0)
+    assert np.allclose(1.0 + init[:, 5] ** 2, 25.0, rtol=1e-15)

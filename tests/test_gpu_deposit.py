@@ -74,6 +74,27 @@ def test_synthetic_with_charges(prec):
     assert dg.tolist() == do.tolist()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_dense_grid_long_intervals(prec):
+    """Observer grids much finer than the sample spacing: ~21 grid points per interval
+    (synthetic, with charges, both fields) and ~50-60 (a small bunch at 4000 grid points per
+    first-harmonic period).  Intervals with more than eight grid points are deposited by the
+    whole wavefront, the rest lane by lane."""
+    c = synthetic(n_p=5, n_samples=100, n_pix=70, n_obs=6000, seed=5)
+    Eo, do = run_oracle(c, "exact", 3, charge=c["charge"])
+    assert do[3] > 20 * 5 * 99 * 70
+    Eg, dg = run_gpu(c, prec, "exact", 3, charge=c["charge"])
+    assert_close(Eg, Eo, prec)
+    assert dg.tolist() == do.tolist()
+    c = small_bunch(n_p=8, n_steps=600, n_side=3, n_obs=1 << 14, samples_per_period=4000.0)
+    for geom in ("exact", "farfield"):
+        Eo, do = run_oracle(c, geom)
+        assert do[3] > 100000
+        Eg, dg = run_gpu(c, prec, geom)
+        assert_close(Eg, Eo, prec)
+        assert dg.tolist() == do.tolist()
+
+
 def test_unusable_samples_and_nonmonotone_take_the_careful_path():
     c = synthetic(n_p=4, seed=3)
     c["r"] = c["r"].copy()
