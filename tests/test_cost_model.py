@@ -1,5 +1,6 @@
-"""Host logic of the wall-clock model refit in bench.py (no GPU): the single-variate fits of
-Sec. "Performance" recover a known leading constant, and the crossover finder."""
+"""Host logic of bench.py's experiment modes (no GPU): the single-variate fits of Sec.
+"Performance" recover a known leading constant, the crossover finder, the line bunch of the
+crossover setting, and the error measure of Eq. spectra_error."""
 import os
 import sys
 
@@ -41,3 +42,10 @@ def test_uniform_line_bunch():
     assert np.allclose(init[:, 2], [-37.5e-6, -12.5e-6, 12.5e-6, 37.5e-6], rtol=0, atol=1e-18)
     assert np.all(init[:, :2] == 0) and np.all(init[:, 3:5] == 0)
     assert np.allclose(1.0 + init[:, 5] ** 2, 25.0, rtol=1e-15)
+
+
+def test_spectra_error():
+    S_ref = np.array([[1.0, 4.0], [2.0, 0.0]])
+    S = np.array([[1.5, 4.0], [2.0, 1.0]])
+    mx, mean = bench.spectra_error(S, S_ref)
+    assert mx == 0.25 and mean == (0.125 + 0.25) / 4
