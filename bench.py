@@ -66,6 +66,7 @@ def parse():
     p.add_argument("--no-fd", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-grad", action="store_true")
+    p.add_argument("--no-cull", action="store_true", help="skip the culled-variant leg")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--cost-model", action="store_true",
                    help="instead of the headline step: refit the wall-clock model constants C1_t, C2_t, C_w "
@@ -134,7 +135,7 @@ def main():
         diag = torch.zeros(4, dtype=torch.int64, device=dev)
         return E, S, ws_d, ws_f, diag
 
-    def run(prec, steps, warmup):
+    def run(prec, steps, warmup, cull=False):
         E, S, ws_d, ws_f, diag = buffers(prec)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         dep_ms, fft_ms = [], []
@@ -144,7 +145,7 @@ def main():
                 t_start = time.time()
             ev[0].record()
             lw.deposit_td(r, b, bd, W.t_start, W.dt, x_det, W.t0, W.dt_obs, n_obs, prec=prec, geom=args.geom,
-                          out=E, diag=diag, ws=ws_d)
+                          out=E, diag=diag, ws=ws_d, cull=cull)
             ev[1].record()
             lw.spectrum_fft(E, W.dt_obs, prec, out=S, ws=ws_f)
             ev[2].record()
@@ -152,7 +153,8 @@ def main():
                 torch.cuda.synchronize()
                 dep_ms.append(ev[0].elapsed_time(ev[1]))
                 fft_ms.append(ev[1].elapsed_time(ev[2]))
-                log(f"[bench] {prec} step {it - warmup}: deposit {dep_ms[-1]:.1f} ms, fft {fft_ms[-1]:.1f} ms")
+                log(f"[bench] {prec}{' culled' if cull else ''} step {it - warmup}: deposit {dep_ms[-1]:.1f} ms, "
+                    f"fft {fft_ms[-1]:.1f} ms")
         torch.cuda.synchronize()
         wall = (time.time() - t_start) / steps * 1e3
         return dict(ms_per_step=wall, deposit_ms=float(np.mean(dep_ms)), fft_ms=float(np.mean(fft_ms)),
@@ -191,6 +193,17 @@ def main():
         out["mixed_vs_fp64_band_l2_err"] = ({"max": float(errs.max()), "median": float(np.median(errs)),
                                             "pixels": int(errs.size)} if errs.size else None)
         del S64
+    if not args.no_cull:
+        # culled variant (LW_CULL): particles whose arrivals miss a wavefront's window are
+        # skipped after two arrival-time evaluations; same spectra, reported separately
+        cul = run("mixed", max(1, min(args.steps, 2)), 1, cull=True)
+        cul.pop("E")
+        S_c = cul.pop("S")
+        diff = float(torch.max(torch.abs(S_c - S_mixed)) / torch.max(torch.abs(S_mixed)))
+        out["culled"] = {"ms_per_step": cul["ms_per_step"], "deposit_ms": cul["deposit_ms"],
+                         "fft_ms": cul["fft_ms"], "evals_per_s": triples / (cul["ms_per_step"] / 1e3),
+                         "diag_equal": cul["diag"] == mixed["diag"], "max_rel_diff_vs_full": diff}
+        del S_c
     del S_mixed
     torch.cuda.empty_cache()
 

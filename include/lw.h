@@ -66,6 +66,13 @@ typedef enum {
  * diag) instead of overwriting them (for particle-chunked calls). */
 #define LW_ACCUMULATE (1 << 8)
 
+/* flag OR-ed into the geometry argument of lw_deposit_td: skip every particle whose
+ * arrival times at a wavefront's pixels hold no observer grid point (tested on the
+ * first and last sample where the arrival times are provably increasing; particles
+ * that take the careful path are never skipped).  E and diag are exactly those of the
+ * full evaluation; only the work changes.  Not set in the headline measurement. */
+#define LW_CULL (1 << 9)
+
 /* trajectory source */
 #define LW_TRAJ_SAMPLES 0 /* stored samples r, beta, beta_dot                  */
 #define LW_TRAJ_BORIS 1   /* FP64 Boris push from init + laser (lw_trajectory_boris) */
@@ -160,7 +167,7 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec);
  *             rounding), to first order in MIXED mode (relative error of the
  *             correction <= 1.25e-8); other particles use the square-root form.
  * field_mask: LW_FIELD_ACCEL and/or LW_FIELD_VELOCITY (non-zero).
- * geom:       LW_GEOM_EXACT or LW_GEOM_FARFIELD, optionally | LW_ACCUMULATE.
+ * geom:       LW_GEOM_EXACT or LW_GEOM_FARFIELD, optionally | LW_ACCUMULATE, | LW_CULL.
  * E:          [n_pix][3][n_obs] float or double, overwritten (or accumulated).
  * diag:       NULL or int64[4]: {skipped non-monotone intervals, skipped
  *             intervals touching an unusable sample, grid points of deposited

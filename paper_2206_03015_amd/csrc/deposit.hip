@@ -495,6 +495,37 @@ struct Wave {
         }
     }
 
+    // Culling (LW_CULL, fast-path particles only): arrival times are strictly increasing, so the
+    // particle deposits into this wavefront's pixels only if some pixel has a window grid point
+    // in (tau_first, tau_last].  If none has, the counters follow from the two end points and
+    // the particle is skipped; the results are those of the full scan.
+    template <int FORM>
+    __device__ bool outside(const PixGeo *g, const bool *lane_ok, const bool *pix_in, int64_t k,
+                            unsigned long long &c1, unsigned long long &c2)
+    {
+        const int64_t ns = sh.n_samples;
+        const double nob = (double)sh.n_obs;
+        const double *p0 = r + (size_t)k * ns * 3, *p1 = p0 + (size_t)(ns - 1) * 3;
+        const double a0 = alpha[0], a1 = alpha[ns - 1];
+        double tf[kPPL], tl[kPPL];
+        bool in = false;
+#pragma unroll
+        for (int h = 0; h < kPPL; ++h) {
+            tf[h] = arrival_tau<GEOM, FORM>(g[h], a0, p0[0], p0[1], p0[2], sq3(p0[0], p0[1], p0[2]), sh.inv_cdt);
+            tl[h] = arrival_tau<GEOM, FORM>(g[h], a1, p1[0], p1[1], p1[2], sq3(p1[0], p1[1], p1[2]), sh.inv_cdt);
+            in |= lane_ok[h] && grid_count(tl[h], nob) > grid_count(tf[h], nob);
+        }
+        if (__ballot(in)) return false;
+#pragma unroll
+        for (int h = 0; h < kPPL; ++h) {
+            if (lane_ok[h])
+                c2 += (unsigned long long)(int64_t)(floor(tl[h]) - floor(tf[h]));
+            else if (pix_in[h])
+                c1 += (unsigned long long)(ns - 1);
+        }
+        return true;
+    }
+
     // Careful path: the skip rules of lw_deposit_td interval by interval.
     __device__ void careful_particle(const PixGeo &g, bool lane_ok, bool pix_in, int64_t m, int h, int64_t k,
                                      unsigned long long &c0, unsigned long long &c1, unsigned long long &c2,
@@ -543,7 +574,7 @@ struct Wave {
     }
 };
 
-template <typename T, int GEOM>
+template <typename T, int GEOM, bool CULL>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_deposit(const double *__restrict__ r, const double *__restrict__ beta,
                                                  const double *__restrict__ beta_dot,
                                                  const double *__restrict__ charge, const double *__restrict__ x_det,
@@ -622,10 +653,13 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     unsigned long long c0 = 0, c1 = 0, c2 = 0, c3 = 0;
     for (int64_t k = wave_live ? k0 : k1; k < k1; ++k) {
         if (pflag[k] == 0) {
-            if (GEOM == LW_GEOM_EXACT && w.series(k))
+            if (GEOM == LW_GEOM_EXACT && w.series(k)) {
+                if (CULL && w.template outside<Wave<T, GEOM>::kSer>(g, lane_ok, pix_in, k, c1, c2)) continue;
                 w.template fast_particle<Wave<T, GEOM>::kSer>(g, lane_ok, pix_in, k, c1, c2, c3);
-            else
+            } else {
+                if (CULL && w.template outside<kTauSqrt>(g, lane_ok, pix_in, k, c1, c2)) continue;
                 w.template fast_particle<kTauSqrt>(g, lane_ok, pix_in, k, c1, c2, c3);
+            }
         } else {
 #pragma unroll
             for (int h = 0; h < kPPL; ++h) w.careful_particle(g[h], lane_ok[h], pix_in[h], m[h], h, k, c0, c1, c2, c3);
@@ -657,6 +691,8 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
                          void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s)
 {
     const int64_t n_p = t->n_particles, ns = t->n_samples, n_pix = gr->n_pix, n_obs = gr->n_obs;
+    const bool cull = (geom & LW_CULL) != 0;
+    geom &= ~LW_CULL;
     const size_t trace_elems = (size_t)n_pix * 3 * (size_t)n_obs;
     const bool f64 = prec == LW_PREC_FP64;
     if (n_obs > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: n_obs must be below 2^31");
@@ -703,19 +739,22 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
     }
     unsigned long long *dg = (unsigned long long *)diag;
     const dim3 grid((unsigned)blocks), block(kBlockThreads);
-#define LW_DEPOSIT_LAUNCH(T, G)                                                                                     \
-    k_deposit<T, G><<<grid, block, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge, gr->x_det, w.alpha, w.pflag,       \
-                                           w.rmax2, (T *)E, dg, sh)
+#define LW_DEPOSIT_LAUNCH(T, G, C)                                                                                  \
+    k_deposit<T, G, C><<<grid, block, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge, gr->x_det, w.alpha, w.pflag,    \
+                                              w.rmax2, (T *)E, dg, sh)
+    // culling is a separate instantiation: the full evaluation carries none of its code
     if (f64) {
-        if (geom == LW_GEOM_EXACT)
-            LW_DEPOSIT_LAUNCH(double, LW_GEOM_EXACT);
-        else
-            LW_DEPOSIT_LAUNCH(double, LW_GEOM_FARFIELD);
+        if (geom == LW_GEOM_EXACT) {
+            if (cull) LW_DEPOSIT_LAUNCH(double, LW_GEOM_EXACT, true); else LW_DEPOSIT_LAUNCH(double, LW_GEOM_EXACT, false);
+        } else {
+            if (cull) LW_DEPOSIT_LAUNCH(double, LW_GEOM_FARFIELD, true); else LW_DEPOSIT_LAUNCH(double, LW_GEOM_FARFIELD, false);
+        }
     } else {
-        if (geom == LW_GEOM_EXACT)
-            LW_DEPOSIT_LAUNCH(float, LW_GEOM_EXACT);
-        else
-            LW_DEPOSIT_LAUNCH(float, LW_GEOM_FARFIELD);
+        if (geom == LW_GEOM_EXACT) {
+            if (cull) LW_DEPOSIT_LAUNCH(float, LW_GEOM_EXACT, true); else LW_DEPOSIT_LAUNCH(float, LW_GEOM_EXACT, false);
+        } else {
+            if (cull) LW_DEPOSIT_LAUNCH(float, LW_GEOM_FARFIELD, true); else LW_DEPOSIT_LAUNCH(float, LW_GEOM_FARFIELD, false);
+        }
     }
 #undef LW_DEPOSIT_LAUNCH
     return check_launch("lw_deposit_td");

@@ -139,8 +139,9 @@ lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, 
     if (field_mask <= 0 || (field_mask & ~(LW_FIELD_ACCEL | LW_FIELD_VELOCITY)))
         return fail(LW_E_ARG, "%s: field_mask must be a non-empty combination of LW_FIELD_*", fn);
     const bool acc = (geom & LW_ACCUMULATE) != 0;
-    const int g = geom & ~LW_ACCUMULATE;
+    const int g = geom & ~(LW_ACCUMULATE | LW_CULL);
     if (g != LW_GEOM_EXACT && g != LW_GEOM_FARFIELD) return fail(LW_E_ARG, "%s: unknown geometry %d", fn, g);
+    const int gc = g | (geom & LW_CULL);  // geometry and culling for the launchers
     if (grid->n_pix > 0 && !E) return fail(LW_E_ARG, "%s: E is NULL", fn);
     if (E && !aligned(E, 16)) return fail(LW_E_ALIGN, "%s: E must be 16-byte aligned", fn);
     if (diag && !aligned(diag, 8)) return fail(LW_E_ALIGN, "%s: diag must be 8-byte aligned", fn);
@@ -152,12 +153,12 @@ lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, 
         if (work && (!ws || boris_batch_fit(traj->n_particles, traj->n_samples, ws_bytes, 3) < 1))
             return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes holds no batch (one particle needs %zu)", fn,
                         ws_bytes, boris_stream_ws_bytes(1, traj->n_samples, 1, 3));
-        return launch_deposit_boris(traj, grid, prec, field_mask, g, acc, E, diag, ws, ws_bytes, stream);
+        return launch_deposit_boris(traj, grid, prec, field_mask, gc, acc, E, diag, ws, ws_bytes, stream);
     }
     const size_t need = deposit_ws_bytes(traj->n_particles, traj->n_samples);
     if (traj->n_particles > 0 && grid->n_pix > 0 && (!ws || ws_bytes < need))
         return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes < %zu needed", fn, ws_bytes, need);
-    return launch_deposit(traj, grid, prec, field_mask, g, acc, E, diag, ws, ws_bytes, stream);
+    return launch_deposit(traj, grid, prec, field_mask, gc, acc, E, diag, ws, ws_bytes, stream);
 }
 
 lw_status lw_spectrum_fft(const void *E, int64_t n_pix, int64_t n_obs, double dt_obs, int prec, void *S, void *ws,

@@ -21,6 +21,7 @@ FIELD_ACCEL = 1
 FIELD_VELOCITY = 2
 GEOM = {"exact": 0, "farfield": 1}
 ACCUMULATE = 1 << 8
+CULL = 1 << 9
 TRAJ_SAMPLES = 0
 TRAJ_BORIS = 1
 WS_DEPOSIT, WS_FFT, WS_DIRECT_FD, WS_DEPOSIT_BWD, WS_FFT_BWD, WS_DIRECT_FD_BWD = 1, 2, 3, 4, 5, 6
@@ -157,7 +158,7 @@ def make_grid(x_det, t0, dt_obs, n_obs):
 
 
 def deposit_td(r, beta, beta_dot, t_start, dt, x_det, t0, dt_obs, n_obs, prec="mixed", field_mask=FIELD_ACCEL,
-               geom="exact", charge=None, out=None, accumulate=False, diag=None, ws=None):
+               geom="exact", charge=None, out=None, accumulate=False, diag=None, ws=None, cull=False):
     """lw_deposit_td.  Returns (E [n_pix][3][n_obs], diag int64[4])."""
     lib = load()
     tr = make_traj(r, beta, beta_dot, t_start, dt, charge)
@@ -171,7 +172,7 @@ def deposit_td(r, beta, beta_dot, t_start, dt, x_det, t0, dt_obs, n_obs, prec="m
     need = workspace_bytes(WS_DEPOSIT, tr.n_particles, tr.n_samples, prec)
     if ws is None:
         ws = _workspace(need, r.device)
-    flags = GEOM[geom] | (ACCUMULATE if accumulate else 0)
+    flags = GEOM[geom] | (ACCUMULATE if accumulate else 0) | (CULL if cull else 0)
     _check(lib.lw_deposit_td(ctypes.byref(tr), ctypes.byref(gr), PREC[prec], int(field_mask), flags, _ptr(out),
                              _ptr(diag), _ptr(ws), ws.numel(), _stream()))
     return out, diag
@@ -314,7 +315,8 @@ def direct_fd_bwd(r, beta, beta_dot, t_start, dt, x_det, t0, omega, dS, field_ma
 
 
 def deposit_td_boris(init, n_samples, t_start, dt, a0, lam, w0, n_cycles, x_det, t0, dt_obs, n_obs, prec="mixed",
-                     field_mask=FIELD_ACCEL, geom="exact", charge=None, out=None, accumulate=False, diag=None, ws=None):
+                     field_mask=FIELD_ACCEL, geom="exact", charge=None, out=None, accumulate=False, diag=None, ws=None,
+                     cull=False):
     """lw_deposit_td with LW_TRAJ_BORIS: trajectories recomputed inside the call from init [n_p][6]
     in batches.  Returns (E, diag)."""
     lib = load()
@@ -333,7 +335,7 @@ def deposit_td_boris(init, n_samples, t_start, dt, a0, lam, w0, n_cycles, x_det,
         diag = torch.zeros(4, dtype=torch.int64, device=init.device)
     if ws is None:
         ws = _workspace(workspace_bytes(WS_DEPOSIT_BORIS, tr.n_particles, tr.n_samples, prec), init.device)
-    flags = GEOM[geom] | (ACCUMULATE if accumulate else 0)
+    flags = GEOM[geom] | (ACCUMULATE if accumulate else 0) | (CULL if cull else 0)
     _check(lib.lw_deposit_td(ctypes.byref(tr), ctypes.byref(gr), PREC[prec], int(field_mask), flags, _ptr(out),
                              _ptr(diag), _ptr(ws), ws.numel(), _stream()))
     return out, diag
