@@ -101,6 +101,13 @@ def test_host_validation_rejects_bad_arguments(lib):
     p = ctypes.c_void_p(256)
     tr.r = tr.beta = tr.beta_dot = p
     gr.x_det = p
+    # geometry flags: LW_ACCUMULATE and LW_CULL are accepted, other bits are not (checked
+    # before the NULL trace, which is reported next)
+    for flags in (lw.ACCUMULATE, lw.CULL, lw.CULL | lw.ACCUMULATE | lw.GEOM["farfield"]):
+        assert lib.lw_deposit_td(ctypes.byref(tr), ctypes.byref(gr), 0, 1, flags, None, None, None, 0, None) == -1
+        assert b"E is NULL" in lib.lw_last_error()
+    assert lib.lw_deposit_td(ctypes.byref(tr), ctypes.byref(gr), 0, 1, 1 << 10, None, None, None, 0, None) == -1
+    assert b"unknown geometry" in lib.lw_last_error()
     assert lib.lw_deposit_td_bwd(ctypes.byref(tr), ctypes.byref(gr), 1, 1, 0, p, p, p, p, None, 0, None) == -6
     assert lib.lw_direct_fd_bwd(ctypes.byref(tr), ctypes.byref(gr), p, 4, 1, 1, 0, p, p, p, p, None, 0, None) == -6
     assert lib.lw_direct_fd_bwd(ctypes.byref(tr), ctypes.byref(gr), p, 4, 0, 1, 0, p, p, p, p, None, 0, None) == -4
