@@ -7,7 +7,8 @@
 //     every lane reads each staged sample once (a broadcast) and uses it for each of its
 //     pixels: it forms the (particle, sample, pixel) arrival time in double and tests
 //     whether the interval (tau_{i-1}, tau_i] crosses the next grid point of that
-//     pixel's window.  The broadcast reads bound this loop (LDS returns 128 B per
+//     pixel's window (all four tests of a sample pair first, then one branch into the
+//     crossing logic if any holds).  The broadcast reads bound this loop (LDS returns 128 B per
 //     clock), so kPPL pixels per lane divide their cost by kPPL;
 //   * a crossing appends (particle, sample, pixel) to a per-wavefront queue in LDS;
 //     whenever 64 entries are queued, all lanes take one entry each, evaluate the
@@ -451,20 +452,26 @@ struct Wave {
                 }
                 j = 1;
             }
-            auto step = [&](int jj, const double *e) {
+            // queue the crossings of the arrival times tv of sample jj
+            auto hits = [&](int jj, const double *tv) {
 #pragma unroll
                 for (int h = 0; h < kPPL; ++h) {
-                    tau[h] = arrival_tau<GEOM, FORM>(g[h], e[0], e[1], e[2], e[3], e[4], sh.inv_cdt);
-                    const bool hit = tau[h] >= gnext[h];
+                    const bool hit = tv[h] >= gnext[h];
                     const uint64_t mask = __ballot(hit);
                     if (mask) {
                         if (hit) {
-                            const double f = floor(tau[h]) + 1.0;
+                            const double f = floor(tv[h]) + 1.0;
                             gnext[h] = f >= nob ? INFINITY : f;
                         }
                         push(hit, mask, (uint32_t)(c0 + jj), tag0 + 64u * (uint32_t)h);
                     }
                 }
+            };
+            auto step = [&](int jj, const double *e) {
+#pragma unroll
+                for (int h = 0; h < kPPL; ++h)
+                    tau[h] = arrival_tau<GEOM, FORM>(g[h], e[0], e[1], e[2], e[3], e[4], sh.inv_cdt);
+                hits(jj, tau);
             };
             for (; j + 1 < cnt; j += 2) {
                 double v[2][5];
@@ -472,9 +479,23 @@ struct Wave {
                 for (int u = 0; u < 2; ++u)
 #pragma unroll
                     for (int c = 0; c < 5; ++c) v[u][c] = stage[(j + u) * kStage + c];
-                step(j, v[0]);
-                step(j + 1, v[1]);
-                pump();
+                // every arrival time is evaluated; one test per pixel on the later sample of the
+                // pair (arrival times increase) decides whether the crossing logic runs
+                double t0v[kPPL], t1v[kPPL];
+                bool any = false;
+#pragma unroll
+                for (int h = 0; h < kPPL; ++h) {
+                    t0v[h] = arrival_tau<GEOM, FORM>(g[h], v[0][0], v[0][1], v[0][2], v[0][3], v[0][4], sh.inv_cdt);
+                    t1v[h] = arrival_tau<GEOM, FORM>(g[h], v[1][0], v[1][1], v[1][2], v[1][3], v[1][4], sh.inv_cdt);
+                    any |= (t0v[h] >= gnext[h]) | (t1v[h] >= gnext[h]);
+                }
+                if (__ballot(any)) {
+                    hits(j, t0v);
+                    hits(j + 1, t1v);
+                    pump();
+                }
+#pragma unroll
+                for (int h = 0; h < kPPL; ++h) tau[h] = t1v[h];
             }
             for (; j < cnt; ++j) {
                 step(j, stage + j * kStage);
