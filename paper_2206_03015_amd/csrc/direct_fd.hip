@@ -3,10 +3,14 @@
 // A wavefront owns one pixel and 64 frequencies (one per lane) and a group of
 // particles.  Per chunk of 64 samples every lane evaluates one sample (arrival time
 // and E*kappa, the integrand of Eq. const_phase_drop) into LDS; then every lane
-// sweeps the 64 staged samples for its own frequency.  The phase w*(t_a - t0) is
-// formed in double and reduced to one revolution before sin/cos, so the float sin/cos
-// of the mixed mode never sees a large argument.  Partial sums of the wavefront go
-// to a double workspace with atomics; a final kernel forms S = (dt^2/2pi) sum_c |F_c|^2.
+// sweeps the 64 staged samples for its own frequency.  FP64 mode forms the phase
+// w*(t_a - t0) in double per term and reduces it to one revolution before sin/cos.  Mixed
+// mode forms, per chunk and lane, the phase at a reference arrival time of the chunk in
+// double (reduced to one revolution) and adds nu*(t_a - t_ref) in float per term: the
+// offsets span a few revolutions at most, so the float phase keeps ~1e-8 of a
+// revolution and the hardware sin/cos (arguments in revolutions) never see a large
+// argument.  Partial sums of the wavefront go to a double workspace with atomics; a final
+// kernel forms S = (dt^2/2pi) sum_c |F_c|^2.
 #include "lw_internal.h"
 
 #include <algorithm>
@@ -15,6 +19,15 @@ namespace lw {
 namespace {
 
 constexpr int kWavesPerBlock = 4;
+
+// value of lane src (wavefront-uniform src) of a double register
+__device__ __forceinline__ double readlane_f64(double v, int src)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, src);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), src);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
 
 struct FdShape {
     int64_t n_particles, n_samples, n_pix, n_omega;
@@ -31,6 +44,7 @@ __global__ __launch_bounds__(256) void k_direct_fd(const double *__restrict__ r,
                                                    FdShape sh)
 {
     __shared__ double s_ta[kWavesPerBlock][64];
+    __shared__ float s_dtf[kWavesPerBlock][64];  // mixed: nu-free offsets t_a - t_ref (s)
     __shared__ T s_ek[kWavesPerBlock][3][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wv;
@@ -76,7 +90,16 @@ __global__ __launch_bounds__(256) void k_direct_fd(const double *__restrict__ r,
                         }
                     }
                 }
-                s_ta[wv][lane] = ta;
+                const bool live = ex != (T)0 || ey != (T)0 || ez != (T)0;
+                if constexpr (sizeof(T) == 4) {
+                    // reference arrival time: the first lane with a contribution
+                    const uint64_t lm = __ballot(live);
+                    const double tref = lm ? readlane_f64(ta, (int)__builtin_ctzll(lm)) : 0.0;
+                    s_dtf[wv][lane] = live ? (float)(ta - tref) : 0.0f;
+                    if (lane == 0) s_ta[wv][0] = tref;
+                } else {
+                    s_ta[wv][lane] = ta;
+                }
                 s_ek[wv][0][lane] = ex;
                 s_ek[wv][1][lane] = ey;
                 s_ek[wv][2][lane] = ez;
@@ -85,27 +108,36 @@ __global__ __launch_bounds__(256) void k_direct_fd(const double *__restrict__ r,
             __builtin_amdgcn_wave_barrier();
             const int cnt = (int)std::min<int64_t>(64, ns - i0);
             T b0 = 0, b1 = 0, b2 = 0, b3 = 0, b4 = 0, b5 = 0;
-            for (int j = 0; j < cnt; ++j) {
-                const double x = nu * s_ta[wv][j];
-                const double fr = x - floor(x);  // revolutions in [0, 1)
-                T c, sn;
-                if (sizeof(T) == 4) {
-                    const float f = (float)fr;
-                    c = (T)__builtin_amdgcn_cosf(f);
-                    sn = (T)__builtin_amdgcn_sinf(f);
-                } else {
+            if constexpr (sizeof(T) == 4) {
+                const double x = nu * s_ta[wv][0];
+                const float base = (float)(x - floor(x));  // revolutions in [0, 1)
+                const float nuf = (float)nu;
+                for (int j = 0; j < cnt; ++j) {
+                    const float ph = fmaf(nuf, s_dtf[wv][j], base);
+                    const float c = __builtin_amdgcn_cosf(ph), sn = __builtin_amdgcn_sinf(ph);
+                    const T e0 = s_ek[wv][0][j], e1 = s_ek[wv][1][j], e2 = s_ek[wv][2][j];
+                    b0 += e0 * c;
+                    b1 += e0 * sn;
+                    b2 += e1 * c;
+                    b3 += e1 * sn;
+                    b4 += e2 * c;
+                    b5 += e2 * sn;
+                }
+            } else {
+                for (int j = 0; j < cnt; ++j) {
+                    const double x = nu * s_ta[wv][j];
+                    const double fr = x - floor(x);  // revolutions in [0, 1)
                     double sd, cd;
                     sincospi(2.0 * fr, &sd, &cd);
-                    c = (T)cd;
-                    sn = (T)sd;
+                    const T c = (T)cd, sn = (T)sd;
+                    const T e0 = s_ek[wv][0][j], e1 = s_ek[wv][1][j], e2 = s_ek[wv][2][j];
+                    b0 += e0 * c;
+                    b1 += e0 * sn;
+                    b2 += e1 * c;
+                    b3 += e1 * sn;
+                    b4 += e2 * c;
+                    b5 += e2 * sn;
                 }
-                const T e0 = s_ek[wv][0][j], e1 = s_ek[wv][1][j], e2 = s_ek[wv][2][j];
-                b0 += e0 * c;
-                b1 += e0 * sn;
-                b2 += e1 * c;
-                b3 += e1 * sn;
-                b4 += e2 * c;
-                b5 += e2 * sn;
             }
             a0 += (double)b0;
             a1 += (double)b1;
