@@ -17,7 +17,8 @@
 // 256 bytes.  Sub-transforms run in place in one LDS buffer as Stockham passes of radix 16
 // (FP32) or 8 (FP64) whose butterflies each thread holds in registers between two
 // barriers; twiddles come from two 64-entry tables (W_4096^b and W_64^a).  For N <= N2 pass
-// B alone reads the traces.
+// B alone reads the traces.  Pass B writes the spectrum at a stride of N1 floats; all its
+// blocks of one pixel pair run on one XCD so that those partial lines merge in its L2.
 //
 // Adjoint path: N1 = 2^ceil(lg/2), N2 = 2^floor(lg/2), radix-4 Stockham passes between two
 // LDS buffers.
@@ -456,7 +457,7 @@ __device__ __forceinline__ void fft_inplace(T2 *buf, const Lay &lay, int lgL, in
 }
 
 struct FwdShape {
-    int64_t n_pix, pair0;
+    int64_t n_pix, pair0, nbatch;
     int lg, lg1, lg2, lgC;
 };
 
@@ -530,8 +531,22 @@ __global__ __launch_bounds__(kThrB) void k_fwd_rows(const typename C2<T>::type *
     const int tid = threadIdx.x;
     const int lg2 = sh.lg2, N2 = 1 << lg2, N1 = 1 << sh.lg1;
     const int64_t N = (int64_t)1 << sh.lg, half = N / 2;
-    const int rp = blockIdx.x;
-    const int64_t pl = blockIdx.y, p = sh.pair0 + pl;
+    // block -> (row pair, pixel pair): all row-pair blocks of one pixel pair run on one XCD
+    // (blocks go to the 8 XCDs round robin), so the partial lines of its spectrum, written
+    // at a stride of N1 floats, merge in that XCD's L2
+    int rp;
+    int64_t pl;
+    if (FROM_E) {
+        rp = 0;
+        pl = blockIdx.y;
+    } else {
+        const int64_t b = blockIdx.x, xcd = b & 7, slot = b >> 3;
+        const int nrp = N1 / 2 + 1;
+        rp = (int)(slot % nrp);
+        pl = (slot / nrp) * 8 + xcd;
+        if (pl >= sh.nbatch) return;  // padding block (whole block)
+    }
+    const int64_t p = sh.pair0 + pl;
     const int64_t m = 2 * p, m1 = 2 * p + 1;
     const bool has1 = m1 < sh.n_pix;
     const int ka = rp, kb = (N1 - rp) & (N1 - 1);
@@ -836,6 +851,7 @@ lw_status run_fft(const T *E, int64_t n_pix, int64_t n_obs, double dt_obs, T *S,
     using Cfg = FwdCfg<T>;
     FwdShape sh;
     sh.n_pix = n_pix;
+    sh.nbatch = 0;
     sh.lg = ilog2(n_obs);
     sh.lg2 = std::min(sh.lg, Cfg::kLgRow);
     sh.lg1 = sh.lg - sh.lg2;
@@ -859,7 +875,8 @@ lw_status run_fft(const T *E, int64_t n_pix, int64_t n_obs, double dt_obs, T *S,
         const int64_t nb = std::min(batch, pairs - p0);
         sh.pair0 = p0;
         k_fwd_cols<T><<<dim3(gx_a, 3, (unsigned)nb), kThrA, 0, s>>>(E, Y, sh);
-        k_fwd_rows<T, false><<<dim3(gx_b, (unsigned)nb, 1), kThrB, 0, s>>>(Y, nullptr, S, sh, sc);
+        sh.nbatch = nb;
+        k_fwd_rows<T, false><<<dim3((unsigned)((nb + 7) / 8 * 8 * gx_b), 1, 1), kThrB, 0, s>>>(Y, nullptr, S, sh, sc);
     }
     return check_launch("lw_spectrum_fft");
 }
