@@ -71,6 +71,9 @@ def parse():
     p.add_argument("--cost-model", action="store_true",
                    help="instead of the headline step: refit the wall-clock model constants C1_t, C2_t, C_w "
                         "by single-variate sweeps and time the TD/FD crossover in the particle count")
+    p.add_argument("--workload", default="bunch", choices=["bunch", "precision", "large"],
+                   help="bunch: the headline step; precision / large: one full-size pass of that "
+                        "configuration (trajectories recomputed inside the deposit), mixed against FP64")
     p.add_argument("--accuracy", action="store_true",
                    help="instead of the headline step: the single-electron accuracy experiment (Eq. "
                         "spectra_error of TD and FD against a converged FP64 FD reference)")
@@ -99,6 +102,9 @@ def main():
         return 0
     if args.accuracy:
         print(json.dumps(accuracy(torch, dev)), flush=True)
+        return 0
+    if args.workload != "bunch":
+        print(json.dumps(full_size(torch, dev, args.workload)), flush=True)
         return 0
     W = inputs.workload("bunch")
     if args.particles:
@@ -445,6 +451,62 @@ def cost_model(torch, dev):
                                  "N_s 100, one on-axis observer, TD N_Tu 2^20, FD N_w 100",
                         "n_p": [x[0] for x in rows], "td_s": [x[1] for x in rows], "fd_s": [x[2] for x in rows],
                         "td_faster_from_n_p": crossover(*zip(*rows)), "paper_cpu_serial_td_faster_from_n_p": 41}
+    return out
+
+
+def full_size(torch, dev, name):
+    """One full-size pass of the precision or large workload: deposit with the trajectories
+    recomputed batch by batch inside the call (LW_TRAJ_BORIS: 1e5 electrons x 2e4 steps would
+    need 144 GB stored), then FFT, in mixed precision and in FP64; the band-L2 error of mixed
+    against FP64 in the harmonic bands [(h - 0.3) w1, (h + 0.1) w1] of every pixel (h = 1..5 for
+    the precision workload, h = 1 otherwise).  Reports evaluations per second of each pass."""
+    from paper_2206_03015_amd import inputs, lw
+    W = inputs.workload(name)
+    L = W.laser
+    init = torch.as_tensor(inputs.bunch_init(W), device=dev)
+    x = torch.as_tensor(inputs.pixel_positions(W.n_side, W.theta_max, W.D), device=dev)
+    triples = W.n_p * W.n_samples * W.n_pix
+    args = (W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles, x, W.t0, W.dt_obs, W.n_obs)
+    out = {"workload": name, "n_particles": W.n_p, "n_samples": W.n_samples, "n_pix": W.n_pix, "n_obs": W.n_obs}
+    S = {}
+    for prec in ("mixed", "fp64"):
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        E, diag = lw.deposit_td_boris(init, *args, prec=prec)
+        e[1].record()
+        S[prec] = lw.spectrum_fft(E, W.dt_obs, prec)
+        e[2].record()
+        torch.cuda.synchronize()
+        dep_ms, fft_ms = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+        out[prec] = {"deposit_ms": dep_ms, "fft_ms": fft_ms, "evals_per_s": triples / (dep_ms / 1e3),
+                     "diag": diag.cpu().tolist()}
+        log(f"[{name}] {prec}: deposit {dep_ms:.0f} ms ({triples / dep_ms * 1e3:.3e} evals/s), fft {fft_ms:.1f} ms")
+        del E
+        torch.cuda.empty_cache()
+    tx, ty = inputs.pixel_angles(W.n_side, W.theta_max)
+    th = torch.as_tensor(np.hypot(tx, ty), device=dev)
+    w1 = torch.as_tensor(np.array([W.omega1(t) for t in np.hypot(tx, ty)]), device=dev)[:, None]
+    wgrid = torch.as_tensor(2 * np.pi * np.arange(W.n_obs // 2 + 1) / (W.n_obs * W.dt_obs), device=dev)
+    harmonics = range(1, 6) if name == "precision" else range(1, 2)
+    out["band_l2_err"] = {}
+    for h in harmonics:
+        errs = []
+        for m0 in range(0, W.n_pix, 512):
+            m1 = min(W.n_pix, m0 + 512)
+            band = (wgrid[None, :] >= (h - 0.3) * w1[m0:m1]) & (wgrid[None, :] <= (h + 0.1) * w1[m0:m1])
+            a = S["mixed"][m0:m1].double() * band
+            b = S["fp64"][m0:m1] * band
+            den = torch.linalg.vector_norm(b, dim=1)
+            ok = den > 0
+            errs.append((torch.linalg.vector_norm(a - b, dim=1)[ok] / den[ok]).cpu().numpy())
+        errs = np.concatenate(errs)
+        out["band_l2_err"][f"h{h}"] = {"max": float(errs.max()), "median": float(np.median(errs)),
+                                      "pixels": int(errs.size)}
+        log(f"[{name}] h={h}: band L2 mixed vs FP64 max {errs.max():.2e} median {np.median(errs):.2e} "
+            f"over {errs.size} pixels")
+    del th
+    out["mixed_vs_fp64_deposit_speedup"] = out["fp64"]["deposit_ms"] / out["mixed"]["deposit_ms"]
     return out
 
 
