@@ -507,7 +507,57 @@ def full_size(torch, dev, name):
             f"over {errs.size} pixels")
     del th
     out["mixed_vs_fp64_deposit_speedup"] = out["fp64"]["deposit_ms"] / out["mixed"]["deposit_ms"]
+    del S
+    torch.cuda.empty_cache()
+    if name == "large":
+        out["adjoint"] = full_size_adjoint(torch, dev, W, init)
     return out
+
+
+def full_size_adjoint(torch, dev, W, init):
+    """Adjoint of a band objective on the large workload at full size: J = sum over the central
+    8 x 8 pixels of the first-harmonic band energy (+-2 % of w1, reading of the differentiation
+    objective), dJ/d(init, a0) through the FFT adjoint, the deposit adjoint and the pusher's
+    tangents with the trajectories recomputed in the call (FP64), checked against a central
+    difference in a0 (step 1e-6 a0)."""
+    from paper_2206_03015_amd import inputs, lw
+    L = W.laser
+    cen = inputs.central_pixels(W.n_side, 8)
+    xc_np = inputs.pixel_positions(W.n_side, W.theta_max, W.D)[cen]
+    xc = torch.as_tensor(np.ascontiguousarray(xc_np), device=dev)
+    wts = torch.as_tensor(inputs.band_weights(W, xc_np), device=dev)
+
+    def objective(a0):
+        E, _ = lw.deposit_td_boris(init, W.n_samples, W.t_start, W.dt, a0, L.lam, L.w0, L.n_cycles, xc, W.t0,
+                                   W.dt_obs, W.n_obs, prec="fp64")
+        S = lw.spectrum_fft(E, W.dt_obs, "fp64")
+        return E, float(torch.sum(wts * S))
+
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record()
+    E, J = objective(L.a0)
+    e[1].record()
+    dE = lw.spectrum_fft_bwd(E, wts, W.dt_obs, "fp64")
+    e[2].record()
+    g_init, g_a0 = lw.deposit_td_bwd_boris(init, W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles, xc,
+                                           W.t0, W.dt_obs, W.n_obs, dE)
+    e[3].record()
+    torch.cuda.synchronize()
+    dj_da0 = float(torch.sum(g_a0))
+    del E, dE
+    h = 1e-6 * L.a0
+    _, Jp = objective(L.a0 + h)
+    _, Jm = objective(L.a0 - h)
+    fd = (Jp - Jm) / (2 * h)
+    rec = {"pixels": int(len(cen)), "J": J, "dJ_da0": dj_da0, "dJ_da0_central_difference": fd,
+           "rel_diff": abs(dj_da0 - fd) / abs(fd), "forward_ms": e[0].elapsed_time(e[1]),
+           "fft_bwd_ms": e[1].elapsed_time(e[2]), "deposit_boris_bwd_ms": e[2].elapsed_time(e[3]),
+           "grad_init_norm": float(torch.linalg.vector_norm(g_init))}
+    log(f"[large] adjoint on {len(cen)} pixels: forward {rec['forward_ms']:.0f} ms, FFT adjoint "
+        f"{rec['fft_bwd_ms']:.1f} ms, deposit+pusher adjoint {rec['deposit_boris_bwd_ms']:.0f} ms; dJ/da0 "
+        f"{dj_da0:.6e} vs central difference {fd:.6e} (rel {rec['rel_diff']:.1e})")
+    return rec
 
 
 def spectra_error(S, S_ref):

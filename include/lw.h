@@ -131,7 +131,7 @@ typedef struct {
  * (fft, fft_bwd, direct_fd, direct_fd_bwd); n_b = n_samples (deposit*), n_obs
  * (fft, fft_bwd), n_omega (direct_fd, direct_fd_bwd).  LW_WS_DEPOSIT_BORIS and
  * LW_WS_DEPOSIT_BWD_BORIS size the trajectory batches of LW_TRAJ_BORIS calls (at
- * most ~4 GiB by default; any workspace that holds one particle's batch is
+ * most ~16 GiB by default; any workspace that holds one particle's batch is
  * accepted and sets the batch size).  Returns 0 for
  * an unknown `which`.  Larger workspaces are accepted; for the FFT a larger
  * workspace lets more pixels be transformed per pass.

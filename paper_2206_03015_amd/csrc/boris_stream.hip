@@ -10,7 +10,10 @@
 namespace lw {
 namespace {
 
-constexpr size_t kBatchBytes = size_t(4) << 30;  // default trajectory batch (all three arrays)
+// default trajectory batch (all three arrays): the pusher runs one lane per particle through
+// every step, so a batch must hold enough particles to occupy the GPU (16 GiB: ~12k particles
+// at 2e4 steps)
+constexpr size_t kBatchBytes = size_t(16) << 30;
 
 inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 

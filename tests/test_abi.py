@@ -54,11 +54,11 @@ def test_workspace_sizes(lib):
     assert fft >= 3 * (1 << 12) * 16 and fft % (3 * (1 << 12) * 16) == 0
     assert lw.workspace_bytes(lw.WS_DIRECT_FD, 3, 5) >= 3 * 5 * 6 * 8
     assert lw.workspace_bytes(lw.WS_DIRECT_FD_BWD, 3, 5, "fp64") == lw.workspace_bytes(lw.WS_DIRECT_FD, 3, 5)
-    # Boris batches: the whole set when small, capped near 4 GiB when large
+    # Boris batches: the whole set when small, capped near 16 GiB when large
     small = lw.workspace_bytes(lw.WS_DEPOSIT_BORIS, 10, 1000)
     assert small >= 10 * 1000 * 72
     big = lw.workspace_bytes(lw.WS_DEPOSIT_BORIS, 100000, 20001)
-    assert 3.5 * 2**30 < big < 4.5 * 2**30
+    assert 15.5 * 2**30 < big < 16.5 * 2**30
     assert lw.workspace_bytes(lw.WS_DEPOSIT_BWD_BORIS, 10, 1000) >= 10 * 1000 * 144
     assert lib.lw_workspace_bytes(999, 1, 1, 0) == 0
 
