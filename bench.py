@@ -13,10 +13,17 @@ precision (arrival times in double, fields/trace/FFT in float).  ``value`` count
 particle * sample * pixel triples per second of step time.
 
 Also measured: the same step in all-FP64 (speedup of mixed over FP64), the spectral error
-of mixed against FP64 in the first-harmonic band of every pixel, the deposit kernel's
-share against its VALU roofline, the FFT against HBM bandwidth, the direct
-frequency-domain sum on a pixel subset, and the FP64 CPU oracle on a bounded sample
-(``cpu_baseline``).
+of mixed against FP64 in the first-harmonic band of every pixel, the culled variant
+(LW_CULL, same spectra), the deposit kernel's share against its VALU roofline with its
+counter-measured HBM traffic and VALU instruction count, the FFT against HBM bandwidth, the
+direct frequency-domain sum on a pixel subset, the gradient of a band objective, and the
+FP64 CPU oracle on a bounded sample (``cpu_baseline``).
+
+Other modes (one JSON line each, not the headline): ``--workload precision|large`` (one
+full-size pass of that configuration with in-library trajectories, mixed against FP64 per
+harmonic band; the large one adds the full-size adjoint), ``--cost-model`` (refit of the
+wall-clock model constants and the TD/FD crossover) and ``--accuracy`` (the single-electron
+accuracy experiment against a converged reference).
 """
 from __future__ import annotations
 
