@@ -8,17 +8,21 @@
 //     pixels: it forms the (particle, sample, pixel) arrival time in double and tests
 //     whether the interval (tau_{i-1}, tau_i] crosses the next grid point of that
 //     pixel's window (all four tests of a sample pair first, then one branch into the
-//     crossing logic if any holds).  The broadcast reads bound this loop (LDS returns 128 B per
-//     clock), so kPPL pixels per lane divide their cost by kPPL;
-//   * a crossing appends (particle, sample, pixel) to a per-wavefront queue in LDS;
-//     whenever 64 entries are queued, all lanes take one entry each, evaluate the
-//     Lienard-Wiechert field at the interval's two ends and add the interpolated
-//     values at the crossed grid points into a write-combining line of that pixel
-//     in LDS (a short run of consecutive grid points of its trace);
+//     crossing logic if any holds).  With one pixel per lane the broadcast reads bound
+//     this loop (LDS returns 128 B per clock); kPPL pixels per lane divide their cost;
+//   * a crossing appends (particle, sample, pixel, arrival-time form) to a per-wavefront
+//     queue in LDS; whenever 64 entries are queued, all lanes take one entry each,
+//     evaluate the Lienard-Wiechert field at the interval's two ends and add the
+//     interpolated values at the crossed grid points into a write-combining line of that
+//     pixel in LDS (a short run of consecutive grid points of its trace); an interval
+//     holding more than kLongRun grid points (an observer grid much finer than the
+//     samples) is deposited by the whole wavefront instead, 64 grid points per pass;
 //   * a line whose pixel moves past it is added to the trace with global atomics,
 //     several lines per instruction (lane l takes value l % 3N of line l / 3N).
 // The field is therefore evaluated only at samples that the interpolation reads;
-// samples whose interval holds no grid point of the window contribute nothing.
+// samples whose interval holds no grid point of the window contribute nothing.  With
+// LW_CULL (a separate instantiation) a fast-path particle is skipped when its first and
+// last arrival times at the wavefront's pixels bracket no window grid point.
 //
 // Fast path condition (checked per particle by a pre-pass): every sample usable and
 // every step shorter than c*dt by a margin well above the rounding of tau, which makes
