@@ -211,15 +211,13 @@ __device__ __forceinline__ void push_particle(const LaserDev &L, R a0, const R *
     R x = init[0], y = init[1], z = init[2];
     R usx = init[3], usy = init[4], usz = init[5];  // u at the sample time
     R uhx = usx, uhy = usy, uhz = usz;              // u half a step later
-    R Ex, By;
+    R Ex, By;  // the field at the current sample (r_i, t_i)
     laser_eb(L, a0, x, y, z, t_start, Ex, By);
     kick(uhx, uhy, uhz, Ex, By, 0.5 * dt);
     const double q = -kQe, m = kMe;
     for (int64_t i = 0; i < n_samples; ++i) {
-        const double ti = t_start + (double)i * dt;
         const R g = sqrt(1.0 + (usx * usx + usy * usy + usz * usz));
         const R bx = usx / g, by = usy / g, bz = usz / g;
-        laser_eb(L, a0, x, y, z, ti, Ex, By);
         // d beta/dt = q/(gamma m c) [E + c beta x B - beta (beta.E)],  E = (Ex,0,0), B = (0,By,0)
         const R f = (q / (m * kC)) / g;
         const R be = bx * Ex;
@@ -232,6 +230,7 @@ __device__ __forceinline__ void push_particle(const LaserDev &L, R a0, const R *
         y = y + (kC * dt) * (uhy / gh);
         z = z + (kC * dt) * (uhz / gh);
         R nx = uhx, ny = uhy, nz = uhz;
+        // the field at (r_{i+1}, t_{i+1}) drives the kick and is the next sample's field
         laser_eb(L, a0, x, y, z, t_start + (double)(i + 1) * dt, Ex, By);
         kick(nx, ny, nz, Ex, By, dt);
         usx = 0.5 * (uhx + nx);
