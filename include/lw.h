@@ -206,7 +206,11 @@ lw_status lw_spectrum_fft(const void *E, int64_t n_pix, int64_t n_obs, double dt
  * 2 eps0 c |x_m|^2 S is the right-hand side of Eq. inty_dft.
  * grid: x_det and t0 are used (dt_obs, n_obs ignored).  omega: [n_omega]
  * rad/s (device).  prec: FP64 = all double; MIXED = phase in double reduced
- * to one revolution, sin/cos and the sums' terms in float, sums in double.
+ * to one revolution, sin/cos and the sums' terms in float, sums in double;
+ * where each block of 512 consecutive frequencies is equally spaced (to 1e-13
+ * relative), the phasors of 8 consecutive frequencies come from one float
+ * sin/cos pair and a recurrence over frequency (any other frequencies: one
+ * sin/cos pair per phasor).
  * S: [n_pix][n_omega] double.
  * ws: >= lw_workspace_bytes(LW_WS_DIRECT_FD, n_pix, n_omega, prec) bytes.
  */

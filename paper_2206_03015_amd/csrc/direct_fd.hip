@@ -1,16 +1,25 @@
 // Direct frequency-domain sum (Eq. inty_dft, Algorithm 1), the comparison path.
 //
-// A wavefront owns one pixel and 64 frequencies (one per lane) and a group of
-// particles.  Per chunk of 64 samples every lane evaluates one sample (arrival time
-// and E*kappa, the integrand of Eq. const_phase_drop) into LDS; then every lane
-// sweeps the 64 staged samples for its own frequency.  FP64 mode forms the phase
-// w*(t_a - t0) in double per term and reduces it to one revolution before sin/cos.  Mixed
-// mode forms, per chunk and lane, the phase at a reference arrival time of the chunk in
-// double (reduced to one revolution) and adds nu*(t_a - t_ref) in float per term: the
-// offsets span a few revolutions at most, so the float phase keeps ~1e-8 of a
-// revolution and the hardware sin/cos (arguments in revolutions) never see a large
-// argument.  Partial sums of the wavefront go to a double workspace with atomics; a final
-// kernel forms S = (dt^2/2pi) sum_c |F_c|^2.
+// FP64 (k_direct_fd): a wavefront owns one pixel and 64 frequencies (one per lane) and a
+// group of particles.  Per chunk of 64 samples every lane evaluates one sample (arrival
+// time and E*kappa, the integrand of Eq. const_phase_drop) into LDS; then every lane sweeps
+// the 64 staged samples for its own frequency, forming the phase w*(t_a - t0) in double per
+// term and reducing it to one revolution before sin/cos.
+//
+// Mixed (k_direct_fd_mixed): lane l owns K consecutive frequencies (8, or fewer for short
+// frequency lists).  Per chunk and
+// lane the phase of the lane's first frequency at a reference arrival time of the chunk is
+// formed in double (reduced to one revolution); per sample one float FMA adds nu*(t_a -
+// t_ref), a few revolutions at most, and the hardware sin/cos (arguments in revolutions)
+// give the first phasor.  When the wavefront's frequencies are equally spaced by dw (checked
+// once per wavefront), the others follow by a recurrence over frequency: with the step
+// phasor e^{i dw t_a} formed once per sample at staging (phase in double, reduced, then
+// float sin/cos), p_1 = p_0 e^{i dw t} and p_{j+1} = 2 cos(dw t) p_j - p_{j-1}, two FMAs per
+// further frequency instead of a sin/cos pair.  Otherwise every phasor gets its own sin/cos.
+// Terms are summed in float over a chunk, chunks in double.
+//
+// Partial sums of a wavefront go to a double workspace with atomics; a final kernel forms
+// S = (dt^2/2pi) sum_c |F_c|^2.
 #include "lw_internal.h"
 
 #include <algorithm>
@@ -36,7 +45,43 @@ struct FdShape {
     int fmask;
 };
 
+// most frequencies per lane of the mixed kernel (fewer when there are few frequencies, so
+// that the lanes stay busy), and how equal the spacing of a wavefront's frequencies must be
+// (relative) for the recurrence over frequency
+constexpr int kFdFreq = 8;
+constexpr double kFdEqualTol = 1e-13;
+
+// Arrival time relative to t0 (s) and E*kappa of sample i of particle k at pixel g; zeros for
+// samples past the end, unusable samples and non-finite results.
 template <typename T, int GEOM>
+__device__ __forceinline__ void stage_sample(const double *__restrict__ r, const double *__restrict__ beta,
+                                             const double *__restrict__ beta_dot, const PixGeo &g, const double *xm,
+                                             double q, int64_t k, int64_t i, const FdShape &sh, double &ta, T &ex,
+                                             T &ey, T &ez)
+{
+    ta = 0.0;
+    ex = ey = ez = (T)0;
+    if (i >= sh.n_samples || !g.ok) return;
+    const size_t s = (size_t)(k * sh.n_samples + i) * 3;
+    if (!sample_usable(r + s, beta + s, beta_dot + s)) return;
+    double kap;
+    lw_field<T, GEOM>(g, xm, r[s], r[s + 1], r[s + 2], beta[s], beta[s + 1], beta[s + 2], beta_dot[s], beta_dot[s + 1],
+                      beta_dot[s + 2], q, sh.fmask, ex, ey, ez, &kap);
+    // arrival time relative to t0 (s), formed in units of u = cdt / c
+    const double u = sh.cdt / kC;
+    const double alpha = ((sh.t_start + (double)i * sh.dt) - sh.t0) / u;
+    ta = arrival_tau<GEOM, kTauSqrt>(g, alpha, r[s], r[s + 1], r[s + 2], 0.0, sh.inv_cdt) * u;
+    const T tk = (T)kap;
+    ex *= tk;
+    ey *= tk;
+    ez *= tk;
+    if (!(isfinite(ta) && isfinite((double)ex) && isfinite((double)ey) && isfinite((double)ez))) {
+        ta = 0.0;
+        ex = ey = ez = (T)0;
+    }
+}
+
+template <int GEOM>
 __global__ __launch_bounds__(256) void k_direct_fd(const double *__restrict__ r, const double *__restrict__ beta,
                                                    const double *__restrict__ beta_dot,
                                                    const double *__restrict__ charge, const double *__restrict__ x_det,
@@ -44,8 +89,7 @@ __global__ __launch_bounds__(256) void k_direct_fd(const double *__restrict__ r,
                                                    FdShape sh)
 {
     __shared__ double s_ta[kWavesPerBlock][64];
-    __shared__ float s_dtf[kWavesPerBlock][64];  // mixed: nu-free offsets t_a - t_ref (s)
-    __shared__ T s_ek[kWavesPerBlock][3][64];
+    __shared__ double s_ek[kWavesPerBlock][3][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wv;
     const int64_t per_pix = sh.n_wblocks * sh.n_groups;
@@ -66,40 +110,9 @@ __global__ __launch_bounds__(256) void k_direct_fd(const double *__restrict__ r,
         for (int64_t i0 = 0; i0 < ns; i0 += 64) {
             // stage: lane -> sample i0 + lane
             {
-                const int64_t i = i0 + lane;
-                double ta = 0.0;
-                T ex = 0, ey = 0, ez = 0;
-                if (i < ns && g.ok) {
-                    const size_t s = (size_t)(k * ns + i) * 3;
-                    if (sample_usable(r + s, beta + s, beta_dot + s)) {
-                        double kap;
-                        lw_field<T, GEOM>(g, xm, r[s], r[s + 1], r[s + 2], beta[s], beta[s + 1], beta[s + 2],
-                                          beta_dot[s], beta_dot[s + 1], beta_dot[s + 2], q, sh.fmask, ex, ey, ez,
-                                          &kap);
-                        // arrival time relative to t0 (s), formed in units of u = cdt / c
-                        const double u = sh.cdt / kC;
-                        const double alpha = ((sh.t_start + (double)i * sh.dt) - sh.t0) / u;
-                        ta = arrival_tau<GEOM, kTauSqrt>(g, alpha, r[s], r[s + 1], r[s + 2], 0.0, sh.inv_cdt) * u;
-                        const T tk = (T)kap;
-                        ex *= tk;
-                        ey *= tk;
-                        ez *= tk;
-                        if (!(isfinite(ta) && isfinite((double)ex) && isfinite((double)ey) && isfinite((double)ez))) {
-                            ta = 0.0;
-                            ex = ey = ez = 0;
-                        }
-                    }
-                }
-                const bool live = ex != (T)0 || ey != (T)0 || ez != (T)0;
-                if constexpr (sizeof(T) == 4) {
-                    // reference arrival time: the first lane with a contribution
-                    const uint64_t lm = __ballot(live);
-                    const double tref = lm ? readlane_f64(ta, (int)__builtin_ctzll(lm)) : 0.0;
-                    s_dtf[wv][lane] = live ? (float)(ta - tref) : 0.0f;
-                    if (lane == 0) s_ta[wv][0] = tref;
-                } else {
-                    s_ta[wv][lane] = ta;
-                }
+                double ta = 0.0, ex = 0, ey = 0, ez = 0;
+                stage_sample<double, GEOM>(r, beta, beta_dot, g, xm, q, k, i0 + lane, sh, ta, ex, ey, ez);
+                s_ta[wv][lane] = ta;
                 s_ek[wv][0][lane] = ex;
                 s_ek[wv][1][lane] = ey;
                 s_ek[wv][2][lane] = ez;
@@ -107,44 +120,26 @@ __global__ __launch_bounds__(256) void k_direct_fd(const double *__restrict__ r,
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             const int cnt = (int)std::min<int64_t>(64, ns - i0);
-            T b0 = 0, b1 = 0, b2 = 0, b3 = 0, b4 = 0, b5 = 0;
-            if constexpr (sizeof(T) == 4) {
-                const double x = nu * s_ta[wv][0];
-                const float base = (float)(x - floor(x));  // revolutions in [0, 1)
-                const float nuf = (float)nu;
-                for (int j = 0; j < cnt; ++j) {
-                    const float ph = fmaf(nuf, s_dtf[wv][j], base);
-                    const float c = __builtin_amdgcn_cosf(ph), sn = __builtin_amdgcn_sinf(ph);
-                    const T e0 = s_ek[wv][0][j], e1 = s_ek[wv][1][j], e2 = s_ek[wv][2][j];
-                    b0 += e0 * c;
-                    b1 += e0 * sn;
-                    b2 += e1 * c;
-                    b3 += e1 * sn;
-                    b4 += e2 * c;
-                    b5 += e2 * sn;
-                }
-            } else {
-                for (int j = 0; j < cnt; ++j) {
-                    const double x = nu * s_ta[wv][j];
-                    const double fr = x - floor(x);  // revolutions in [0, 1)
-                    double sd, cd;
-                    sincospi(2.0 * fr, &sd, &cd);
-                    const T c = (T)cd, sn = (T)sd;
-                    const T e0 = s_ek[wv][0][j], e1 = s_ek[wv][1][j], e2 = s_ek[wv][2][j];
-                    b0 += e0 * c;
-                    b1 += e0 * sn;
-                    b2 += e1 * c;
-                    b3 += e1 * sn;
-                    b4 += e2 * c;
-                    b5 += e2 * sn;
-                }
+            double b0 = 0, b1 = 0, b2 = 0, b3 = 0, b4 = 0, b5 = 0;
+            for (int j = 0; j < cnt; ++j) {
+                const double x = nu * s_ta[wv][j];
+                const double fr = x - floor(x);  // revolutions in [0, 1)
+                double sn, c;
+                sincospi(2.0 * fr, &sn, &c);
+                const double e0 = s_ek[wv][0][j], e1 = s_ek[wv][1][j], e2 = s_ek[wv][2][j];
+                b0 += e0 * c;
+                b1 += e0 * sn;
+                b2 += e1 * c;
+                b3 += e1 * sn;
+                b4 += e2 * c;
+                b5 += e2 * sn;
             }
-            a0 += (double)b0;
-            a1 += (double)b1;
-            a2 += (double)b2;
-            a3 += (double)b3;
-            a4 += (double)b4;
-            a5 += (double)b5;
+            a0 += b0;
+            a1 += b1;
+            a2 += b2;
+            a3 += b3;
+            a4 += b4;
+            a5 += b5;
             __builtin_amdgcn_wave_barrier();
         }
     }
@@ -156,6 +151,160 @@ __global__ __launch_bounds__(256) void k_direct_fd(const double *__restrict__ r,
         atomicAdd(o + 3, a3);
         atomicAdd(o + 4, a4);
         atomicAdd(o + 5, a5);
+    }
+}
+
+template <int GEOM, int K>
+__global__ __launch_bounds__(256) void k_direct_fd_mixed(const double *__restrict__ r,
+                                                         const double *__restrict__ beta,
+                                                         const double *__restrict__ beta_dot,
+                                                         const double *__restrict__ charge,
+                                                         const double *__restrict__ x_det,
+                                                         const double *__restrict__ omega, double *__restrict__ acc,
+                                                         FdShape sh)
+{
+    __shared__ double s_tref[kWavesPerBlock];
+    __shared__ float s_dtf[kWavesPerBlock][64];     // t_a - t_ref (s)
+    __shared__ float2 s_step[kWavesPerBlock][64];   // e^{i dw t_a}
+    __shared__ float s_ek[kWavesPerBlock][3][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+    const int64_t per_pix = sh.n_wblocks * sh.n_groups;
+    const int64_t m = wave / per_pix;
+    if (m >= sh.n_pix) return;  // whole wavefront idle; no block-level sync below
+    const int64_t rem = wave - m * per_pix;
+    const int64_t wb = rem / sh.n_groups, grp = rem - wb * sh.n_groups;
+    const int64_t wfirst = wb * 64 * K, wl = wfirst + (int64_t)lane * K;
+    // frequencies in cycles per second; the wavefront's spacing from its first two
+    double nu[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) nu[j] = wl + j < sh.n_omega ? omega[wl + j] / (2.0 * kPi) : 0.0;
+    const double nu_a = omega[wfirst] / (2.0 * kPi);
+    const double dnu = wfirst + 1 < sh.n_omega ? omega[wfirst + 1] / (2.0 * kPi) - nu_a : 0.0;
+    bool lane_eq = true;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const double pred = nu[0] + (double)j * dnu;
+        if (wl + j < sh.n_omega) lane_eq &= fabs(nu[j] - pred) <= kFdEqualTol * fabs(nu[j]);
+    }
+    const bool equal = __ballot(!lane_eq) == 0;  // wavefront-uniform
+    const int64_t k0 = grp * sh.parts_per_group, k1 = std::min(k0 + sh.parts_per_group, sh.n_particles);
+    PixGeo g = pix_geo(x_det, m);
+    const double *xm = x_det + 3 * m;
+    double a[K][6];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) a[j][c] = 0.0;
+    const int64_t ns = sh.n_samples;
+    for (int64_t k = k0; k < k1; ++k) {
+        const double q = charge ? charge[k] : -kQe;
+        for (int64_t i0 = 0; i0 < ns; i0 += 64) {
+            // stage: lane -> sample i0 + lane
+            {
+                double ta = 0.0;
+                float ex = 0, ey = 0, ez = 0;
+                stage_sample<float, GEOM>(r, beta, beta_dot, g, xm, q, k, i0 + lane, sh, ta, ex, ey, ez);
+                const bool live = ex != 0.0f || ey != 0.0f || ez != 0.0f;
+                // reference arrival time: the first lane with a contribution
+                const uint64_t lm = __ballot(live);
+                const double tref = lm ? readlane_f64(ta, (int)__builtin_ctzll(lm)) : 0.0;
+                s_dtf[wv][lane] = live ? (float)(ta - tref) : 0.0f;
+                if (lane == 0) s_tref[wv] = tref;
+                float2 st = make_float2(1.0f, 0.0f);
+                if (equal && live) {
+                    const double x = dnu * ta;
+                    const float fr = (float)(x - floor(x));  // revolutions in [0, 1)
+                    st = make_float2(__builtin_amdgcn_cosf(fr), __builtin_amdgcn_sinf(fr));
+                }
+                s_step[wv][lane] = st;
+                s_ek[wv][0][lane] = ex;
+                s_ek[wv][1][lane] = ey;
+                s_ek[wv][2][lane] = ez;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const int cnt = (int)std::min<int64_t>(64, ns - i0);
+            const double tref = s_tref[wv];
+            float b[K][6];
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) b[j][c] = 0.0f;
+            if (equal) {
+                const double x = nu[0] * tref;
+                const float base = (float)(x - floor(x));  // revolutions in [0, 1)
+                const float nuf = (float)nu[0];
+                for (int s = 0; s < cnt; ++s) {
+                    const float ph = fmaf(nuf, s_dtf[wv][s], base);
+                    // phasors p_j = e^{i(w_0 + j dw)t}: p_1 = p_0 e^{i dw t}, then the two-term
+                    // recurrence p_{j+1} = 2 cos(dw t) p_j - p_{j-1} (two FMAs per frequency)
+                    float c = __builtin_amdgcn_cosf(ph), sn = __builtin_amdgcn_sinf(ph);
+                    const float e0 = s_ek[wv][0][s], e1 = s_ek[wv][1][s], e2 = s_ek[wv][2][s];
+                    const float2 st = s_step[wv][s];
+                    const float tc = st.x + st.x;
+                    float cp = 0.0f, sp = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < K; ++j) {
+                        b[j][0] = fmaf(e0, c, b[j][0]);
+                        b[j][1] = fmaf(e0, sn, b[j][1]);
+                        b[j][2] = fmaf(e1, c, b[j][2]);
+                        b[j][3] = fmaf(e1, sn, b[j][3]);
+                        b[j][4] = fmaf(e2, c, b[j][4]);
+                        b[j][5] = fmaf(e2, sn, b[j][5]);
+                        if (j == 0 && K > 1) {
+                            cp = c;
+                            sp = sn;
+                            c = fmaf(cp, st.x, -sp * st.y);
+                            sn = fmaf(cp, st.y, sp * st.x);
+                        } else if (j + 1 < K) {
+                            const float cn = fmaf(tc, c, -cp), sn2 = fmaf(tc, sn, -sp);
+                            cp = c;
+                            sp = sn;
+                            c = cn;
+                            sn = sn2;
+                        }
+                    }
+                }
+            } else {
+                float base[K], nuf[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const double x = nu[j] * tref;
+                    base[j] = (float)(x - floor(x));
+                    nuf[j] = (float)nu[j];
+                }
+                for (int s = 0; s < cnt; ++s) {
+                    const float dtf = s_dtf[wv][s];
+                    const float e0 = s_ek[wv][0][s], e1 = s_ek[wv][1][s], e2 = s_ek[wv][2][s];
+#pragma unroll
+                    for (int j = 0; j < K; ++j) {
+                        const float ph = fmaf(nuf[j], dtf, base[j]);
+                        const float c = __builtin_amdgcn_cosf(ph), sn = __builtin_amdgcn_sinf(ph);
+                        b[j][0] = fmaf(e0, c, b[j][0]);
+                        b[j][1] = fmaf(e0, sn, b[j][1]);
+                        b[j][2] = fmaf(e1, c, b[j][2]);
+                        b[j][3] = fmaf(e1, sn, b[j][3]);
+                        b[j][4] = fmaf(e2, c, b[j][4]);
+                        b[j][5] = fmaf(e2, sn, b[j][5]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) a[j][c] += (double)b[j][c];
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (k1 > k0) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (wl + j >= sh.n_omega) continue;
+            double *o = acc + ((size_t)m * sh.n_omega + wl + j) * 6;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) atomicAdd(o + c, a[j][c]);
+        }
     }
 }
 
@@ -309,7 +458,11 @@ lw_status launch_direct_fd(const lw_traj_t *t, const lw_grid_t *gr, const double
     sh.n_samples = t->n_samples;
     sh.n_pix = n_pix;
     sh.n_omega = n_omega;
-    sh.n_wblocks = (n_omega + 63) / 64;
+    // frequencies per lane (mixed): the largest power of two <= kFdFreq that still fills a wavefront
+    int K = 1;
+    while (K < kFdFreq && 64 * 2 * K <= n_omega) K *= 2;
+    const int64_t per_wave = prec == LW_PREC_FP64 ? 64 : 64 * K;  // frequencies per wavefront
+    sh.n_wblocks = (n_omega + per_wave - 1) / per_wave;
     const int64_t base = n_pix * sh.n_wblocks;
     int64_t groups = std::max<int64_t>(1, (8192 + base - 1) / base);
     groups = std::min<int64_t>(groups, std::max<int64_t>(t->n_particles, 1));
@@ -329,18 +482,27 @@ lw_status launch_direct_fd(const lw_traj_t *t, const lw_grid_t *gr, const double
         if (blocks > 0x7fffffff) return fail(LW_E_SHAPE, "lw_direct_fd: problem too large for one launch");
         if (prec == LW_PREC_FP64) {
             if (geom == LW_GEOM_EXACT)
-                k_direct_fd<double, LW_GEOM_EXACT><<<(unsigned)blocks, 256, 0, s>>>(
+                k_direct_fd<LW_GEOM_EXACT><<<(unsigned)blocks, 256, 0, s>>>(
                     t->r, t->beta, t->beta_dot, t->charge, gr->x_det, omega, acc, sh);
             else
-                k_direct_fd<double, LW_GEOM_FARFIELD><<<(unsigned)blocks, 256, 0, s>>>(
+                k_direct_fd<LW_GEOM_FARFIELD><<<(unsigned)blocks, 256, 0, s>>>(
                     t->r, t->beta, t->beta_dot, t->charge, gr->x_det, omega, acc, sh);
         } else {
-            if (geom == LW_GEOM_EXACT)
-                k_direct_fd<float, LW_GEOM_EXACT><<<(unsigned)blocks, 256, 0, s>>>(
-                    t->r, t->beta, t->beta_dot, t->charge, gr->x_det, omega, acc, sh);
-            else
-                k_direct_fd<float, LW_GEOM_FARFIELD><<<(unsigned)blocks, 256, 0, s>>>(
-                    t->r, t->beta, t->beta_dot, t->charge, gr->x_det, omega, acc, sh);
+#define LW_FD_MIXED(G, KK)                                                                                        \
+    k_direct_fd_mixed<G, KK><<<(unsigned)blocks, 256, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge, gr->x_det, omega, \
+                                                               acc, sh)
+            if (geom == LW_GEOM_EXACT) {
+                if (K == 8) LW_FD_MIXED(LW_GEOM_EXACT, 8);
+                else if (K == 4) LW_FD_MIXED(LW_GEOM_EXACT, 4);
+                else if (K == 2) LW_FD_MIXED(LW_GEOM_EXACT, 2);
+                else LW_FD_MIXED(LW_GEOM_EXACT, 1);
+            } else {
+                if (K == 8) LW_FD_MIXED(LW_GEOM_FARFIELD, 8);
+                else if (K == 4) LW_FD_MIXED(LW_GEOM_FARFIELD, 4);
+                else if (K == 2) LW_FD_MIXED(LW_GEOM_FARFIELD, 2);
+                else LW_FD_MIXED(LW_GEOM_FARFIELD, 1);
+            }
+#undef LW_FD_MIXED
         }
     }
     const double f = t->dt * t->dt / (2.0 * kPi);
@@ -380,10 +542,10 @@ lw_status launch_direct_fd_bwd(const lw_traj_t *t, const lw_grid_t *gr, const do
         const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
         if (blocks > 0x7fffffff) return fail(LW_E_SHAPE, "lw_direct_fd_bwd: problem too large for one launch");
         if (geom == LW_GEOM_EXACT)
-            k_direct_fd<double, LW_GEOM_EXACT><<<(unsigned)blocks, 256, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge,
+            k_direct_fd<LW_GEOM_EXACT><<<(unsigned)blocks, 256, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge,
                                                                               gr->x_det, omega, acc, sh);
         else
-            k_direct_fd<double, LW_GEOM_FARFIELD><<<(unsigned)blocks, 256, 0, s>>>(
+            k_direct_fd<LW_GEOM_FARFIELD><<<(unsigned)blocks, 256, 0, s>>>(
                 t->r, t->beta, t->beta_dot, t->charge, gr->x_det, omega, acc, sh);
     }
     {

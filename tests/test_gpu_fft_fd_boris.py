@@ -95,6 +95,36 @@ def test_direct_fd(prec, geom):
     assert err <= (1e-10 if prec == "fp64" else 1e-4)
 
 
+@pytest.mark.parametrize("layout,n_w", [("equal", 150), ("equal", 300), ("equal", 1100), ("piecewise", 1100),
+                                        ("random", 1100)])
+def test_direct_fd_mixed_frequency_layouts(layout, n_w):
+    # Mixed mode gives each lane 2, 4 or 8 consecutive frequencies (150, 300, 1100 here; 100
+    # frequencies in test_direct_fd give one) and runs a recurrence over frequency for
+    # wavefronts whose frequencies are equally spaced, one sin/cos per phasor for the others.
+    # 1100 frequencies span three wavefronts of 512 with a ragged tail; "piecewise" changes
+    # the spacing inside the second (that one takes the sin/cos path, the others the
+    # recurrence), "random" has no spacing.
+    from paper_2206_03015_amd import lw
+    c = small_bunch(n_p=4, n_steps=1200, n_side=2)
+    W = c["W"]
+    w1 = W.omega1()
+    if layout == "equal":
+        omega = np.linspace(0.5 * w1, 1.3 * w1, n_w)
+    elif layout == "piecewise":
+        omega = np.concatenate([np.linspace(0.5 * w1, 0.9 * w1, 700, endpoint=False),
+                                np.linspace(0.9 * w1, 1.3 * w1, n_w - 700)])
+    else:
+        omega = np.sort(np.random.default_rng(11).uniform(0.5 * w1, 1.3 * w1, n_w))
+    So = oracle.direct_fd(c["t_start"], c["dt"], c["r"], c["beta"], c["beta_dot"], c["x_det"], c["t0"], omega,
+                          field_mask=3)
+    t = {k: torch.as_tensor(np.ascontiguousarray(c[k]), device=DEV) for k in ("r", "beta", "beta_dot", "x_det")}
+    Sg = lw.direct_fd(t["r"], t["beta"], t["beta_dot"], c["t_start"], c["dt"], t["x_det"], c["t0"],
+                      torch.as_tensor(omega, device=DEV), prec="mixed", field_mask=3).cpu().numpy()
+    err = np.max(np.abs(Sg - So), axis=1) / np.max(So, axis=1)
+    print(f"direct FD mixed, {n_w} {layout} frequencies: rel err per pixel {err}")
+    assert np.all(err <= 1e-4)
+
+
 def test_direct_fd_synthetic_charges():
     from paper_2206_03015_amd import lw
     c = synthetic(n_p=3, n_samples=300, n_pix=65)
