@@ -15,7 +15,9 @@ particle * sample * pixel triples per second of step time.
 Also measured: the same step in all-FP64 (speedup of mixed over FP64), the spectral error
 of mixed against FP64 in the first-harmonic band of every pixel, the culled variant
 (LW_CULL, same spectra), the deposit kernel's share against its VALU roofline with its
-counter-measured HBM traffic and VALU instruction count, the FFT against HBM bandwidth, the
+counter-measured HBM traffic, VALU instruction count and executed FP64/FP32 flop rates
+(committed rocprofv3 summaries, used while the deposit sources are unchanged), the FFT
+against HBM bandwidth, the
 direct frequency-domain sum on a pixel subset, the gradient of a band objective, and the
 FP64 CPU oracle on a bounded sample (``cpu_baseline``).
 
@@ -60,6 +62,7 @@ PEAK_EVAL_TFLOPS = EVAL_FLOPS / EVAL_ROOF_S / 1e12
 DEPOSIT_SOURCES = ("paper_2206_03015_amd/csrc/deposit.hip", "paper_2206_03015_amd/csrc/lw_internal.h")
 TRAFFIC_SUMMARY = "profiles/k_deposit_bunch_mixed_exact_hbm_traffic.md"
 VALU_SUMMARY = "profiles/k_deposit_bunch_mixed_exact_valu.md"
+VALU_TYPES_SUMMARY = "profiles/valu_fp32_fp64_bunch_exact.md"
 
 
 def parse():
@@ -239,6 +242,13 @@ def main():
     if valu is not None:
         roof["executed_valu_insts_per_launch"] = valu
         roof["valu_issue_frac"] = valu * 4 / (CUS * 4 * CLOCK_GHZ * 1e9 * dep_s)
+    # FP64 and FP32 flops the launch executes (SQ_INSTS_VALU_{FMA,MUL,ADD}_{F32,F64}, committed
+    # summary) over its measured time: the VALU utilisation by precision
+    ex = deposit_executed_flops() if profiled else None
+    if ex is not None:
+        f64, f32 = ex[0] / dep_s / 1e12, ex[1] / dep_s / 1e12
+        roof["executed"] = {"f64_tflops": f64, "f64_frac": f64 / PEAK_F64_TFLOPS,
+                            "f32_tflops": f32, "f32_frac": f32 / PEAK_F32_TFLOPS}
     fft_bytes = n_pix * (3 * n_obs + n_obs // 2 + 1) * 4
     fft_gbs = fft_bytes / (mixed["fft_ms"] / 1e3) / 1e9
 
@@ -726,6 +736,16 @@ def deposit_valu_insts():
     vals = _profile_figures(VALU_SUMMARY)
     try:
         return float(vals["valu_insts_per_launch"]) if vals else None
+    except (KeyError, ValueError):
+        return None
+
+
+def deposit_executed_flops():
+    """(FP64, FP32) flops executed by one deposit launch from the committed summary of the
+    SQ_INSTS_VALU_{FMA,MUL,ADD}_{F32,F64} counters."""
+    vals = _profile_figures(VALU_TYPES_SUMMARY)
+    try:
+        return (float(vals["f64_flops_per_launch"]), float(vals["f32_flops_per_launch"])) if vals else None
     except (KeyError, ValueError):
         return None
 
