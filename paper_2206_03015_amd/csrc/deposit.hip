@@ -57,7 +57,10 @@ constexpr uint32_t kSerBit = 1u << 31;
 // intervals with more grid points than this are deposited by the whole wavefront
 constexpr int kLongRun = 8;
 constexpr int kStage = 6;  // doubles per staged sample: alpha, x, y, z, |r|^2, pad
-constexpr int kTargetWaves = 16384;
+// wavefronts per launch to aim for (particle groups x pixel tiles): ~26 rounds of the 3072
+// resident wavefronts (12 per CU), so that the last, partly filled round is a small share
+// (bunch workload: 16384 wavefronts took 705 ms, 80000 take 655 ms)
+constexpr int kTargetWaves = 98304;
 // (|r|/|x|)^2 up to which the series form of the exact-geometry arrival time is used
 constexpr double kSeriesBound = 1e-8;
 constexpr int kPrepassChunk = 8192;
