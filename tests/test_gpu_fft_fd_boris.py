@@ -125,6 +125,27 @@ def test_direct_fd_mixed_frequency_layouts(layout, n_w):
     assert np.all(err <= 1e-4)
 
 
+@pytest.mark.parametrize("n_w", [1, 2, 65, 513])
+@pytest.mark.parametrize("n_samples", [5, 130])
+def test_direct_fd_mixed_edge_sizes(n_w, n_samples):
+    # one frequency, a pair, a wavefront and one more, 512 + 1 (a second wavefront of eight
+    # frequencies per lane holding a single frequency); sample counts below and above one
+    # chunk of 64
+    from paper_2206_03015_amd import lw
+    c = synthetic(n_p=2, n_samples=n_samples, n_pix=3)
+    omega = np.linspace(1e17, 2e19, n_w) if n_w > 1 else np.array([3e18])
+    So = oracle.direct_fd(c["t_start"], c["dt"], c["r"], c["beta"], c["beta_dot"], c["x_det"], c["t0"], omega,
+                          charge=c["charge"])
+    t = {k: torch.as_tensor(np.ascontiguousarray(c[k]), device=DEV) for k in ("r", "beta", "beta_dot", "x_det",
+                                                                              "charge")}
+    Sg = lw.direct_fd(t["r"], t["beta"], t["beta_dot"], c["t_start"], c["dt"], t["x_det"], c["t0"],
+                      torch.as_tensor(omega, device=DEV), prec="mixed", charge=t["charge"]).cpu().numpy()
+    assert Sg.shape == So.shape
+    err = np.max(np.abs(Sg - So)) / np.max(So)
+    print(f"direct FD mixed, {n_w} frequencies, {n_samples} samples: rel err {err:.2e}")
+    assert err <= 1e-4
+
+
 def test_direct_fd_synthetic_charges():
     from paper_2206_03015_amd import lw
     c = synthetic(n_p=3, n_samples=300, n_pix=65)
