@@ -94,7 +94,8 @@ typedef struct {
  * t_i = t_start + i*dt (computed, never accumulated). */
 typedef struct {
     int32_t kind;          /* LW_TRAJ_SAMPLES or LW_TRAJ_BORIS                          */
-    int32_t reserved;      /* must be 0                                                  */
+    int32_t span;          /* 0, or >= 2: samples per pushed span of an LW_TRAJ_BORIS     */
+                           /* lw_deposit_td (0: chosen from the workspace); 0 elsewhere  */
     int64_t n_particles;   /* >= 0                                                       */
     int64_t n_samples;     /* >= 1  (= N_s + 1 in the paper's notation)                  */
     double t_start, dt;    /* s; dt > 0                                                  */
@@ -129,10 +130,12 @@ typedef struct {
  * Workspace (scratch device memory) that the call `which` needs, in bytes:
  * n_a = n_particles (deposit, deposit_bwd, deposit_boris, deposit_bwd_boris), n_pix
  * (fft, fft_bwd, direct_fd, direct_fd_bwd); n_b = n_samples (deposit*), n_obs
- * (fft, fft_bwd), n_omega (direct_fd, direct_fd_bwd).  LW_WS_DEPOSIT_BORIS and
- * LW_WS_DEPOSIT_BWD_BORIS size the trajectory batches of LW_TRAJ_BORIS calls (at
- * most ~16 GiB by default; any workspace that holds one particle's batch is
- * accepted and sets the batch size).  Returns 0 for
+ * (fft, fft_bwd), n_omega (direct_fd, direct_fd_bwd).  LW_WS_DEPOSIT_BORIS sizes
+ * the pushed batches and spans of LW_TRAJ_BORIS deposits (~16 GiB at most by
+ * default: min(n_particles, 65536) particles over the longest spans that fit);
+ * any workspace that holds a two-sample span of one particle is accepted and
+ * sets batch and span.  LW_WS_DEPOSIT_BWD_BORIS sizes the adjoint's batches of
+ * whole trajectories (any workspace holding one is accepted).  Returns 0 for
  * an unknown `which`.  Larger workspaces are accepted; for the FFT a larger
  * workspace lets more pixels be transformed per pass.
  */
@@ -155,10 +158,15 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec);
  * sample with a non-finite value or |beta| >= 1 is skipped.
  *
  * traj:       LW_TRAJ_SAMPLES, or LW_TRAJ_BORIS: the samples are then recomputed
- *             inside the call by the FP64 Boris pusher of lw_trajectory_boris, batch
- *             by batch of particles into the workspace (never the whole set), each
- *             batch deposited and discarded; ws then needs
- *             lw_workspace_bytes(LW_WS_DEPOSIT_BORIS, n_particles, n_samples, prec).
+ *             inside the call by the FP64 Boris pusher of lw_trajectory_boris, a
+ *             batch of particles over a span of samples at a time into the workspace
+ *             (never the whole set), each span deposited and discarded.  Spans share
+ *             their boundary sample and the pusher's state carries over between
+ *             them, so the samples equal those of lw_trajectory_boris bit for bit
+ *             and n_samples is not limited by memory.  Batch and span follow from
+ *             ws_bytes (traj->span = 0), or traj->span >= 2 fixes the span; ws then
+ *             needs lw_workspace_bytes(LW_WS_DEPOSIT_BORIS, n_particles, n_samples,
+ *             prec) bytes, or less (smaller batches and spans).
  * grid:       pixels and observer grid.
  * prec:       LW_PREC_FP64 (E is double) or LW_PREC_MIXED (E is float; tau and
  *             the crossing decisions are still computed in double).  In the exact

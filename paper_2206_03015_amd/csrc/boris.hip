@@ -203,42 +203,85 @@ __device__ __forceinline__ void kick(R &ux, R &uy, R &uz, R Ex, R By, double h)
     uz = nz;
 }
 
+// State of one particle's pusher at sample i: position, u = gamma beta at the sample time, u
+// half a step later, and the field at (r_i, t_i).  The field is a function of the position and
+// the time only, so a state saved without it and resumed at sample i recomputes it bit for bit.
+template <typename R>
+struct PushState {
+    R x, y, z, usx, usy, usz, uhx, uhy, uhz, Ex, By;
+};
+
+template <typename R>
+__device__ __forceinline__ void push_start(const LaserDev &L, R a0, const R *init, double t_start, double dt,
+                                           PushState<R> &S)
+{
+    S.x = init[0];
+    S.y = init[1];
+    S.z = init[2];
+    S.usx = init[3];
+    S.usy = init[4];
+    S.usz = init[5];
+    S.uhx = S.usx;
+    S.uhy = S.usy;
+    S.uhz = S.usz;
+    laser_eb(L, a0, S.x, S.y, S.z, t_start, S.Ex, S.By);
+    kick(S.uhx, S.uhy, S.uhz, S.Ex, S.By, 0.5 * dt);
+}
+
+// r, beta and beta_dot of the sample the state stands at
+template <typename R>
+__device__ __forceinline__ void push_sample(const PushState<R> &S, R *rr, R *bb, R *aa)
+{
+    const double q = -kQe, m = kMe;
+    const R g = sqrt(1.0 + (S.usx * S.usx + S.usy * S.usy + S.usz * S.usz));
+    const R bx = S.usx / g, by = S.usy / g, bz = S.usz / g;
+    // d beta/dt = q/(gamma m c) [E + c beta x B - beta (beta.E)],  E = (Ex,0,0), B = (0,By,0)
+    const R f = (q / (m * kC)) / g;
+    const R be = bx * S.Ex;
+    rr[0] = S.x;
+    rr[1] = S.y;
+    rr[2] = S.z;
+    bb[0] = bx;
+    bb[1] = by;
+    bb[2] = bz;
+    aa[0] = f * (S.Ex - kC * (bz * S.By) - bx * be);
+    aa[1] = f * (-(by * be));
+    aa[2] = f * (kC * (bx * S.By) - bz * be);
+}
+
+// one Boris step from sample i to sample i + 1 (t_next = t_start + (i + 1) dt)
+template <typename R>
+__device__ __forceinline__ void push_step(const LaserDev &L, R a0, double t_next, double dt, PushState<R> &S)
+{
+    const R gh = sqrt(1.0 + (S.uhx * S.uhx + S.uhy * S.uhy + S.uhz * S.uhz));
+    S.x = S.x + (kC * dt) * (S.uhx / gh);
+    S.y = S.y + (kC * dt) * (S.uhy / gh);
+    S.z = S.z + (kC * dt) * (S.uhz / gh);
+    R nx = S.uhx, ny = S.uhy, nz = S.uhz;
+    // the field at (r_{i+1}, t_{i+1}) drives the kick and is the next sample's field
+    laser_eb(L, a0, S.x, S.y, S.z, t_next, S.Ex, S.By);
+    kick(nx, ny, nz, S.Ex, S.By, dt);
+    S.usx = 0.5 * (S.uhx + nx);
+    S.usy = 0.5 * (S.uhy + ny);
+    S.usz = 0.5 * (S.uhz + nz);
+    S.uhx = nx;
+    S.uhy = ny;
+    S.uhz = nz;
+}
+
 // Runs the pusher of one particle and calls emit(i, r[3], beta[3], beta_dot[3]) per sample.
 template <typename R, typename Emit>
 __device__ __forceinline__ void push_particle(const LaserDev &L, R a0, const R *init, int64_t n_samples,
                                               double t_start, double dt, Emit emit)
 {
-    R x = init[0], y = init[1], z = init[2];
-    R usx = init[3], usy = init[4], usz = init[5];  // u at the sample time
-    R uhx = usx, uhy = usy, uhz = usz;              // u half a step later
-    R Ex, By;  // the field at the current sample (r_i, t_i)
-    laser_eb(L, a0, x, y, z, t_start, Ex, By);
-    kick(uhx, uhy, uhz, Ex, By, 0.5 * dt);
-    const double q = -kQe, m = kMe;
+    PushState<R> S;
+    push_start(L, a0, init, t_start, dt, S);
     for (int64_t i = 0; i < n_samples; ++i) {
-        const R g = sqrt(1.0 + (usx * usx + usy * usy + usz * usz));
-        const R bx = usx / g, by = usy / g, bz = usz / g;
-        // d beta/dt = q/(gamma m c) [E + c beta x B - beta (beta.E)],  E = (Ex,0,0), B = (0,By,0)
-        const R f = (q / (m * kC)) / g;
-        const R be = bx * Ex;
-        const R rr[3] = {x, y, z}, bb[3] = {bx, by, bz};
-        const R aa[3] = {f * (Ex - kC * (bz * By) - bx * be), f * (-(by * be)), f * (kC * (bx * By) - bz * be)};
+        R rr[3], bb[3], aa[3];
+        push_sample(S, rr, bb, aa);
         emit(i, rr, bb, aa);
         if (i + 1 == n_samples) break;
-        const R gh = sqrt(1.0 + (uhx * uhx + uhy * uhy + uhz * uhz));
-        x = x + (kC * dt) * (uhx / gh);
-        y = y + (kC * dt) * (uhy / gh);
-        z = z + (kC * dt) * (uhz / gh);
-        R nx = uhx, ny = uhy, nz = uhz;
-        // the field at (r_{i+1}, t_{i+1}) drives the kick and is the next sample's field
-        laser_eb(L, a0, x, y, z, t_start + (double)(i + 1) * dt, Ex, By);
-        kick(nx, ny, nz, Ex, By, dt);
-        usx = 0.5 * (uhx + nx);
-        usy = 0.5 * (uhy + ny);
-        usz = 0.5 * (uhz + nz);
-        uhx = nx;
-        uhy = ny;
-        uhz = nz;
+        push_step(L, a0, t_start + (double)(i + 1) * dt, dt, S);
     }
 }
 
@@ -260,6 +303,61 @@ __global__ __launch_bounds__(256) void k_boris(const double *__restrict__ init, 
                                   beta_dot[o + c] = aa[c];
                               }
                           });
+}
+
+// Samples s0 .. s0 + n_span - 1 of each particle into r, beta, beta_dot [n_particles][n_span][3].
+// The pusher starts from init (s0 = 0) or from the state saved by the previous span, which ends
+// at sample s0 (spans share their boundary sample), and saves its state at the last sample it
+// writes: x, y, z, u at the sample and u half a step later, [n_particles][9].
+constexpr int kStateDoubles = 9;
+
+__global__ __launch_bounds__(256) void k_boris_span(const double *__restrict__ init, int64_t n_particles,
+                                                    int64_t s0, int64_t n_span, double t_start, double dt,
+                                                    LaserDev L, double *__restrict__ state, double *__restrict__ r,
+                                                    double *__restrict__ beta, double *__restrict__ beta_dot)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_particles) return;
+    PushState<double> S;
+    double *st = state + kStateDoubles * k;
+    if (s0 == 0) {
+        double in[6];
+        for (int c = 0; c < 6; ++c) in[c] = init[6 * k + c];
+        push_start(L, L.a0, in, t_start, dt, S);
+    } else {
+        S.x = st[0];
+        S.y = st[1];
+        S.z = st[2];
+        S.usx = st[3];
+        S.usy = st[4];
+        S.usz = st[5];
+        S.uhx = st[6];
+        S.uhy = st[7];
+        S.uhz = st[8];
+        // the same arguments as the step that reached sample s0: the same field
+        laser_eb(L, L.a0, S.x, S.y, S.z, t_start + (double)s0 * dt, S.Ex, S.By);
+    }
+    for (int64_t j = 0; j < n_span; ++j) {
+        double rr[3], bb[3], aa[3];
+        push_sample(S, rr, bb, aa);
+        const size_t o = (size_t)(k * n_span + j) * 3;
+        for (int c = 0; c < 3; ++c) {
+            r[o + c] = rr[c];
+            beta[o + c] = bb[c];
+            beta_dot[o + c] = aa[c];
+        }
+        if (j + 1 == n_span) break;
+        push_step(L, L.a0, t_start + (double)(s0 + j + 1) * dt, dt, S);
+    }
+    st[0] = S.x;
+    st[1] = S.y;
+    st[2] = S.z;
+    st[3] = S.usx;
+    st[4] = S.usy;
+    st[5] = S.usz;
+    st[6] = S.uhx;
+    st[7] = S.uhy;
+    st[8] = S.uhz;
 }
 
 // Gradient through the pusher by forward-mode tangents: lane l handles particle k = l / 7
@@ -319,6 +417,17 @@ lw_status launch_boris(const lw_traj_t *t, double *r, double *beta, double *beta
     k_boris<<<(unsigned)blocks, 64, 0, s>>>(t->init, t->n_particles, t->n_samples, t->t_start, t->dt, L, r, beta,
                                            beta_dot);
     return check_launch("lw_trajectory_boris");
+}
+
+lw_status launch_boris_span(const lw_traj_t *t, int64_t s0, int64_t n_span, double *state, double *r, double *beta,
+                            double *beta_dot, hipStream_t s)
+{
+    if (t->n_particles == 0 || n_span == 0) return LW_OK;
+    const LaserDev L = laser_dev(t->laser);
+    const int64_t blocks = (t->n_particles + 63) / 64;
+    k_boris_span<<<(unsigned)blocks, 64, 0, s>>>(t->init, t->n_particles, s0, n_span, t->t_start, t->dt, L, state, r,
+                                                beta, beta_dot);
+    return check_launch("lw_deposit_td (pusher span)");
 }
 
 lw_status launch_boris_bwd(const lw_traj_t *t, const double *g_r, const double *g_beta, const double *g_beta_dot,

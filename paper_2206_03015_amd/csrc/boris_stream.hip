@@ -1,8 +1,12 @@
 // Deposit and its adjoint for trajectories given as initial conditions plus a laser pulse
-// (LW_TRAJ_BORIS): the FP64 Boris pusher recomputes the samples batch by batch of particles
-// inside the library, so the whole trajectory set is never stored (the paper's time-domain
-// method with the trajectory update inside the particle loop).  Each batch is pushed into
-// the workspace, deposited (accumulating after the first batch) and discarded.
+// (LW_TRAJ_BORIS): the FP64 Boris pusher recomputes the samples inside the library, so the
+// whole trajectory set is never stored (the paper's time-domain method with the trajectory
+// update inside the particle loop, and its on-the-fly evaluation over time).  The deposit
+// pushes a batch of particles over a span of samples into the workspace, deposits it
+// (accumulating after the first) and reuses the space for the next span: spans share their
+// boundary sample, the pusher's state (position and the two momenta) is kept between them, so
+// the samples are those of one uninterrupted push and the trajectory length is unbounded.
+// The adjoint pushes whole trajectories, batch by batch of particles.
 #include "lw_internal.h"
 
 #include <algorithm>
@@ -10,15 +14,51 @@
 namespace lw {
 namespace {
 
-// default trajectory batch (all three arrays): the pusher runs one lane per particle through
-// every step, so a batch must hold enough particles to occupy the GPU (16 GiB: ~12k particles
-// at 2e4 steps)
+// default trajectory budget (all three sample arrays of a batch)
 constexpr size_t kBatchBytes = size_t(16) << 30;
+// the pusher runs one lane per particle through every step of a span, so its time is the
+// per-step latency of one wavefront times the span length for up to one wavefront per SIMD
+// (1024 SIMDs x 64 lanes): batches of up to that many particles, spans as long as fit
+constexpr int64_t kFillParticles = 65536;
+// spans shorter than this give way to smaller batches (each span is one deposit launch)
+constexpr int64_t kMinSpan = 1024;
+// longest span one deposit launch takes (its pre-pass grid covers 8192 samples per block row)
+constexpr int64_t kMaxSpan = int64_t(1) << 28;
+constexpr int kStateBytes = 9 * sizeof(double);
 
 inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 // bytes of one particle's batch buffers: `arrays` sample arrays of [n_samples][3] doubles
 inline size_t per_particle(int64_t ns, int arrays) { return align256((size_t)ns * 3 * sizeof(double)) * arrays; }
+
+// workspace of a forward plan: deposit scratch, pusher states, r, beta, beta_dot of the span
+size_t plan_bytes(int64_t B, int64_t L)
+{
+    return align256(deposit_ws_bytes(B, L)) + align256((size_t)B * kStateBytes) +
+           3 * align256((size_t)B * (size_t)L * 3 * sizeof(double));
+}
+
+// longest span (<= lmax) of B particles within `bytes` (0 if not even one sample fits)
+int64_t fit_span(int64_t B, int64_t lmax, size_t bytes)
+{
+    const size_t fixed = plan_bytes(B, 1);
+    if (fixed > bytes) return 0;
+    const size_t per_sample = (size_t)B * 72 + sizeof(double);
+    int64_t L = std::min<int64_t>(lmax, 1 + (int64_t)((bytes - fixed) / per_sample));
+    while (L > 1 && plan_bytes(B, L) > bytes) --L;
+    return L;
+}
+
+// largest batch (<= bmax) with spans of L samples within `bytes` (0 if none)
+int64_t fit_batch(int64_t bmax, int64_t L, size_t bytes)
+{
+    const size_t fixed = plan_bytes(1, L);
+    if (fixed > bytes) return 0;
+    const size_t per_particle_bytes = (size_t)L * 72 + kStateBytes + 2 * sizeof(double);
+    int64_t B = std::min<int64_t>(bmax, 1 + (int64_t)((bytes - fixed) / per_particle_bytes));
+    while (B > 1 && plan_bytes(B, L) > bytes) --B;
+    return B;
+}
 
 __global__ void k_zero(double *__restrict__ p, int64_t n)
 {
@@ -27,6 +67,37 @@ __global__ void k_zero(double *__restrict__ p, int64_t n)
 }
 
 }  // namespace
+
+// Batch and span from the workspace: batches of min(n_p, kFillParticles) particles over the
+// longest spans that fit (whole trajectories when they do); spans shorter than kMinSpan give
+// way to smaller batches; a requested span fixes L and leaves the batch to the workspace.
+BorisPlan boris_plan_fit(int64_t n_p, int64_t ns, int64_t span_req, size_t ws_bytes)
+{
+    const int64_t b0 = std::max<int64_t>(1, std::min<int64_t>(n_p, kFillParticles));
+    const int64_t lmax = std::min<int64_t>(ns, kMaxSpan);
+    const int64_t lmin = std::min<int64_t>(lmax, 2);  // a span must advance (one interval at least)
+    if (span_req > 0) {
+        const int64_t L = std::max<int64_t>(lmin, std::min<int64_t>(span_req, lmax));
+        return {fit_batch(b0, L, ws_bytes), L};
+    }
+    const int64_t L0 = fit_span(b0, lmax, ws_bytes);
+    if (L0 >= std::min<int64_t>(lmax, kMinSpan)) return {b0, L0};
+    const int64_t Lm = std::min<int64_t>(lmax, kMinSpan);
+    const int64_t B = fit_batch(b0, Lm, ws_bytes);
+    if (B >= 1) return {B, Lm};
+    const int64_t L1 = fit_span(1, lmax, ws_bytes);
+    if (L1 >= lmin) return {1, L1};
+    return {0, 0};
+}
+
+BorisPlan boris_plan_default(int64_t n_p, int64_t ns)
+{
+    const BorisPlan p = boris_plan_fit(n_p, ns, 0, kBatchBytes);
+    // a budget too small for even one particle's two-sample span cannot happen at 16 GiB
+    return p.batch > 0 ? p : BorisPlan{1, std::min<int64_t>(ns, 2)};
+}
+
+size_t boris_plan_ws_bytes(const BorisPlan &p) { return plan_bytes(std::max<int64_t>(p.batch, 1), p.span); }
 
 int64_t boris_batch_default(int64_t n_p, int64_t ns, int arrays)
 {
@@ -60,33 +131,44 @@ lw_status launch_deposit_boris(const lw_traj_t *t, const lw_grid_t *gr, int prec
     if (n_p == 0 || gr->n_pix == 0) {  // nothing to push: only the trace and diag reset of the plain call
         lw_traj_t sub = *t;
         sub.kind = LW_TRAJ_SAMPLES;
+        sub.span = 0;
         sub.n_particles = 0;
         sub.r = sub.beta = sub.beta_dot = nullptr;
         return launch_deposit(&sub, gr, prec, fmask, geom, accumulate, E, diag, ws, ws_bytes, s);
     }
-    const int64_t B = boris_batch_fit(n_p, ns, ws_bytes, 3);
-    if (B < 1) return fail(LW_E_WORKSPACE, "lw_deposit_td: workspace holds no trajectory batch");
-    const size_t dep_bytes = align256(deposit_ws_bytes(B, ns));
+    const BorisPlan P = boris_plan_fit(n_p, ns, t->span, ws_bytes);
+    if (P.batch < 1 || (ns > 1 && P.span < 2)) return fail(LW_E_WORKSPACE, "lw_deposit_td: workspace holds no span");
+    const size_t dep_bytes = align256(deposit_ws_bytes(P.batch, P.span));
     char *p = (char *)ws + dep_bytes;
-    const size_t arr = align256((size_t)ns * 3 * sizeof(double)) * (size_t)B;
+    double *state = (double *)p;
+    p += align256((size_t)P.batch * kStateBytes);
+    const size_t arr = align256((size_t)P.batch * (size_t)P.span * 3 * sizeof(double));
     double *r = (double *)p, *b = (double *)(p + arr), *bd = (double *)(p + 2 * arr);
-    for (int64_t b0 = 0; b0 < n_p; b0 += B) {
-        const int64_t nb = std::min<int64_t>(B, n_p - b0);
+    for (int64_t b0 = 0; b0 < n_p; b0 += P.batch) {
+        const int64_t nb = std::min<int64_t>(P.batch, n_p - b0);
         lw_traj_t push = *t;
         push.n_particles = nb;
         push.init = t->init + 6 * b0;
-        lw_status st = launch_boris(&push, r, b, bd, s);
-        if (st != LW_OK) return st;
-        lw_traj_t sub = *t;
-        sub.kind = LW_TRAJ_SAMPLES;
-        sub.n_particles = nb;
-        sub.r = r;
-        sub.beta = b;
-        sub.beta_dot = bd;
-        sub.init = nullptr;
-        sub.charge = t->charge ? t->charge + b0 : nullptr;
-        st = launch_deposit(&sub, gr, prec, fmask, geom, accumulate || b0 > 0, E, diag, ws, dep_bytes, s);
-        if (st != LW_OK) return st;
+        for (int64_t s0 = 0;;) {
+            const int64_t n_span = std::min<int64_t>(P.span, ns - s0);
+            lw_status st = launch_boris_span(&push, s0, n_span, state, r, b, bd, s);
+            if (st != LW_OK) return st;
+            lw_traj_t sub = *t;
+            sub.kind = LW_TRAJ_SAMPLES;
+            sub.span = 0;
+            sub.n_particles = nb;
+            sub.n_samples = n_span;
+            sub.r = r;
+            sub.beta = b;
+            sub.beta_dot = bd;
+            sub.init = nullptr;
+            sub.charge = t->charge ? t->charge + b0 : nullptr;
+            st = launch_deposit(&sub, gr, prec, fmask, geom, accumulate || b0 > 0 || s0 > 0, E, diag, ws, dep_bytes,
+                                s, s0);
+            if (st != LW_OK) return st;
+            if (s0 + n_span >= ns) break;
+            s0 += n_span - 1;  // the next span starts at this span's last sample
+        }
     }
     return LW_OK;
 }

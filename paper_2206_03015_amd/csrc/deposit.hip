@@ -141,7 +141,8 @@ DepWs carve(void *ws, int64_t n_p, int64_t ns)
 // per-particle max |r|^2 and the fast-path flag
 __global__ __launch_bounds__(256) void k_prepass(const double *__restrict__ r, const double *__restrict__ beta,
                                                  const double *__restrict__ beta_dot, int64_t n_samples,
-                                                 double t_start, double dt, double t0, double dt_obs, double inv_cdt,
+                                                 int64_t sample0, double t_start, double dt, double t0,
+                                                 double dt_obs, double inv_cdt,
                                                  double *__restrict__ alpha, int *__restrict__ pflag,
                                                  unsigned long long *__restrict__ rmax2)
 {
@@ -155,7 +156,8 @@ __global__ __launch_bounds__(256) void k_prepass(const double *__restrict__ r, c
     int bad = 0;
     for (int64_t i = i_begin + threadIdx.x; i < i_end; i += blockDim.x) {
         const int64_t s = k * n_samples + i;
-        const double ai = ((t_start + (double)i * dt) - t0) / dt_obs;
+        // sample i of the arrays is sample sample0 + i of the trajectory (spans of a longer one)
+        const double ai = ((t_start + (double)(sample0 + i) * dt) - t0) / dt_obs;
         if (k == 0) alpha[i] = ai;
         const double *ri = r + 3 * s, *bi = beta + 3 * s, *di = beta_dot + 3 * s;
         const double x = ri[0], y = ri[1], z = ri[2];
@@ -716,7 +718,7 @@ size_t deposit_ws_bytes(int64_t n_particles, int64_t n_samples)
 }
 
 lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int fmask, int geom, bool accumulate,
-                         void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s)
+                         void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s, int64_t sample0)
 {
     const int64_t n_p = t->n_particles, ns = t->n_samples, n_pix = gr->n_pix, n_obs = gr->n_obs;
     const bool cull = (geom & LW_CULL) != 0;
@@ -762,7 +764,7 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
     k_fill<unsigned long long><<<fill_blocks, 256, 0, s>>>(w.rmax2, n_p);
     {
         k_prepass<<<dim3((unsigned)n_p, (unsigned)chunks), 256, 0, s>>>(
-            t->r, t->beta, t->beta_dot, ns, t->t_start, t->dt, gr->t0, gr->dt_obs, inv_cdt, w.alpha, w.pflag,
+            t->r, t->beta, t->beta_dot, ns, sample0, t->t_start, t->dt, gr->t0, gr->dt_obs, inv_cdt, w.alpha, w.pflag,
             w.rmax2);
     }
     unsigned long long *dg = (unsigned long long *)diag;

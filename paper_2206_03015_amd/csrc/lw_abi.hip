@@ -1,6 +1,7 @@
 // extern "C" entry points of liblw.so: argument validation, workspace checks, dispatch.
 #include "lw_internal.h"
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -45,7 +46,7 @@ lw_status check_traj_samples(const lw_traj_t *t, const char *fn)
     if (!t) return fail(LW_E_ARG, "%s: traj is NULL", fn);
     if (t->kind != LW_TRAJ_SAMPLES)
         return fail(LW_E_UNSUPPORTED, "%s: traj->kind must be LW_TRAJ_SAMPLES", fn);
-    if (t->reserved != 0) return fail(LW_E_ARG, "%s: traj->reserved must be 0", fn);
+    if (t->span != 0) return fail(LW_E_ARG, "%s: traj->span must be 0 for stored samples", fn);
     if (t->n_particles < 0 || t->n_samples < 1 || t->n_samples >= kMaxSamples)
         return fail(LW_E_SHAPE, "%s: need n_particles >= 0 and 1 <= n_samples < 2^31 (got %lld, %lld)", fn,
                     (long long)t->n_particles, (long long)t->n_samples);
@@ -76,11 +77,13 @@ lw_status check_grid(const lw_grid_t *g, const char *fn, bool need_grid)
 
 bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
-lw_status check_traj_boris(const lw_traj_t *t, const char *fn)
+// spans: whether this call pushes in spans (lw_deposit_td), where traj->span may be >= 2
+lw_status check_traj_boris(const lw_traj_t *t, const char *fn, bool spans = false)
 {
     if (!t) return fail(LW_E_ARG, "%s: traj is NULL", fn);
     if (t->kind != LW_TRAJ_BORIS) return fail(LW_E_ARG, "%s: traj->kind must be LW_TRAJ_BORIS", fn);
-    if (t->reserved != 0) return fail(LW_E_ARG, "%s: traj->reserved must be 0", fn);
+    if (t->span != 0 && !(spans && t->span >= 2))
+        return fail(LW_E_ARG, "%s: traj->span must be 0%s", fn, spans ? " or >= 2" : "");
     if (t->n_particles < 0 || t->n_particles > (int64_t(1) << 28) || t->n_samples < 1 || t->n_samples >= kMaxSamples)
         return fail(LW_E_SHAPE, "%s: bad sizes", fn);
     if (!finite_pos(t->dt) || !(t->t_start > -1e300 && t->t_start < 1e300))
@@ -119,7 +122,7 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec)
     case LW_WS_DIRECT_FD_BWD:
         return direct_fd_ws_bytes(n_a, n_b);
     case LW_WS_DEPOSIT_BORIS:
-        return boris_stream_ws_bytes(n_a, n_b, boris_batch_default(n_a, n_b, 3), 3);
+        return n_b >= 1 ? boris_plan_ws_bytes(boris_plan_default(n_a, n_b)) : 0;
     case LW_WS_DEPOSIT_BWD_BORIS:
         return boris_stream_ws_bytes(n_a, n_b, boris_batch_default(n_a, n_b, 6), 6);
     default:
@@ -132,7 +135,7 @@ lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, 
 {
     const char *fn = "lw_deposit_td";
     const bool boris = traj && traj->kind == LW_TRAJ_BORIS;
-    lw_status st = boris ? check_traj_boris(traj, fn) : check_traj_samples(traj, fn);
+    lw_status st = boris ? check_traj_boris(traj, fn, true) : check_traj_samples(traj, fn);
     if (st != LW_OK) return st;
     if ((st = check_grid(grid, fn, true)) != LW_OK) return st;
     if (prec != LW_PREC_FP64 && prec != LW_PREC_MIXED) return fail(LW_E_ARG, "%s: unknown prec %d", fn, prec);
@@ -150,9 +153,11 @@ lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, 
     if (ws && !aligned(ws, 256)) return fail(LW_E_ALIGN, "%s: workspace must be 256-byte aligned", fn);
     if (boris) {
         const bool work = traj->n_particles > 0 && grid->n_pix > 0;
-        if (work && (!ws || boris_batch_fit(traj->n_particles, traj->n_samples, ws_bytes, 3) < 1))
-            return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes holds no batch (one particle needs %zu)", fn,
-                        ws_bytes, boris_stream_ws_bytes(1, traj->n_samples, 1, 3));
+        const BorisPlan plan = boris_plan_fit(traj->n_particles, traj->n_samples, traj->span, ws_bytes);
+        const int64_t lmin = std::min<int64_t>(traj->n_samples, 2);
+        if (work && (!ws || plan.batch < 1 || plan.span < lmin))
+            return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes holds no span (one particle needs %zu)", fn,
+                        ws_bytes, boris_plan_ws_bytes(BorisPlan{1, traj->span > 0 ? traj->span : lmin}));
         return launch_deposit_boris(traj, grid, prec, field_mask, gc, acc, E, diag, ws, ws_bytes, stream);
     }
     const size_t need = deposit_ws_bytes(traj->n_particles, traj->n_samples);
@@ -203,6 +208,7 @@ lw_status lw_trajectory_boris(const lw_traj_t *traj, double *r, double *beta, do
     const char *fn = "lw_trajectory_boris";
     if (!traj) return fail(LW_E_ARG, "%s: traj is NULL", fn);
     if (traj->kind != LW_TRAJ_BORIS) return fail(LW_E_ARG, "%s: traj->kind must be LW_TRAJ_BORIS", fn);
+    if (traj->span != 0) return fail(LW_E_ARG, "%s: traj->span must be 0", fn);
     if (traj->n_particles < 0 || traj->n_samples < 1 || traj->n_samples >= (int64_t(1) << 31))
         return fail(LW_E_SHAPE, "%s: bad sizes", fn);
     if (!finite_pos(traj->dt)) return fail(LW_E_ARG, "%s: dt must be positive and finite", fn);
@@ -223,6 +229,7 @@ lw_status lw_trajectory_boris_bwd(const lw_traj_t *traj, const double *g_r, cons
     const char *fn = "lw_trajectory_boris_bwd";
     if (!traj) return fail(LW_E_ARG, "%s: traj is NULL", fn);
     if (traj->kind != LW_TRAJ_BORIS) return fail(LW_E_ARG, "%s: traj->kind must be LW_TRAJ_BORIS", fn);
+    if (traj->span != 0) return fail(LW_E_ARG, "%s: traj->span must be 0", fn);
     if (traj->n_particles < 0 || traj->n_samples < 1 || traj->n_samples >= (int64_t(1) << 31) ||
         traj->n_particles > (int64_t(1) << 28))
         return fail(LW_E_SHAPE, "%s: bad sizes", fn);

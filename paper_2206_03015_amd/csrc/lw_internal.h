@@ -265,8 +265,11 @@ __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
 // host-side launch helpers (defined in the kernel files)
+// sample0: index of the first sample of traj within a longer trajectory (its arrival times use
+// t_start + (sample0 + i) dt); 0 for whole trajectories
 lw_status launch_deposit(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom,
-                         bool accumulate, void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s);
+                         bool accumulate, void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s,
+                         int64_t sample0 = 0);
 size_t deposit_ws_bytes(int64_t n_particles, int64_t n_samples);
 lw_status launch_fft(const void *E, int64_t n_pix, int64_t n_obs, double dt_obs, int prec, void *S, void *ws,
                      size_t ws_bytes, hipStream_t s);
@@ -280,12 +283,23 @@ lw_status launch_direct_fd_bwd(const lw_traj_t *traj, const lw_grid_t *grid, con
                                double *d_beta_dot, void *ws, size_t ws_bytes, hipStream_t s);
 size_t direct_fd_ws_bytes(int64_t n_pix, int64_t n_omega);
 lw_status launch_boris(const lw_traj_t *traj, double *r, double *beta, double *beta_dot, hipStream_t s);
+// samples s0 .. s0 + n_span - 1 of every particle of traj (LW_TRAJ_BORIS), starting from init
+// (s0 = 0) or from the pusher state [n_particles][9] left by the span that ended at sample s0
+lw_status launch_boris_span(const lw_traj_t *traj, int64_t s0, int64_t n_span, double *state, double *r,
+                            double *beta, double *beta_dot, hipStream_t s);
 lw_status launch_boris_bwd(const lw_traj_t *traj, const double *g_r, const double *g_beta,
                            const double *g_beta_dot, double *grad_init, double *grad_a0, hipStream_t s);
 lw_status launch_deposit_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int field_mask, int geom, const double *dE,
                              double *d_r, double *d_beta, double *d_beta_dot, hipStream_t s);
-// trajectories recomputed batch by batch from LW_TRAJ_BORIS initial conditions (boris_stream.hip);
-// `arrays` = 3 for the forward batch buffers (r, beta, beta_dot), 6 for the adjoint (plus gradients)
+// trajectories recomputed from LW_TRAJ_BORIS initial conditions (boris_stream.hip).  The forward
+// deposit pushes batches of particles over spans of samples; the adjoint pushes whole
+// trajectories batch by batch (6 arrays: samples and their gradients).
+struct BorisPlan {
+    int64_t batch, span;  // particles per batch, samples per span (spans share their boundary sample)
+};
+BorisPlan boris_plan_default(int64_t n_p, int64_t ns);
+BorisPlan boris_plan_fit(int64_t n_p, int64_t ns, int64_t span_req, size_t ws_bytes);
+size_t boris_plan_ws_bytes(const BorisPlan &p);
 int64_t boris_batch_default(int64_t n_p, int64_t ns, int arrays);
 size_t boris_stream_ws_bytes(int64_t n_p, int64_t ns, int64_t batch, int arrays);
 int64_t boris_batch_fit(int64_t n_p, int64_t ns, size_t ws_bytes, int arrays);

@@ -37,7 +37,7 @@ class Laser(ctypes.Structure):
 
 
 class Traj(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n_particles", c_i64),
+    _fields_ = [("kind", ctypes.c_int32), ("span", ctypes.c_int32), ("n_particles", c_i64),
                 ("n_samples", c_i64), ("t_start", c_d), ("dt", c_d), ("r", c_vp), ("beta", c_vp),
                 ("beta_dot", c_vp), ("init", c_vp), ("laser", Laser), ("charge", c_vp)]
 
@@ -135,7 +135,7 @@ def make_traj(r, beta, beta_dot, t_start, dt, charge=None):
         _need(charge, torch.float64, (n_p,), "charge")
     tr = Traj()
     tr.kind = TRAJ_SAMPLES
-    tr.reserved = 0
+    tr.span = 0
     tr.n_particles = n_p
     tr.n_samples = ns
     tr.t_start = float(t_start)
@@ -220,7 +220,7 @@ def make_boris_traj(init, n_samples, t_start, dt, a0, lam, w0, n_cycles):
     _need(init, torch.float64, (n_p, 6), "init")
     tr = Traj()
     tr.kind = TRAJ_BORIS
-    tr.reserved = 0
+    tr.span = 0
     tr.n_particles = n_p
     tr.n_samples = int(n_samples)
     tr.t_start = float(t_start)
@@ -316,11 +316,13 @@ def direct_fd_bwd(r, beta, beta_dot, t_start, dt, x_det, t0, omega, dS, field_ma
 
 def deposit_td_boris(init, n_samples, t_start, dt, a0, lam, w0, n_cycles, x_det, t0, dt_obs, n_obs, prec="mixed",
                      field_mask=FIELD_ACCEL, geom="exact", charge=None, out=None, accumulate=False, diag=None, ws=None,
-                     cull=False):
-    """lw_deposit_td with LW_TRAJ_BORIS: trajectories recomputed inside the call from init [n_p][6]
-    in batches.  Returns (E, diag)."""
+                     cull=False, span=0):
+    """lw_deposit_td with LW_TRAJ_BORIS: trajectories recomputed inside the call from init [n_p][6],
+    a batch of particles over a span of samples at a time (span=0: chosen from the workspace).
+    Returns (E, diag)."""
     lib = load()
     tr = make_boris_traj(init, n_samples, t_start, dt, a0, lam, w0, n_cycles)
+    tr.span = int(span)
     if charge is not None:
         _need(charge, torch.float64, (int(init.shape[0]),), "charge")
         tr.charge = c_vp(charge.data_ptr())

@@ -54,7 +54,7 @@ def test_workspace_sizes(lib):
     assert fft >= 3 * (1 << 12) * 16 and fft % (3 * (1 << 12) * 16) == 0
     assert lw.workspace_bytes(lw.WS_DIRECT_FD, 3, 5) >= 3 * 5 * 6 * 8
     assert lw.workspace_bytes(lw.WS_DIRECT_FD_BWD, 3, 5, "fp64") == lw.workspace_bytes(lw.WS_DIRECT_FD, 3, 5)
-    # Boris batches: the whole set when small, capped near 16 GiB when large
+    # Boris batches and spans: the whole set when small, capped near 16 GiB when large
     small = lw.workspace_bytes(lw.WS_DEPOSIT_BORIS, 10, 1000)
     assert small >= 10 * 1000 * 72
     big = lw.workspace_bytes(lw.WS_DEPOSIT_BORIS, 100000, 20001)
@@ -117,4 +117,22 @@ def test_host_validation_rejects_bad_arguments(lib):
     tb.n_samples = 10
     tb.dt = 1e-18
     assert lib.lw_trajectory_boris_bwd(ctypes.byref(tb), p, p, p, p, p, None) == -1  # kind must be BORIS
+    # traj->span: 0 for stored samples and for every call but lw_deposit_td, 0 or >= 2 there
+    tr.span = 5
+    assert lib.lw_deposit_td(ctypes.byref(tr), ctypes.byref(gr), 0, 1, 0, p, None, None, 0, None) == -1
+    assert b"span" in lib.lw_last_error()
+    tr.span = 0
+    tb.kind = lw.TRAJ_BORIS
+    tb.laser.lam, tb.laser.n_cycles = 1e-6, 10.0
+    tb.init = p
+    for span in (1, -3):
+        tb.span = span
+        assert lib.lw_deposit_td(ctypes.byref(tb), ctypes.byref(gr), 0, 1, 0, p, None, None, 0, None) == -1
+        assert b"span" in lib.lw_last_error()
+    tb.span = 2  # accepted; the missing workspace is reported next
+    assert lib.lw_deposit_td(ctypes.byref(tb), ctypes.byref(gr), 0, 1, 0, p, None, None, 0, None) == -4
+    assert lib.lw_trajectory_boris(ctypes.byref(tb), p, p, p, None) == -1
+    assert b"span" in lib.lw_last_error()
+    assert lib.lw_trajectory_boris_bwd(ctypes.byref(tb), p, p, p, p, p, None) == -1
+    assert b"span" in lib.lw_last_error()
     assert lib.lw_version().startswith(b"liblw")

@@ -1,5 +1,6 @@
-"""LW_TRAJ_BORIS: lw_deposit_td recomputing the trajectories batch by batch inside the call,
-and lw_deposit_td_bwd_boris, against the same computation on stored trajectories and
+"""LW_TRAJ_BORIS: lw_deposit_td recomputing the trajectories inside the call (a batch of
+particles over a span of samples at a time) and lw_deposit_td_bwd_boris (batches of whole
+trajectories), against the same computation on stored trajectories and
 against the oracle at the shapes of the large workload (gamma = 100, 64 x 64 pixels, 2^20
 grid) and of the precision workload (gamma = 200, a0 = 1, 128 x 128 pixels, 2^18 grid at 16
 samples per period, harmonics 1..5)."""
@@ -46,6 +47,51 @@ def test_stream_equals_stored_trajectories(prec, per_batch):
                                c["n_obs"])
     assert np.max(np.abs(Es - Ew)) <= (1e-9 if prec == "fp64" else 2e-5) * np.max(np.abs(Ew))
     assert ds.tolist() == list(dw)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("span", [2, 3, 64, 1000])
+def test_stream_spans_equal_stored_trajectories(prec, span):
+    """LW_TRAJ_BORIS pushed over spans of `span` samples (neighbouring spans share their boundary
+    sample and the pusher's state carries over; span 2 deposits one interval per launch): the
+    trace and the counters equal those of the stored trajectories of lw_trajectory_boris."""
+    from paper_2206_03015_amd import lw
+    c = small_bunch(n_p=24, n_steps=3000, n_side=10, n_obs=1 << 12)
+    W, L = c["W"], c["W"].laser
+    init = T(c["init"])
+    args = (W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
+    Es, ds = lw.deposit_td_boris(init, *args, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], prec=prec, span=span)
+    r, b, bd = lw.trajectory_boris(init, *args)
+    Eo, do = lw.deposit_td(r, b, bd, W.t_start, W.dt, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], prec=prec)
+    torch.cuda.synchronize()
+    Es, Eo = Es.double().cpu().numpy(), Eo.double().cpu().numpy()
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert np.max(np.abs(Es - Eo)) <= tol * np.max(np.abs(Eo))
+    assert ds.tolist() == do.tolist()
+    assert int(do[3]) > 0
+
+
+def test_stream_long_trajectory_small_workspace():
+    """2e5 samples per particle through a workspace that holds 1024-sample spans of the four
+    particles: ~200 spans with the pusher's state carried across all of them, against the
+    deposit of the stored trajectories (FP64) and the oracle's counters."""
+    from paper_2206_03015_amd import lw
+    c = small_bunch(n_p=4, n_steps=200000, n_side=4, n_obs=1 << 14)
+    W, L = c["W"], c["W"].laser
+    init = T(c["init"])
+    args = (W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
+    ws = small_ws(lw, lw.WS_DEPOSIT_BORIS, 4, 1024)
+    assert ws.numel() < 4 * W.n_samples * 72 / 100
+    Es, ds = lw.deposit_td_boris(init, *args, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], prec="fp64", ws=ws)
+    r, b, bd = lw.trajectory_boris(init, *args)
+    Eo, do = lw.deposit_td(r, b, bd, W.t_start, W.dt, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], prec="fp64")
+    torch.cuda.synchronize()
+    Es, Eo = Es.cpu().numpy(), Eo.cpu().numpy()
+    assert np.max(np.abs(Es - Eo)) <= 1e-12 * np.max(np.abs(Eo))
+    assert ds.tolist() == do.tolist()
+    _, dw = oracle.deposit_td(W.t_start, W.dt, c["r"], c["beta"], c["beta_dot"], c["x_det"], c["t0"], c["dt_obs"],
+                              c["n_obs"])
+    assert ds.tolist() == list(dw) and int(dw[3]) > 0
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
