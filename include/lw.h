@@ -95,7 +95,8 @@ typedef struct {
 typedef struct {
     int32_t kind;          /* LW_TRAJ_SAMPLES or LW_TRAJ_BORIS                          */
     int32_t span;          /* 0, or >= 2: samples per pushed span of an LW_TRAJ_BORIS     */
-                           /* lw_deposit_td (0: chosen from the workspace); 0 elsewhere  */
+                           /* deposit or its adjoint (0: chosen from the workspace);     */
+                           /* 0 elsewhere                                                */
     int64_t n_particles;   /* >= 0                                                       */
     int64_t n_samples;     /* >= 1  (= N_s + 1 in the paper's notation)                  */
     double t_start, dt;    /* s; dt > 0                                                  */
@@ -134,8 +135,8 @@ typedef struct {
  * the pushed batches and spans of LW_TRAJ_BORIS deposits (~16 GiB at most by
  * default: min(n_particles, 65536) particles over the longest spans that fit);
  * any workspace that holds a two-sample span of one particle is accepted and
- * sets batch and span.  LW_WS_DEPOSIT_BWD_BORIS sizes the adjoint's batches of
- * whole trajectories (any workspace holding one is accepted).  Returns 0 for
+ * sets batch and span.  LW_WS_DEPOSIT_BWD_BORIS does the same for the adjoint
+ * (min(n_particles, 16384) particles, seven tangents each).  Returns 0 for
  * an unknown `which`.  Larger workspaces are accepted; for the FFT a larger
  * workspace lets more pixels be transformed per pass.
  */
@@ -289,11 +290,14 @@ lw_status lw_deposit_td_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int pr
  * given dE = dJ/dE_tot (double [n_pix][3][n_obs]), writes
  *   grad_init[k][c] = dJ/d init[k][c]   [n_particles][6]  (overwritten)
  *   grad_a0[k]      = particle k's part of dJ/d a0 [n_particles] (overwritten)
- * For each batch of particles it recomputes the samples (lw_trajectory_boris),
- * runs the sample adjoint (lw_deposit_td_bwd) into the workspace and contracts it
- * with the pusher's tangents (lw_trajectory_boris_bwd).  prec: FP64 only.
+ * For a batch of particles over a span of samples at a time (spans as in
+ * lw_deposit_td: shared boundary samples, pusher and tangent states carried
+ * over; traj->span = 0 lets the workspace choose, >= 2 fixes it) it recomputes
+ * the samples, runs the sample adjoint (lw_deposit_td_bwd) over the span's
+ * intervals into the workspace and contracts it with the pusher's tangents
+ * (lw_trajectory_boris_bwd) over the span.  prec: FP64 only.
  * ws: >= lw_workspace_bytes(LW_WS_DEPOSIT_BWD_BORIS, n_particles, n_samples, prec)
- * bytes, or any size that holds one particle's batch.
+ * bytes, or any size that holds a two-sample span of one particle.
  */
 lw_status lw_deposit_td_bwd_boris(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom,
                                   const void *dE, double *grad_init, double *grad_a0, void *ws, size_t ws_bytes,

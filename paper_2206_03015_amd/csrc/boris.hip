@@ -396,6 +396,69 @@ __global__ __launch_bounds__(64) void k_boris_tangent(const double *__restrict__
         grad_a0[k] = acc;
 }
 
+// The tangents over samples s0 .. s0 + n_span - 1 only: each lane starts from its seeded
+// initial state (s0 = 0) or from the dual-number state the previous span left at sample s0
+// ([lane][18]: the 9 state values, then their derivatives), contracts the span's gradients
+// g_* [n_particles][n_span][3], saves its state at the span's last sample, and writes (s0 = 0)
+// or adds its sum.  Spans share their boundary sample; the gradients of a boundary sample are
+// split between the two spans' deposit adjoints (each gathers its own intervals), so the two
+// contractions add up to the whole.
+constexpr int kTanStateDoubles = 18;
+
+__global__ __launch_bounds__(64) void k_boris_tangent_span(const double *__restrict__ init, int64_t n_particles,
+                                                           int64_t s0, int64_t n_span, double t_start, double dt,
+                                                           LaserDev L, double *__restrict__ tstate,
+                                                           const double *__restrict__ g_r,
+                                                           const double *__restrict__ g_b,
+                                                           const double *__restrict__ g_a,
+                                                           double *__restrict__ grad_init,
+                                                           double *__restrict__ grad_a0)
+{
+    using D = Dual<1>;
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n_particles * kParams) return;
+    const int64_t k = l / kParams;
+    const int p = (int)(l - k * kParams);
+    D a0(L.a0);
+    a0.d[0] = (p == 6) ? 1.0 : 0.0;
+    PushState<D> S;
+    double *st = tstate + kTanStateDoubles * l;
+    if (s0 == 0) {
+        D in[6];
+        for (int c = 0; c < 6; ++c) {
+            in[c] = D(init[6 * k + c]);
+            in[c].d[0] = (c == p) ? 1.0 : 0.0;
+        }
+        push_start(L, a0, in, t_start, dt, S);
+    } else {
+        D *f[9] = {&S.x, &S.y, &S.z, &S.usx, &S.usy, &S.usz, &S.uhx, &S.uhy, &S.uhz};
+        for (int c = 0; c < 9; ++c) {
+            f[c]->v = st[c];
+            f[c]->d[0] = st[9 + c];
+        }
+        // the same arguments as the step that reached sample s0: the same field and derivative
+        laser_eb(L, a0, S.x, S.y, S.z, t_start + (double)s0 * dt, S.Ex, S.By);
+    }
+    double acc = 0.0;
+    for (int64_t j = 0; j < n_span; ++j) {
+        D rr[3], bb[3], aa[3];
+        push_sample(S, rr, bb, aa);
+        const size_t o = (size_t)(k * n_span + j) * 3;
+        for (int c = 0; c < 3; ++c) acc += g_r[o + c] * rr[c].d[0] + g_b[o + c] * bb[c].d[0] + g_a[o + c] * aa[c].d[0];
+        if (j + 1 == n_span) break;
+        push_step(L, a0, t_start + (double)(s0 + j + 1) * dt, dt, S);
+    }
+    {
+        const D *f[9] = {&S.x, &S.y, &S.z, &S.usx, &S.usy, &S.usz, &S.uhx, &S.uhy, &S.uhz};
+        for (int c = 0; c < 9; ++c) {
+            st[c] = f[c]->v;
+            st[9 + c] = f[c]->d[0];
+        }
+    }
+    double *out = p < 6 ? grad_init + 6 * k + p : grad_a0 + k;
+    *out = s0 == 0 ? acc : *out + acc;
+}
+
 LaserDev laser_dev(const lw_laser_t &l)
 {
     LaserDev L;
@@ -428,6 +491,19 @@ lw_status launch_boris_span(const lw_traj_t *t, int64_t s0, int64_t n_span, doub
     k_boris_span<<<(unsigned)blocks, 64, 0, s>>>(t->init, t->n_particles, s0, n_span, t->t_start, t->dt, L, state, r,
                                                 beta, beta_dot);
     return check_launch("lw_deposit_td (pusher span)");
+}
+
+lw_status launch_boris_bwd_span(const lw_traj_t *t, int64_t s0, int64_t n_span, double *tstate, const double *g_r,
+                                const double *g_beta, const double *g_beta_dot, double *grad_init, double *grad_a0,
+                                hipStream_t s)
+{
+    if (t->n_particles == 0 || n_span == 0) return LW_OK;
+    const LaserDev L = laser_dev(t->laser);
+    const int64_t lanes = t->n_particles * kParams;
+    const int64_t blocks = (lanes + 63) / 64;
+    k_boris_tangent_span<<<(unsigned)blocks, 64, 0, s>>>(t->init, t->n_particles, s0, n_span, t->t_start, t->dt, L,
+                                                        tstate, g_r, g_beta, g_beta_dot, grad_init, grad_a0);
+    return check_launch("lw_deposit_td_bwd_boris (tangent span)");
 }
 
 lw_status launch_boris_bwd(const lw_traj_t *t, const double *g_r, const double *g_beta, const double *g_beta_dot,

@@ -6,7 +6,9 @@
 // (accumulating after the first) and reuses the space for the next span: spans share their
 // boundary sample, the pusher's state (position and the two momenta) is kept between them, so
 // the samples are those of one uninterrupted push and the trajectory length is unbounded.
-// The adjoint pushes whole trajectories, batch by batch of particles.
+// The adjoint takes the same spans: per span the samples, the deposit adjoint over the span's
+// intervals, then the pusher's tangents over the span, their dual-number state kept between
+// spans like the pusher's.
 #include "lw_internal.h"
 
 #include <algorithm>
@@ -14,7 +16,7 @@
 namespace lw {
 namespace {
 
-// default trajectory budget (all three sample arrays of a batch)
+// default workspace budget of a plan
 constexpr size_t kBatchBytes = size_t(16) << 30;
 // the pusher runs one lane per particle through every step of a span, so its time is the
 // per-step latency of one wavefront times the span length for up to one wavefront per SIMD
@@ -25,38 +27,41 @@ constexpr int64_t kMinSpan = 1024;
 // longest span one deposit launch takes (its pre-pass grid covers 8192 samples per block row)
 constexpr int64_t kMaxSpan = int64_t(1) << 28;
 constexpr int kStateBytes = 9 * sizeof(double);
+// the adjoint runs seven tangent lanes per particle: batches of up to ~1.75 wavefronts per SIMD
+constexpr int64_t kFillParticlesBwd = 16384;
+constexpr int kTanStateBytes = 7 * 18 * sizeof(double);
 
 inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
-// bytes of one particle's batch buffers: `arrays` sample arrays of [n_samples][3] doubles
-inline size_t per_particle(int64_t ns, int arrays) { return align256((size_t)ns * 3 * sizeof(double)) * arrays; }
-
-// workspace of a forward plan: deposit scratch, pusher states, r, beta, beta_dot of the span
-size_t plan_bytes(int64_t B, int64_t L)
+// workspace of a plan.  Forward: deposit scratch, pusher states, r, beta, beta_dot of the span.
+// Adjoint (bwd): tangent states, pusher states, the span's samples and their gradients.
+size_t plan_bytes(int64_t B, int64_t L, bool bwd)
 {
-    return align256(deposit_ws_bytes(B, L)) + align256((size_t)B * kStateBytes) +
-           3 * align256((size_t)B * (size_t)L * 3 * sizeof(double));
+    const size_t arr = align256((size_t)B * (size_t)L * 3 * sizeof(double));
+    if (bwd) return align256((size_t)B * kTanStateBytes) + align256((size_t)B * kStateBytes) + 6 * arr;
+    return align256(deposit_ws_bytes(B, L)) + align256((size_t)B * kStateBytes) + 3 * arr;
 }
 
 // longest span (<= lmax) of B particles within `bytes` (0 if not even one sample fits)
-int64_t fit_span(int64_t B, int64_t lmax, size_t bytes)
+int64_t fit_span(int64_t B, int64_t lmax, size_t bytes, bool bwd)
 {
-    const size_t fixed = plan_bytes(B, 1);
+    const size_t fixed = plan_bytes(B, 1, bwd);
     if (fixed > bytes) return 0;
-    const size_t per_sample = (size_t)B * 72 + sizeof(double);
+    const size_t per_sample = (size_t)B * (bwd ? 144 : 72) + sizeof(double);
     int64_t L = std::min<int64_t>(lmax, 1 + (int64_t)((bytes - fixed) / per_sample));
-    while (L > 1 && plan_bytes(B, L) > bytes) --L;
+    while (L > 1 && plan_bytes(B, L, bwd) > bytes) --L;
     return L;
 }
 
 // largest batch (<= bmax) with spans of L samples within `bytes` (0 if none)
-int64_t fit_batch(int64_t bmax, int64_t L, size_t bytes)
+int64_t fit_batch(int64_t bmax, int64_t L, size_t bytes, bool bwd)
 {
-    const size_t fixed = plan_bytes(1, L);
+    const size_t fixed = plan_bytes(1, L, bwd);
     if (fixed > bytes) return 0;
-    const size_t per_particle_bytes = (size_t)L * 72 + kStateBytes + 2 * sizeof(double);
+    const size_t per_particle_bytes =
+        bwd ? (size_t)L * 144 + kTanStateBytes + kStateBytes : (size_t)L * 72 + kStateBytes + 2 * sizeof(double);
     int64_t B = std::min<int64_t>(bmax, 1 + (int64_t)((bytes - fixed) / per_particle_bytes));
-    while (B > 1 && plan_bytes(B, L) > bytes) --B;
+    while (B > 1 && plan_bytes(B, L, bwd) > bytes) --B;
     return B;
 }
 
@@ -71,57 +76,35 @@ __global__ void k_zero(double *__restrict__ p, int64_t n)
 // Batch and span from the workspace: batches of min(n_p, kFillParticles) particles over the
 // longest spans that fit (whole trajectories when they do); spans shorter than kMinSpan give
 // way to smaller batches; a requested span fixes L and leaves the batch to the workspace.
-BorisPlan boris_plan_fit(int64_t n_p, int64_t ns, int64_t span_req, size_t ws_bytes)
+BorisPlan boris_plan_fit(int64_t n_p, int64_t ns, int64_t span_req, size_t ws_bytes, bool bwd)
 {
-    const int64_t b0 = std::max<int64_t>(1, std::min<int64_t>(n_p, kFillParticles));
+    const int64_t b0 = std::max<int64_t>(1, std::min<int64_t>(n_p, bwd ? kFillParticlesBwd : kFillParticles));
     const int64_t lmax = std::min<int64_t>(ns, kMaxSpan);
     const int64_t lmin = std::min<int64_t>(lmax, 2);  // a span must advance (one interval at least)
     if (span_req > 0) {
         const int64_t L = std::max<int64_t>(lmin, std::min<int64_t>(span_req, lmax));
-        return {fit_batch(b0, L, ws_bytes), L};
+        return {fit_batch(b0, L, ws_bytes, bwd), L};
     }
-    const int64_t L0 = fit_span(b0, lmax, ws_bytes);
+    const int64_t L0 = fit_span(b0, lmax, ws_bytes, bwd);
     if (L0 >= std::min<int64_t>(lmax, kMinSpan)) return {b0, L0};
     const int64_t Lm = std::min<int64_t>(lmax, kMinSpan);
-    const int64_t B = fit_batch(b0, Lm, ws_bytes);
+    const int64_t B = fit_batch(b0, Lm, ws_bytes, bwd);
     if (B >= 1) return {B, Lm};
-    const int64_t L1 = fit_span(1, lmax, ws_bytes);
+    const int64_t L1 = fit_span(1, lmax, ws_bytes, bwd);
     if (L1 >= lmin) return {1, L1};
     return {0, 0};
 }
 
-BorisPlan boris_plan_default(int64_t n_p, int64_t ns)
+BorisPlan boris_plan_default(int64_t n_p, int64_t ns, bool bwd)
 {
-    const BorisPlan p = boris_plan_fit(n_p, ns, 0, kBatchBytes);
+    const BorisPlan p = boris_plan_fit(n_p, ns, 0, kBatchBytes, bwd);
     // a budget too small for even one particle's two-sample span cannot happen at 16 GiB
     return p.batch > 0 ? p : BorisPlan{1, std::min<int64_t>(ns, 2)};
 }
 
-size_t boris_plan_ws_bytes(const BorisPlan &p) { return plan_bytes(std::max<int64_t>(p.batch, 1), p.span); }
-
-int64_t boris_batch_default(int64_t n_p, int64_t ns, int arrays)
+size_t boris_plan_ws_bytes(const BorisPlan &p, bool bwd)
 {
-    const int64_t b = (int64_t)(kBatchBytes / per_particle(ns, arrays));
-    return std::max<int64_t>(1, std::min<int64_t>(n_p, b));
-}
-
-size_t boris_stream_ws_bytes(int64_t n_p, int64_t ns, int64_t batch, int arrays)
-{
-    const size_t dep = arrays == 3 ? deposit_ws_bytes(batch, ns) : 0;
-    return align256(dep) + (size_t)batch * per_particle(ns, arrays);
-}
-
-// largest batch that fits ws_bytes (0 if none does)
-int64_t boris_batch_fit(int64_t n_p, int64_t ns, size_t ws_bytes, int arrays)
-{
-    int64_t b = boris_batch_default(n_p, ns, arrays);
-    while (b > 0 && boris_stream_ws_bytes(n_p, ns, b, arrays) > ws_bytes) {
-        const size_t pp = per_particle(ns, arrays);
-        const size_t fixed = boris_stream_ws_bytes(n_p, ns, 0, arrays) + 4096;
-        const int64_t guess = ws_bytes > fixed ? (int64_t)((ws_bytes - fixed) / (pp + 64)) : 0;
-        b = std::min<int64_t>(b - 1, guess);
-    }
-    return std::max<int64_t>(b, 0);
+    return plan_bytes(std::max<int64_t>(p.batch, 1), p.span, bwd);
 }
 
 lw_status launch_deposit_boris(const lw_traj_t *t, const lw_grid_t *gr, int prec, int fmask, int geom,
@@ -178,39 +161,52 @@ lw_status launch_deposit_bwd_boris(const lw_traj_t *t, const lw_grid_t *gr, int 
 {
     const int64_t n_p = t->n_particles, ns = t->n_samples;
     if (n_p == 0) return LW_OK;
-    if (gr->n_pix == 0) {  // no pixels: the gradient is zero
+    if (gr->n_pix == 0 || ns < 2) {  // no pixels or no interval: the gradient is zero
         k_zero<<<(int)std::min<int64_t>((6 * n_p + 255) / 256, 65536), 256, 0, s>>>(grad_init, 6 * n_p);
         k_zero<<<(int)std::min<int64_t>((n_p + 255) / 256, 65536), 256, 0, s>>>(grad_a0, n_p);
         return check_launch("lw_deposit_td_bwd_boris");
     }
-    const int64_t B = boris_batch_fit(n_p, ns, ws_bytes, 6);
-    if (B < 1) return fail(LW_E_WORKSPACE, "lw_deposit_td_bwd_boris: workspace holds no trajectory batch");
-    const size_t arr = align256((size_t)ns * 3 * sizeof(double)) * (size_t)B;
+    const BorisPlan P = boris_plan_fit(n_p, ns, t->span, ws_bytes, true);
+    if (P.batch < 1 || P.span < 2) return fail(LW_E_WORKSPACE, "lw_deposit_td_bwd_boris: workspace holds no span");
     char *p = (char *)ws;
+    double *tstate = (double *)p;
+    p += align256((size_t)P.batch * kTanStateBytes);
+    double *pstate = (double *)p;
+    p += align256((size_t)P.batch * kStateBytes);
+    const size_t arr = align256((size_t)P.batch * (size_t)P.span * 3 * sizeof(double));
     double *r = (double *)p, *b = (double *)(p + arr), *bd = (double *)(p + 2 * arr);
     double *gr_ = (double *)(p + 3 * arr), *gb = (double *)(p + 4 * arr), *ga = (double *)(p + 5 * arr);
-    for (int64_t b0 = 0; b0 < n_p; b0 += B) {
-        const int64_t nb = std::min<int64_t>(B, n_p - b0);
+    for (int64_t b0 = 0; b0 < n_p; b0 += P.batch) {
+        const int64_t nb = std::min<int64_t>(P.batch, n_p - b0);
         lw_traj_t push = *t;
         push.n_particles = nb;
         push.init = t->init + 6 * b0;
-        lw_status st = launch_boris(&push, r, b, bd, s);
-        if (st != LW_OK) return st;
-        const int64_t nz = nb * ns * 3;
-        for (double *z : {gr_, gb, ga})
-            k_zero<<<(int)std::min<int64_t>((nz + 255) / 256, 65536), 256, 0, s>>>(z, nz);
-        lw_traj_t sub = *t;
-        sub.kind = LW_TRAJ_SAMPLES;
-        sub.n_particles = nb;
-        sub.r = r;
-        sub.beta = b;
-        sub.beta_dot = bd;
-        sub.init = nullptr;
-        sub.charge = t->charge ? t->charge + b0 : nullptr;
-        st = launch_deposit_bwd(&sub, gr, fmask, geom, dE, gr_, gb, ga, s);
-        if (st != LW_OK) return st;
-        st = launch_boris_bwd(&push, gr_, gb, ga, grad_init + 6 * b0, grad_a0 + b0, s);
-        if (st != LW_OK) return st;
+        for (int64_t s0 = 0;;) {
+            const int64_t n_span = std::min<int64_t>(P.span, ns - s0);
+            // the span's samples, the deposit adjoint over its intervals (dJ/d samples), then
+            // the tangents of the same span contracted with them
+            lw_status st = launch_boris_span(&push, s0, n_span, pstate, r, b, bd, s);
+            if (st != LW_OK) return st;
+            const int64_t nz = nb * n_span * 3;
+            for (double *z : {gr_, gb, ga})
+                k_zero<<<(int)std::min<int64_t>((nz + 255) / 256, 65536), 256, 0, s>>>(z, nz);
+            lw_traj_t sub = *t;
+            sub.kind = LW_TRAJ_SAMPLES;
+            sub.span = 0;
+            sub.n_particles = nb;
+            sub.n_samples = n_span;
+            sub.r = r;
+            sub.beta = b;
+            sub.beta_dot = bd;
+            sub.init = nullptr;
+            sub.charge = t->charge ? t->charge + b0 : nullptr;
+            st = launch_deposit_bwd(&sub, gr, fmask, geom, dE, gr_, gb, ga, s, s0);
+            if (st != LW_OK) return st;
+            st = launch_boris_bwd_span(&push, s0, n_span, tstate, gr_, gb, ga, grad_init + 6 * b0, grad_a0 + b0, s);
+            if (st != LW_OK) return st;
+            if (s0 + n_span >= ns) break;
+            s0 += n_span - 1;  // the next span starts at this span's last sample
+        }
     }
     return check_launch("lw_deposit_td_bwd_boris");
 }

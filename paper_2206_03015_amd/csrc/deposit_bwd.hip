@@ -25,7 +25,7 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kOwned = 62;
 
 struct BwdShape {
-    int64_t n_particles, n_samples, n_pix, n_obs, n_chunks;
+    int64_t n_particles, n_samples, n_pix, n_obs, n_chunks, sample0;
     double t_start, dt, t0, dt_obs, inv_cdt;
     int fmask;
 };
@@ -66,7 +66,8 @@ __global__ __launch_bounds__(256) void k_deposit_bwd(const double *__restrict__ 
         usable = sample_usable(rs, bs, as);
     }
     const double rr = fma(rs[2], rs[2], fma(rs[1], rs[1], rs[0] * rs[0]));
-    const double alpha = ((sh.t_start + (double)i * sh.dt) - sh.t0) / sh.dt_obs;
+    // sample i of the arrays is sample sample0 + i of the trajectory (spans of a longer one)
+    const double alpha = ((sh.t_start + (double)(sh.sample0 + i) * sh.dt) - sh.t0) / sh.dt_obs;
     const double q = charge ? charge[k] : -kQe;
     const double nob = (double)sh.n_obs;
     double gr[3] = {0, 0, 0}, gb[3] = {0, 0, 0}, ga[3] = {0, 0, 0};
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(256) void k_deposit_bwd(const double *__restrict__ 
 }  // namespace
 
 lw_status launch_deposit_bwd(const lw_traj_t *t, const lw_grid_t *gr, int fmask, int geom, const double *dE,
-                             double *d_r, double *d_beta, double *d_beta_dot, hipStream_t s)
+                             double *d_r, double *d_beta, double *d_beta_dot, hipStream_t s, int64_t sample0)
 {
     if (t->n_particles == 0 || gr->n_pix == 0 || t->n_samples < 2) return LW_OK;
     BwdShape sh;
@@ -167,6 +168,7 @@ lw_status launch_deposit_bwd(const lw_traj_t *t, const lw_grid_t *gr, int fmask,
     sh.n_pix = gr->n_pix;
     sh.n_obs = gr->n_obs;
     sh.n_chunks = (t->n_samples + kOwned - 1) / kOwned;
+    sh.sample0 = sample0;
     sh.t_start = t->t_start;
     sh.dt = t->dt;
     sh.t0 = gr->t0;

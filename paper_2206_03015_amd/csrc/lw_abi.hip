@@ -77,7 +77,8 @@ lw_status check_grid(const lw_grid_t *g, const char *fn, bool need_grid)
 
 bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
-// spans: whether this call pushes in spans (lw_deposit_td), where traj->span may be >= 2
+// spans: whether this call pushes in spans (the deposit and its adjoint), where traj->span
+// may also be >= 2
 lw_status check_traj_boris(const lw_traj_t *t, const char *fn, bool spans = false)
 {
     if (!t) return fail(LW_E_ARG, "%s: traj is NULL", fn);
@@ -124,7 +125,7 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec)
     case LW_WS_DEPOSIT_BORIS:
         return n_b >= 1 ? boris_plan_ws_bytes(boris_plan_default(n_a, n_b)) : 0;
     case LW_WS_DEPOSIT_BWD_BORIS:
-        return boris_stream_ws_bytes(n_a, n_b, boris_batch_default(n_a, n_b, 6), 6);
+        return n_b >= 1 ? boris_plan_ws_bytes(boris_plan_default(n_a, n_b, true), true) : 0;
     default:
         return 0;
     }
@@ -289,7 +290,7 @@ lw_status lw_deposit_td_bwd_boris(const lw_traj_t *traj, const lw_grid_t *grid, 
                                   hipStream_t stream)
 {
     const char *fn = "lw_deposit_td_bwd_boris";
-    lw_status st = check_traj_boris(traj, fn);
+    lw_status st = check_traj_boris(traj, fn, true);
     if (st != LW_OK) return st;
     if ((st = check_grid(grid, fn, true)) != LW_OK) return st;
     if (prec == LW_PREC_MIXED) return fail(LW_E_UNSUPPORTED, "%s: only LW_PREC_FP64 is supported", fn);
@@ -302,9 +303,12 @@ lw_status lw_deposit_td_bwd_boris(const lw_traj_t *traj, const lw_grid_t *grid, 
     if ((dE && !aligned(dE, 16)) || (grad_init && !aligned(grad_init, 8)) || (grad_a0 && !aligned(grad_a0, 8)) ||
         (ws && !aligned(ws, 256)))
         return fail(LW_E_ALIGN, "%s: misaligned pointer", fn);
-    if (work && (!ws || boris_batch_fit(traj->n_particles, traj->n_samples, ws_bytes, 6) < 1))
-        return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes holds no batch (one particle needs %zu)", fn, ws_bytes,
-                    boris_stream_ws_bytes(1, traj->n_samples, 1, 6));
+    if (work && grid->n_pix > 0 && traj->n_samples >= 2) {
+        const BorisPlan plan = boris_plan_fit(traj->n_particles, traj->n_samples, traj->span, ws_bytes, true);
+        if (!ws || plan.batch < 1 || plan.span < 2)
+            return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes holds no span (one particle needs %zu)", fn,
+                        ws_bytes, boris_plan_ws_bytes(BorisPlan{1, traj->span > 0 ? traj->span : 2}, true));
+    }
     return launch_deposit_bwd_boris(traj, grid, field_mask, geom, (const double *)dE, grad_init, grad_a0, ws, ws_bytes,
                                     stream);
 }

@@ -289,20 +289,23 @@ lw_status launch_boris_span(const lw_traj_t *traj, int64_t s0, int64_t n_span, d
                             double *beta, double *beta_dot, hipStream_t s);
 lw_status launch_boris_bwd(const lw_traj_t *traj, const double *g_r, const double *g_beta,
                            const double *g_beta_dot, double *grad_init, double *grad_a0, hipStream_t s);
+// the pusher's tangents over samples s0 .. s0 + n_span - 1 (gradients g_* [n_particles][n_span][3]),
+// their state [n_particles][7][18] carried between spans; the first span (s0 = 0) writes
+// grad_init, grad_a0, later ones add to them
+lw_status launch_boris_bwd_span(const lw_traj_t *traj, int64_t s0, int64_t n_span, double *tstate,
+                                const double *g_r, const double *g_beta, const double *g_beta_dot, double *grad_init,
+                                double *grad_a0, hipStream_t s);
 lw_status launch_deposit_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int field_mask, int geom, const double *dE,
-                             double *d_r, double *d_beta, double *d_beta_dot, hipStream_t s);
-// trajectories recomputed from LW_TRAJ_BORIS initial conditions (boris_stream.hip).  The forward
-// deposit pushes batches of particles over spans of samples; the adjoint pushes whole
-// trajectories batch by batch (6 arrays: samples and their gradients).
+                             double *d_r, double *d_beta, double *d_beta_dot, hipStream_t s, int64_t sample0 = 0);
+// trajectories recomputed from LW_TRAJ_BORIS initial conditions (boris_stream.hip): the deposit
+// and its adjoint push batches of particles over spans of samples.
 struct BorisPlan {
     int64_t batch, span;  // particles per batch, samples per span (spans share their boundary sample)
 };
-BorisPlan boris_plan_default(int64_t n_p, int64_t ns);
-BorisPlan boris_plan_fit(int64_t n_p, int64_t ns, int64_t span_req, size_t ws_bytes);
-size_t boris_plan_ws_bytes(const BorisPlan &p);
-int64_t boris_batch_default(int64_t n_p, int64_t ns, int arrays);
-size_t boris_stream_ws_bytes(int64_t n_p, int64_t ns, int64_t batch, int arrays);
-int64_t boris_batch_fit(int64_t n_p, int64_t ns, size_t ws_bytes, int arrays);
+// bwd: the adjoint's plan (sample arrays and their gradients, tangent states)
+BorisPlan boris_plan_default(int64_t n_p, int64_t ns, bool bwd = false);
+BorisPlan boris_plan_fit(int64_t n_p, int64_t ns, int64_t span_req, size_t ws_bytes, bool bwd = false);
+size_t boris_plan_ws_bytes(const BorisPlan &p, bool bwd = false);
 lw_status launch_deposit_boris(const lw_traj_t *t, const lw_grid_t *gr, int prec, int fmask, int geom,
                                bool accumulate, void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s);
 lw_status launch_deposit_bwd_boris(const lw_traj_t *t, const lw_grid_t *gr, int fmask, int geom, const double *dE,

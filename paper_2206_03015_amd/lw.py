@@ -344,11 +344,13 @@ def deposit_td_boris(init, n_samples, t_start, dt, a0, lam, w0, n_cycles, x_det,
 
 
 def deposit_td_bwd_boris(init, n_samples, t_start, dt, a0, lam, w0, n_cycles, x_det, t0, dt_obs, n_obs, dE,
-                         field_mask=FIELD_ACCEL, geom="exact", charge=None, ws=None):
-    """lw_deposit_td_bwd_boris (FP64): returns (grad_init [n_p][6], grad_a0 [n_p])."""
+                         field_mask=FIELD_ACCEL, geom="exact", charge=None, ws=None, span=0):
+    """lw_deposit_td_bwd_boris (FP64), a batch of particles over a span of samples at a time
+    (span=0: chosen from the workspace): returns (grad_init [n_p][6], grad_a0 [n_p])."""
     lib = load()
     n_p = int(init.shape[0])
     tr = make_boris_traj(init, n_samples, t_start, dt, a0, lam, w0, n_cycles)
+    tr.span = int(span)
     if charge is not None:
         _need(charge, torch.float64, (n_p,), "charge")
         tr.charge = c_vp(charge.data_ptr())

@@ -60,6 +60,7 @@ def test_workspace_sizes(lib):
     big = lw.workspace_bytes(lw.WS_DEPOSIT_BORIS, 100000, 20001)
     assert 15.5 * 2**30 < big < 16.5 * 2**30
     assert lw.workspace_bytes(lw.WS_DEPOSIT_BWD_BORIS, 10, 1000) >= 10 * 1000 * 144
+    assert 15.5 * 2**30 < lw.workspace_bytes(lw.WS_DEPOSIT_BWD_BORIS, 100000, 20001) < 16.5 * 2**30
     assert lib.lw_workspace_bytes(999, 1, 1, 0) == 0
 
 
@@ -135,4 +136,8 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert b"span" in lib.lw_last_error()
     assert lib.lw_trajectory_boris_bwd(ctypes.byref(tb), p, p, p, p, p, None) == -1
     assert b"span" in lib.lw_last_error()
+    # the deposit adjoint takes spans too: span 2 passes, the missing workspace is reported
+    assert lib.lw_deposit_td_bwd_boris(ctypes.byref(tb), ctypes.byref(gr), 0, 1, 0, p, p, p, None, 0, None) == -4
+    tb.span = 1
+    assert lib.lw_deposit_td_bwd_boris(ctypes.byref(tb), ctypes.byref(gr), 0, 1, 0, p, p, p, None, 0, None) == -1
     assert lib.lw_version().startswith(b"liblw")

@@ -117,8 +117,11 @@ def test_stream_with_culling(prec):
     assert np.max(np.abs(Ec - Ef)) <= (1e-13 if prec == "fp64" else 1e-6) * np.max(np.abs(Ef))
 
 
-@pytest.mark.parametrize("per_batch", [None, 5])
-def test_stream_adjoint_equals_chained_adjoints(per_batch):
+@pytest.mark.parametrize("per_batch,span", [(None, 0), (5, 0), (None, 2), (None, 64), (None, 700)])
+def test_stream_adjoint_equals_chained_adjoints(per_batch, span):
+    # the adjoint over spans (span 0: chosen from the workspace; with room for 5 particles'
+    # whole trajectories the 12 particles go as 1024-sample spans of a smaller batch): the
+    # gradients of a span's boundary sample are split between the two spans' deposit adjoints
     from paper_2206_03015_amd import lw
     c = small_bunch(n_p=12, n_steps=2000, n_side=3, n_obs=1 << 11)
     W, L = c["W"], c["W"].laser
@@ -127,14 +130,18 @@ def test_stream_adjoint_equals_chained_adjoints(per_batch):
     rng = np.random.default_rng(4)
     dE = T(rng.normal(size=(c["x_det"].shape[0], 3, c["n_obs"])))
     ws = None if per_batch is None else small_ws(lw, lw.WS_DEPOSIT_BWD_BORIS, per_batch, W.n_samples)
-    gi, ga = lw.deposit_td_bwd_boris(init, *args, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], dE, ws=ws)
+    gi, ga = lw.deposit_td_bwd_boris(init, *args, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], dE, ws=ws,
+                                     span=span)
     r, b, bd = lw.trajectory_boris(init, *args)
     g = lw.deposit_td_bwd(r, b, bd, W.t_start, W.dt, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], dE)
     gi2, ga2 = lw.trajectory_boris_bwd(init, *args, *g)
     torch.cuda.synchronize()
     gi, ga, gi2, ga2 = (x.cpu().numpy() for x in (gi, ga, gi2, ga2))
-    assert np.max(np.abs(gi - gi2)) <= 1e-12 * np.max(np.abs(gi2))
-    assert np.max(np.abs(ga - ga2)) <= 1e-12 * np.max(np.abs(ga2))
+    # one span sums each tangent in the order of the chained adjoint; several spans add
+    # partial sums, a different order of the same terms
+    tol = 1e-12 if per_batch is None and span == 0 else 1e-10
+    assert np.max(np.abs(gi - gi2)) <= tol * np.max(np.abs(gi2))
+    assert np.max(np.abs(ga - ga2)) <= tol * np.max(np.abs(ga2))
 
 
 def centre_cut(name, n_p):
