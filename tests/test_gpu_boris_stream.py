@@ -1,6 +1,6 @@
-"""LW_TRAJ_BORIS: lw_deposit_td recomputing the trajectories inside the call (a batch of
-particles over a span of samples at a time) and lw_deposit_td_bwd_boris (batches of whole
-trajectories), against the same computation on stored trajectories and
+"""LW_TRAJ_BORIS: lw_deposit_td and lw_deposit_td_bwd_boris recomputing the trajectories
+inside the call (a batch of particles over a span of samples at a time), against the same
+computation on stored trajectories and
 against the oracle at the shapes of the large workload (gamma = 100, 64 x 64 pixels, 2^20
 grid) and of the precision workload (gamma = 200, a0 = 1, 128 x 128 pixels, 2^18 grid at 16
 samples per period, harmonics 1..5)."""
