@@ -94,6 +94,32 @@ def test_stream_long_trajectory_small_workspace():
     assert ds.tolist() == list(dw) and int(dw[3]) > 0
 
 
+@pytest.mark.parametrize("n_samples", [1, 2])
+def test_stream_one_and_two_samples(n_samples):
+    """The shortest trajectories: one sample (no interval: nothing deposited, zero gradient)
+    and two (a single span holding a single interval), forward and adjoint, against the
+    stored-trajectory paths."""
+    from paper_2206_03015_amd import lw
+    c = small_bunch(n_p=6, n_steps=300, n_side=3, n_obs=1 << 10)
+    W, L = c["W"], c["W"].laser
+    init = T(c["init"])
+    args = (n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
+    Es, ds = lw.deposit_td_boris(init, *args, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], prec="fp64")
+    r, b, bd = lw.trajectory_boris(init, *args)
+    Eo, do = lw.deposit_td(r, b, bd, W.t_start, W.dt, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], prec="fp64")
+    rng = np.random.default_rng(9)
+    dE = T(rng.normal(size=(c["x_det"].shape[0], 3, c["n_obs"])))
+    gi, ga = lw.deposit_td_bwd_boris(init, *args, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], dE)
+    g = lw.deposit_td_bwd(r, b, bd, W.t_start, W.dt, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], dE)
+    gi2, ga2 = lw.trajectory_boris_bwd(init, *args, *g)
+    torch.cuda.synchronize()
+    assert torch.max(torch.abs(Es - Eo)) <= 1e-12 * torch.max(torch.abs(Eo)) and ds.tolist() == do.tolist()
+    if n_samples == 1:
+        assert not torch.any(Es) and ds.tolist() == [0, 0, 0, 0]
+        assert not torch.any(gi) and not torch.any(ga)
+    assert torch.allclose(gi, gi2, rtol=1e-12, atol=0) and torch.allclose(ga, ga2, rtol=1e-12, atol=0)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_stream_with_culling(prec):
     """LW_TRAJ_BORIS together with LW_CULL (several batches; most of these 256 particles miss
