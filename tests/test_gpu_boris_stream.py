@@ -121,20 +121,23 @@ def test_stream_one_and_two_samples(n_samples):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_stream_with_culling(prec):
-    """LW_TRAJ_BORIS together with LW_CULL (several batches; most of these 256 particles miss
-    the window): the counters equal the full evaluation's, the trace equals the full
-    evaluation's up to the order of atomic additions (the full streamed evaluation itself is
-    checked against stored trajectories and the oracle above)."""
+@pytest.mark.parametrize("span", [0, 100])
+def test_stream_with_culling(prec, span):
+    """LW_TRAJ_BORIS together with LW_CULL (several batches of whole trajectories, or 100-sample
+    spans culled span by span; most of these 256 particles miss the window): the counters
+    equal the full evaluation's, the trace equals the full evaluation's up to the order of
+    atomic additions (the full streamed evaluation itself is checked against stored
+    trajectories and the oracle above)."""
     from paper_2206_03015_amd import lw
     c = small_bunch(n_p=256, n_steps=1000, n_side=12, n_obs=1 << 12)
     W, L = c["W"], c["W"].laser
     init = T(c["init"])
     args = (W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
     ws = small_ws(lw, lw.WS_DEPOSIT_BORIS, 40, W.n_samples)
-    Ef, df = lw.deposit_td_boris(init, *args, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], prec=prec, ws=ws)
+    Ef, df = lw.deposit_td_boris(init, *args, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], prec=prec, ws=ws,
+                                 span=span)
     Ec, dc = lw.deposit_td_boris(init, *args, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], prec=prec, ws=ws,
-                                 cull=True)
+                                 cull=True, span=span)
     torch.cuda.synchronize()
     Ef, Ec = Ef.double().cpu().numpy(), Ec.double().cpu().numpy()
     dc, df = dc.tolist(), df.tolist()
