@@ -100,7 +100,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU pixel "
-              "sharding is a design note, not part of this build.", flush=True)
+              "sharding is described as a design only and not implemented.", flush=True)
         return 2
     import torch
     from paper_2206_03015_amd import inputs, lw

@@ -49,8 +49,8 @@ def test_spectrum_of_a_line_and_parseval(prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_deposit_then_spectrum_single_electron(prec):
-    """Whole path on the single-electron workload: spectrum within the benchmark spec's bounds of
-    the oracle (FP64 1e-10 of the per-pixel maximum; mixed 1e-4 band L2)."""
+    """Whole path on the single-electron workload: spectrum within the parity bounds of the
+    oracle (FP64 1e-10 of the per-pixel maximum; mixed 1e-4 band L2)."""
     from paper_2206_03015_amd import lw
     c = single_electron(thetas=(0.0, 0.01))
     Eo, _ = oracle.deposit_td(c["t_start"], c["dt"], c["r"], c["beta"], c["beta_dot"], c["x_det"], c["t0"],
