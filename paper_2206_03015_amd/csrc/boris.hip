@@ -172,12 +172,12 @@ __device__ __forceinline__ void laser_eb(const LaserDev &L, R a0, R x, R y, R z,
     Ex = 0.0;
     By = 0.0;
     if (!(fabs(val(phi)) < kPi * L.nc)) return;
-    R sh, ch, sp, cp, s2, c2;
+    R sh, ch, sp, cp;
     sincos(phi / (2.0 * L.nc), &sh, &ch);
     sincos(phi, &sp, &cp);
-    sincos(phi / L.nc, &s2, &c2);
     const R g = ch * ch;
-    const R gp = -(s2 / (2.0 * L.nc));
+    // g' = -sin(phi/nc)/(2 nc) = -sh ch / nc (double angle: one sin/cos pair fewer per step)
+    const R gp = -((sh * ch) / L.nc);
     const R dS = gp * sp + g * cp;
     R T = 1.0;
     if (L.w0 > 0.0) T = exp(-((x * x + y * y) / (L.w0 * L.w0)));
