@@ -234,9 +234,10 @@ __device__ __forceinline__ void push_sample(const PushState<R> &S, R *rr, R *bb,
 {
     const double q = -kQe, m = kMe;
     const R g = sqrt(1.0 + (S.usx * S.usx + S.usy * S.usy + S.usz * S.usz));
-    const R bx = S.usx / g, by = S.usy / g, bz = S.usz / g;
+    const R ig = 1.0 / g;  // one division for the four quotients by gamma
+    const R bx = S.usx * ig, by = S.usy * ig, bz = S.usz * ig;
     // d beta/dt = q/(gamma m c) [E + c beta x B - beta (beta.E)],  E = (Ex,0,0), B = (0,By,0)
-    const R f = (q / (m * kC)) / g;
+    const R f = (q / (m * kC)) * ig;
     const R be = bx * S.Ex;
     rr[0] = S.x;
     rr[1] = S.y;
@@ -254,9 +255,10 @@ template <typename R>
 __device__ __forceinline__ void push_step(const LaserDev &L, R a0, double t_next, double dt, PushState<R> &S)
 {
     const R gh = sqrt(1.0 + (S.uhx * S.uhx + S.uhy * S.uhy + S.uhz * S.uhz));
-    S.x = S.x + (kC * dt) * (S.uhx / gh);
-    S.y = S.y + (kC * dt) * (S.uhy / gh);
-    S.z = S.z + (kC * dt) * (S.uhz / gh);
+    const R cg = (kC * dt) / gh;  // c dt / gamma at the half step
+    S.x = S.x + cg * S.uhx;
+    S.y = S.y + cg * S.uhy;
+    S.z = S.z + cg * S.uhz;
     R nx = S.uhx, ny = S.uhy, nz = S.uhz;
     // the field at (r_{i+1}, t_{i+1}) drives the kick and is the next sample's field
     laser_eb(L, a0, S.x, S.y, S.z, t_next, S.Ex, S.By);
