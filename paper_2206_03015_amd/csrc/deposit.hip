@@ -374,7 +374,8 @@ struct Wave {
             const T sax = readlane_t(eax, src), say = readlane_t(eay, src), saz = readlane_t(eaz, src);
             const T sbx = readlane_t(ebx, src), sby = readlane_t(eby, src), sbz = readlane_t(ebz, src);
             T *Em = E + (size_t)(tile * kTilePix + sml) * 3 * sh.n_obs;
-            for (int u = su0 + lane; u < su1; u += 64) {
+            // 64-bit index: su1 may sit within 64 of the largest int (n_obs up to 2^31 - 1)
+            for (int64_t u = (int64_t)su0 + lane; u < su1; u += 64) {
                 const T w = (T)((double)u - sta) * sidt, w1 = (T)1 - w;
                 atomic_add(Em + u, w1 * sax + w * sbx);
                 atomic_add(Em + sh.n_obs + u, w1 * say + w * sby);

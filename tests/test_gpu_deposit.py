@@ -173,3 +173,38 @@ def test_degenerate_sizes():
     Eg, dg = run_gpu(nop, "fp64", "exact")
     assert Eg.shape == (0, 3, 16)
     assert lw is not None
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_largest_grid(prec):
+    """The largest observer grid the library takes, n_obs = 2^31 - 1 (grid indices are 32-bit):
+    the same trajectories as a 4096-point window, with t0 moved back by the K = 2^31 - 1 - 4096
+    extra grid steps, so that grid point u of the small window is point u + K of the large one.
+    The large trace's last 4096 points equal the oracle's small-window trace (within the
+    rounding of arrival times of magnitude ~2^31 grid units: 1e-6 of the maximum), and every
+    interval's grid points are counted once either way (the small window's points below it are
+    inside the large one)."""
+    from paper_2206_03015_amd import lw
+    dev = torch.device("cuda:0")
+    c = synthetic(n_p=3, n_samples=300, n_pix=1, n_obs=4096)
+    Eo, do = run_oracle(c, "exact")
+    n_big = (1 << 31) - 1
+    K = n_big - c["n_obs"]
+    t = {k: torch.as_tensor(np.ascontiguousarray(c[k]), device=dev) for k in ("r", "beta", "beta_dot", "x_det")}
+    E, diag = lw.deposit_td(t["r"], t["beta"], t["beta_dot"], c["t_start"], c["dt"], t["x_det"],
+                            c["t0"] - K * c["dt_obs"], c["dt_obs"], n_big, prec=prec)
+    tail = E[:, :, K:].double().cpu().numpy()
+    below = E[:, :, :K]  # points the small window drops below its start
+    head = max(below.max().item(), -below.min().item())
+    del below
+    diag = diag.cpu().numpy()
+    del E
+    torch.cuda.empty_cache()
+    scale = np.max(np.abs(Eo))
+    assert scale > 0
+    err = np.max(np.abs(tail - Eo)) / scale
+    print(f"n_obs = 2^31 - 1, {prec}: tail vs oracle {err:.2e}, below-window max {head:.2e}, diag {diag.tolist()}")
+    assert err <= (1e-6 if prec == "fp64" else 2e-5)
+    assert int(diag[2] + diag[3]) == int(do[2] + do[3])
+    assert int(diag[3]) >= int(do[3]) > 0
+    assert (head > 0) == (int(diag[3]) > int(do[3]))
