@@ -172,6 +172,14 @@ def test_degenerate_sizes():
     nop["x_det"] = c["x_det"][:0]
     Eg, dg = run_gpu(nop, "fp64", "exact")
     assert Eg.shape == (0, 3, 16)
+    # a one-point observer grid, and two points, against the oracle
+    for n_obs in (1, 2):
+        c1 = synthetic(n_p=3, n_samples=50, n_pix=3, n_obs=n_obs)
+        for prec in ("fp64", "mixed"):
+            Eg, dg = run_gpu(c1, prec, "exact")
+            Eo, do = run_oracle(c1, "exact")
+            assert_close(Eg, Eo, prec)
+            assert dg.tolist() == do.tolist()
     assert lw is not None
 
 
