@@ -278,7 +278,9 @@ lw_status lw_spectrum_fft_bwd(const void *E, const void *dS, int64_t n_pix, int6
  * point coincides with an arrival time).  prec: FP64 only in this version
  * (MIXED returns LW_E_UNSUPPORTED).  traj: kind LW_TRAJ_SAMPLES.  dE: double
  * [n_pix][3][n_obs].  ws, ws_bytes: reserved (pass NULL, 0).  Arrival times of
- * the exact geometry use the sqrt/divide form.
+ * the exact geometry use the third-order series of the path correction where
+ * |r_i|^2 <= 1e-8 |x_m|^2 (exact to rounding, as in the FP64 deposit), else the
+ * sqrt/divide form.
  */
 lw_status lw_deposit_td_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom,
                             const void *dE, double *d_r, double *d_beta, double *d_beta_dot, void *ws,

@@ -23,6 +23,8 @@ namespace {
 
 constexpr int kWavesPerBlock = 4;
 constexpr int kOwned = 62;
+// (|r|/|x|)^2 up to which the series form of the exact-geometry arrival time is used
+constexpr double kSeriesBoundBwd = 1e-8;
 
 struct BwdShape {
     int64_t n_particles, n_samples, n_pix, n_obs, n_chunks, sample0;
@@ -85,7 +87,15 @@ __global__ __launch_bounds__(256) void k_deposit_bwd(const double *__restrict__ 
             const int64_t m = m0 + j;
             const PixGeo g = geo[j];
             const bool ok = usable && g.ok;
-            const double tau = ok ? arrival_tau<GEOM, kTauSqrt>(g, alpha, rs[0], rs[1], rs[2], rr, sh.inv_cdt) : 0.0;
+            // the exact geometry's correction as its third-order series where |r|^2 <= 1e-8 |x|^2
+            // (exact to rounding, the FP64 deposit's form there), else with its square root
+            double tau = 0.0;
+            if (ok) {
+                if (GEOM == LW_GEOM_EXACT && rr * g.invD * g.invD <= kSeriesBoundBwd)
+                    tau = arrival_tau<GEOM, kTauSeries>(g, alpha, rs[0], rs[1], rs[2], rr, sh.inv_cdt);
+                else
+                    tau = arrival_tau<GEOM, kTauSqrt>(g, alpha, rs[0], rs[1], rs[2], rr, sh.inv_cdt);
+            }
             const double tl = __shfl_up(tau, 1), tr = __shfl_down(tau, 1);
             const int okl = __shfl_up((int)ok, 1), okr = __shfl_down((int)ok, 1);
             const bool left = lane >= 1 && ok && okl && tau > tl;
