@@ -49,3 +49,23 @@ def test_spectra_error():
     S = np.array([[1.5, 4.0], [2.0, 1.0]])
     mx, mean = bench.spectra_error(S, S_ref)
     assert mx == 0.25 and mean == (0.125 + 0.25) / 4
+
+
+def test_committed_counter_figures_describe_the_committed_deposit():
+    """The counter summaries under profiles/ carry a SHA-256 of the deposit sources; bench.py
+    reports their figures (HBM traffic, VALU instructions, FP64/FP32 flops) only while the
+    sources are unchanged.  This checks that the committed summaries were taken from the
+    committed sources and hold sane values."""
+    traffic = bench.deposit_traffic()
+    valu = bench.deposit_valu_insts()
+    flops = bench.deposit_executed_flops()
+    assert traffic is not None and valu is not None and flops is not None
+    evals = 10000 * 20001 * 4096
+    # at least the trajectories and the trace once; far below one byte per evaluation
+    assert 27e9 <= traffic < evals
+    # wavefront instructions: at least one per 64 evaluations, at most 32 lane-instructions per
+    # evaluation (the scan takes ~10, the drains ~8)
+    assert evals / 64 <= valu <= 32 * evals / 64
+    f64, f32 = flops
+    # the arrival time's FP64 FMA-class work dominates; the fields at the crossings are FP32
+    assert f64 > f32 > 0
