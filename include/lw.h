@@ -171,7 +171,8 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec);
  * grid:       pixels and observer grid.
  * prec:       LW_PREC_FP64 (E is double) or LW_PREC_MIXED (E is float; tau and
  *             the crossing decisions are still computed in double).  In the exact
- *             geometry, a particle with max_i |r_i|^2 <= 1e-8 |x_m|^2 has its path
+ *             geometry, a particle with max_i |r_i|^2 <= 1e-8 |x_m|^2 (the max over
+ *             the pushed span for LW_TRAJ_BORIS) has its path
  *             correction expanded in |r|/|x_m|: to third order in FP64 mode (exact to
  *             rounding), to first order in MIXED mode (relative error of the
  *             correction <= 1.25e-8); other particles use the square-root form.
