@@ -1,31 +1,35 @@
 #!/usr/bin/env python3
 """Benchmark of the time-domain Lienard-Wiechert hot path on one MI355X.
 
-Workload ("bunch"): 1e4 electrons (gamma = 50, sigma_gamma/gamma = 1e-3, sigma_x,y = 2 um,
-sigma_z = 5 um, eps_n = 1 mm mrad, seeded draws) in a Gaussian laser pulse (a0 = 0.5,
-w0 = 10 um, 20 cycles of 1 um), trajectories from the library's FP64 Boris pusher at
-2e4 steps (resident in HBM before timing), 64 x 64 pixels over +-1/gamma at 1 m, 2^18
-observer grid points per pixel, exact geometry, acceleration field.
+Headline workload ("precision"): 1e5 electrons (gamma = 200, sigma_gamma/gamma = 1e-3,
+sigma_x,y = 2 um, sigma_z = 5 um, eps_n = 1 mm mrad, seeded draws) in a Gaussian laser pulse
+(a0 = 1, w0 = 10 um, 20 cycles of 1 um), 2e4 FP64 Boris steps, 128 x 128 pixels over +-2/gamma
+at 1 m, 2^18 observer grid points per pixel (16 per first-harmonic period), exact geometry,
+acceleration field.  The initial conditions and pixels are resident in HBM before timing.
 
-One step = lw_deposit_td (arrival time of every particle x sample x pixel, field where the
-interpolation reads it, linear-interpolation deposit) + lw_spectrum_fft (|E(w)|^2), in mixed
-precision (arrival times in double, fields/trace/FFT in float).  ``value`` counts
-particle * sample * pixel triples per second of step time.
+One step = lw_deposit_td with the trajectories recomputed inside the call by the FP64 Boris
+pusher, span by span (LW_TRAJ_BORIS: the 144 GB of samples never exist whole), i.e. the arrival
+time of every particle x sample x pixel, the field where the interpolation reads it and the
+linear-interpolation deposit, + lw_spectrum_fft (|E(w)|^2), in mixed precision (arrival times in
+FP64, fields/trace/FFT in FP32).  ``value`` counts particle * sample * pixel triples per second
+of step time.
 
-Also measured: the same step in all-FP64 (speedup of mixed over FP64), the spectral error
-of mixed against FP64 in the first-harmonic band of every pixel, the culled variant
-(LW_CULL, same spectra), the deposit kernel's share against its VALU roofline with its
-counter-measured HBM traffic, VALU instruction count and executed FP64/FP32 flop rates
-(committed rocprofv3 summaries, used while the deposit sources are unchanged), the FFT
-against HBM bandwidth, the
-direct frequency-domain sum on a pixel subset, the gradient of a band objective, and the
-FP64 CPU oracle on a bounded sample (``cpu_baseline``).
+In the same line: the all-FP64 pass of the same workload (speedup of mixed over FP64) and the
+band-L2 error of mixed against FP64 in the harmonic bands h = 1..5 of every pixel; the deposit
+kernel against the roofline of the work it performs (an FP64 arrival time for every triple, the
+field at both ends and the interpolation for every deposited grid point; kernel time from HIP
+events the library records around its launches), with counter figures from committed rocprofv3
+summaries while the deposit sources are unchanged; the culled variant (same spectra); the FFT
+against HBM bandwidth; the Boris pusher's trajectory write rate; the observer-window
+diagnostics; the bunch workload (1e4 e-, 64 x 64 px, stored trajectories) with its own
+roofline; the direct frequency-domain sum on 64 of its pixels; the gradient of a band objective
+on the differentiation workload; and the FP64 CPU oracle on a bounded sample (``cpu_baseline``).
 
-Other modes (one JSON line each, not the headline): ``--workload precision|large`` (one
-full-size pass of that configuration with in-library trajectories, mixed against FP64 per
-harmonic band; the large one adds the full-size adjoint), ``--cost-model`` (refit of the
-wall-clock model constants and the TD/FD crossover) and ``--accuracy`` (the single-electron
-accuracy experiment against a converged reference).
+Other modes (one JSON line each, not the headline): ``--workload bunch`` (the bunch workload as
+the headline), ``--workload large`` (one full-size pass of that configuration, mixed against
+FP64, with the full-size adjoint), ``--cost-model`` (refit of the wall-clock model constants and
+the TD/FD crossover) and ``--accuracy`` (the single-electron accuracy experiment against a
+converged reference and the oracle).
 """
 from __future__ import annotations
 
@@ -48,21 +52,28 @@ PEAK_HBM_GBS = 8000.0
 CUS, CLOCK_GHZ, LANES = 256, 2.4, 64
 PEAK_F32_TFLOPS = 157.3  # vector FP32 (256 CUs x 2.4 GHz x 128 lanes x 2 flops, packed)
 PEAK_F64_TFLOPS = 78.6   # vector FP64
-# Algorithmic work of one (particle, sample, pixel) evaluation in mixed precision: the field
-# formula with its 1/kappa^3 factors in FP32 (68 flops) and the arrival time in FP64 (6 flops).
-# The roofline time of one evaluation is F32/P32 + F64/P64; the "peak" below is the flop rate
-# at which both units would be saturated in that proportion.
-EVAL_F32_FLOPS, EVAL_F64_FLOPS = 68, 6
+# Work the deposit performs (its roofline): the arrival time of every (particle, sample, pixel)
+# triple, 6 FP64 flops (three fused multiply-adds: the sample's time base minus n.r/(c dt_obs)),
+# and for every deposited grid point the field at the interval's two ends (68 FP32 flops each:
+# n x ((n - b) x bd), the 1/kappa^3 factor and the prefactors) plus the interpolation (13 FP32
+# flops: weight, its complement, three lerps).  Roofline time = F64/P64 + F32/P32.
+TRIPLE_F64_FLOPS = 6
+FIELD_F32_FLOPS = 68
+HIT_F32_FLOPS = 2 * FIELD_F32_FLOPS + 13
+# the per-evaluation figure of a method that forms the field for every triple (dense)
+DENSE_F32_FLOPS, DENSE_F64_FLOPS = 68, 6
 # Direct FD: ~18 FP32 flops per (particle, sample, pixel, frequency) term (phase, sin/cos,
 # three complex multiply-accumulates)
 FD_TERM_FLOPS = 18
-EVAL_FLOPS = EVAL_F32_FLOPS + EVAL_F64_FLOPS
-EVAL_ROOF_S = EVAL_F32_FLOPS / (PEAK_F32_TFLOPS * 1e12) + EVAL_F64_FLOPS / (PEAK_F64_TFLOPS * 1e12)
-PEAK_EVAL_TFLOPS = EVAL_FLOPS / EVAL_ROOF_S / 1e12
 DEPOSIT_SOURCES = ("paper_2206_03015_amd/csrc/deposit.hip", "paper_2206_03015_amd/csrc/lw_internal.h")
-TRAFFIC_SUMMARY = "profiles/k_deposit_bunch_mixed_exact_hbm_traffic.md"
-VALU_SUMMARY = "profiles/k_deposit_bunch_mixed_exact_valu.md"
-VALU_TYPES_SUMMARY = "profiles/valu_fp32_fp64_bunch_exact.md"
+SUMMARIES = {
+    "precision": {"traffic": "profiles/k_deposit_precision_mixed_hbm_traffic.md",
+                  "valu": "profiles/k_deposit_precision_mixed_valu.md",
+                  "types": "profiles/valu_fp32_fp64_precision.md"},
+    "bunch": {"traffic": "profiles/k_deposit_bunch_mixed_exact_hbm_traffic.md",
+              "valu": "profiles/k_deposit_bunch_mixed_exact_valu.md",
+              "types": "profiles/valu_fp32_fp64_bunch_exact.md"},
+}
 
 
 def parse():
@@ -77,16 +88,18 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-grad", action="store_true")
     p.add_argument("--no-cull", action="store_true", help="skip the culled-variant leg")
+    p.add_argument("--no-bunch", action="store_true", help="skip the bunch-workload leg of the headline line")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--cost-model", action="store_true",
                    help="instead of the headline step: refit the wall-clock model constants C1_t, C2_t, C_w "
                         "by single-variate sweeps and time the TD/FD crossover in the particle count")
-    p.add_argument("--workload", default="bunch", choices=["bunch", "precision", "large"],
-                   help="bunch: the headline step; precision / large: one full-size pass of that "
-                        "configuration (trajectories recomputed inside the deposit), mixed against FP64")
+    p.add_argument("--workload", default="precision", choices=["precision", "bunch", "large"],
+                   help="precision: the headline (trajectories pushed inside the deposit); bunch: the bunch "
+                        "workload as the headline (stored trajectories); large: one full-size pass of that "
+                        "configuration with its adjoint")
     p.add_argument("--accuracy", action="store_true",
                    help="instead of the headline step: the single-electron accuracy experiment (Eq. "
-                        "spectra_error of TD and FD against a converged FP64 FD reference)")
+                        "spectra_error of TD and FD against a converged FP64 FD reference and the oracle)")
     p.add_argument("--copy-calibration-gib", type=float, default=0.0,
                    help="run a plain device copy of this many GiB first (scale for HBM byte counters)")
     return p.parse_args()
@@ -103,7 +116,7 @@ def main():
               "sharding is described as a design only and not implemented.", flush=True)
         return 2
     import torch
-    from paper_2206_03015_amd import inputs, lw
+    from paper_2206_03015_amd import lw
 
     lw.load()
     dev = torch.device("cuda:0")
@@ -113,25 +126,9 @@ def main():
     if args.accuracy:
         print(json.dumps(accuracy(torch, dev)), flush=True)
         return 0
-    if args.workload != "bunch":
-        print(json.dumps(full_size(torch, dev, args.workload)), flush=True)
+    if args.workload == "large":
+        print(json.dumps(full_size(torch, dev, "large")), flush=True)
         return 0
-    W = inputs.workload("bunch")
-    if args.particles:
-        W = W.scaled(n_p=args.particles)
-    L = W.laser
-    log(f"[bench] workload bunch: n_p={W.n_p} n_samples={W.n_samples} n_pix={W.n_pix} n_obs={W.n_obs}")
-
-    # ---- inputs resident in HBM (untimed): seeded draws -> FP64 Boris trajectories on the GPU
-    init = torch.as_tensor(inputs.bunch_init(W), device=dev)
-    t0 = time.time()
-    r, b, bd = lw.trajectory_boris(init, W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
-    torch.cuda.synchronize()
-    log(f"[bench] Boris trajectories {W.n_p} x {W.n_samples}: {time.time() - t0:.2f} s")
-    x_det = torch.as_tensor(inputs.pixel_positions(W.n_side, W.theta_max, W.D), device=dev)
-    n_pix, n_obs = W.n_pix, W.n_obs
-    triples = W.n_p * W.n_samples * n_pix
-
     if args.copy_calibration_gib > 0:
         n = int(args.copy_calibration_gib * (1 << 30)) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -140,80 +137,176 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: {n * 4} bytes read and written by one elementwise kernel")
         del src, dst
+    rec = headline(torch, dev, args)
+    print(json.dumps(rec), flush=True)
+    return 0
 
-    def buffers(prec):
+
+def deposit_roofline(triples, hits, kernel_s, launches, summaries=None, profiled=False):
+    """Roofline of the deposit kernel on the work it performs (TRIPLE_F64_FLOPS per triple,
+    HIT_F32_FLOPS per deposited grid point) over its measured time (HIP events around its
+    launches), with the dense per-evaluation figure and the committed counter figures beside it."""
+    f64 = triples * TRIPLE_F64_FLOPS
+    f32 = hits * HIT_F32_FLOPS
+    t_roof = f64 / (PEAK_F64_TFLOPS * 1e12) + f32 / (PEAK_F32_TFLOPS * 1e12)
+    work = f64 + f32
+    peak = work / t_roof / 1e12
+    achieved = work / kernel_s / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None, "kernel": "k_deposit", "launches": launches, "kernel_ms": kernel_s * 1e3,
+            "work": {"f64_flops": f64, "f32_flops": f32, "triples": triples, "deposited_points": hits,
+                     "f64_flops_per_triple": TRIPLE_F64_FLOPS, "f32_flops_per_deposited_point": HIT_F32_FLOPS},
+            "roofline_ms": t_roof * 1e3}
+    dense_s = triples * (DENSE_F32_FLOPS / (PEAK_F32_TFLOPS * 1e12) + DENSE_F64_FLOPS / (PEAK_F64_TFLOPS * 1e12))
+    roof["dense_per_eval_figure"] = {"note": "68 FP32 + 6 FP64 flops credited to every triple (a method "
+                                             "that forms the field everywhere); not the work performed",
+                                     "frac": dense_s / kernel_s}
+    if profiled and summaries:
+        roof["traffic"] = _summary_value(summaries["traffic"], "hbm_bytes_per_step")
+        valu = _summary_value(summaries["valu"], "valu_insts_per_step")
+        if valu is not None:
+            roof["executed_valu_insts"] = valu
+            roof["valu_issue_frac"] = valu * 4 / (CUS * 4 * CLOCK_GHZ * 1e9 * kernel_s)
+        ex = (_summary_value(summaries["types"], "f64_flops_per_step"),
+              _summary_value(summaries["types"], "f32_flops_per_step"))
+        if ex[0] is not None and ex[1] is not None:
+            a64, a32 = ex[0] / kernel_s / 1e12, ex[1] / kernel_s / 1e12
+            roof["executed"] = {"f64_tflops": a64, "f64_frac": a64 / PEAK_F64_TFLOPS,
+                                "f32_tflops": a32, "f32_frac": a32 / PEAK_F32_TFLOPS}
+    return roof
+
+
+def band_errors(torch, dev, W, S_a, S_b, harmonics, chunk=512):
+    """Band-L2 error of S_a against S_b (both [n_pix][n_obs/2+1] on the device) in the harmonic bands
+    [(h - 0.3) w1, (h + 0.1) w1] of every pixel (w1 at the pixel's polar angle): max and median."""
+    from paper_2206_03015_amd import inputs
+    tx, ty = inputs.pixel_angles(W.n_side, W.theta_max)
+    w1 = torch.as_tensor(np.array([W.omega1(t) for t in np.hypot(tx, ty)]), device=dev)[:, None]
+    wgrid = torch.as_tensor(2 * np.pi * np.arange(W.n_obs // 2 + 1) / (W.n_obs * W.dt_obs), device=dev)
+    out = {}
+    for h in harmonics:
+        errs = []
+        for m0 in range(0, W.n_pix, chunk):
+            m1 = min(W.n_pix, m0 + chunk)
+            band = (wgrid[None, :] >= (h - 0.3) * w1[m0:m1]) & (wgrid[None, :] <= (h + 0.1) * w1[m0:m1])
+            a = S_a[m0:m1].double() * band
+            b = S_b[m0:m1].double() * band
+            den = torch.linalg.vector_norm(b, dim=1)
+            ok = den > 0
+            errs.append((torch.linalg.vector_norm(a - b, dim=1)[ok] / den[ok]).cpu().numpy())
+        errs = np.concatenate(errs)
+        out[f"h{h}"] = {"max": float(errs.max()), "median": float(np.median(errs)), "pixels": int(errs.size)}
+        log(f"[bench] h={h}: band L2 mixed vs FP64 max {errs.max():.2e} median {np.median(errs):.2e} over "
+            f"{errs.size} pixels")
+    return out
+
+
+def headline(torch, dev, args):
+    """The headline line: the precision workload (default) with in-call Boris trajectories, or the
+    bunch workload with stored trajectories (``--workload bunch``)."""
+    from paper_2206_03015_amd import grid, inputs, lw
+    name = args.workload
+    W = inputs.workload(name)
+    if args.particles:
+        W = W.scaled(n_p=args.particles)
+    L = W.laser
+    log(f"[bench] workload {name}: n_p={W.n_p} n_samples={W.n_samples} n_pix={W.n_pix} n_obs={W.n_obs}")
+    init = torch.as_tensor(inputs.bunch_init(W), device=dev)
+    x_det = torch.as_tensor(inputs.pixel_positions(W.n_side, W.theta_max, W.D), device=dev)
+    n_pix, n_obs = W.n_pix, W.n_obs
+    triples = W.n_p * W.n_samples * n_pix
+    in_call = name == "precision"
+
+    # ---- trajectories pushed once (untimed for the step): the pusher's write rate, and the first
+    # and last samples of every particle for the observer-window diagnostics
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    r, b, bd = lw.trajectory_boris(init, W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
+    e1.record()
+    torch.cuda.synchronize()
+    push_ms = e0.elapsed_time(e1)
+    traj_bytes = 72 * W.n_p * W.n_samples
+    stream_rec = {"kernel": "k_boris (lw_trajectory_boris)", "bytes_written": traj_bytes, "ms": push_ms,
+                  "GBs": traj_bytes / (push_ms / 1e3) / 1e9, "frac_of_hbm_peak":
+                  traj_bytes / (push_ms / 1e3) / 1e9 / PEAK_HBM_GBS}
+    log(f"[bench] Boris trajectories {W.n_p} x {W.n_samples}: {push_ms:.0f} ms, {stream_rec['GBs']:.0f} GB/s")
+    diag_rec = grid.window_diagnostics(W.t_start, W.t_start + (W.n_samples - 1) * W.dt, r[:, 0].cpu().numpy(),
+                                       r[:, -1].cpu().numpy(), x_det.cpu().numpy(), W.t0, W.dt_obs, n_obs,
+                                       W.gamma, L.lam)
+    if in_call:
+        del r, b, bd
+        torch.cuda.empty_cache()
+    ws_f = torch.empty(lw.workspace_bytes(lw.WS_FFT, n_pix, n_obs, "mixed"), dtype=torch.uint8, device=dev)
+
+    def deposit(prec, E, diag, ws, cull=False):
+        if in_call:
+            lw.deposit_td_boris(init, W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles, x_det, W.t0,
+                                W.dt_obs, n_obs, prec=prec, geom=args.geom, out=E, diag=diag, ws=ws, cull=cull)
+        else:
+            lw.deposit_td(r, b, bd, W.t_start, W.dt, x_det, W.t0, W.dt_obs, n_obs, prec=prec, geom=args.geom,
+                          out=E, diag=diag, ws=ws, cull=cull)
+
+    def run(prec, steps, warmup, cull=False):
         dt = torch.float64 if prec == "fp64" else torch.float32
         E = torch.empty((n_pix, 3, n_obs), dtype=dt, device=dev)
         S = torch.empty((n_pix, n_obs // 2 + 1), dtype=dt, device=dev)
-        ws_d = torch.empty(lw.workspace_bytes(lw.WS_DEPOSIT, W.n_p, W.n_samples, prec), dtype=torch.uint8,
-                           device=dev)
-        ws_f = torch.empty(lw.workspace_bytes(lw.WS_FFT, n_pix, n_obs, prec), dtype=torch.uint8, device=dev)
+        which = lw.WS_DEPOSIT_BORIS if in_call else lw.WS_DEPOSIT
+        ws_d = torch.empty(lw.workspace_bytes(which, W.n_p, W.n_samples, prec), dtype=torch.uint8, device=dev)
+        wsf = ws_f if prec == "mixed" else torch.empty(lw.workspace_bytes(lw.WS_FFT, n_pix, n_obs, prec),
+                                                       dtype=torch.uint8, device=dev)
         diag = torch.zeros(4, dtype=torch.int64, device=dev)
-        return E, S, ws_d, ws_f, diag
-
-    def run(prec, steps, warmup, cull=False):
-        E, S, ws_d, ws_f, diag = buffers(prec)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         dep_ms, fft_ms = [], []
+        kern_ms, kern_n = 0.0, 0
         for it in range(warmup + steps):
             if it == warmup:
                 torch.cuda.synchronize()
+                lw.timing_enable(True)
                 t_start = time.time()
             ev[0].record()
-            lw.deposit_td(r, b, bd, W.t_start, W.dt, x_det, W.t0, W.dt_obs, n_obs, prec=prec, geom=args.geom,
-                          out=E, diag=diag, ws=ws_d, cull=cull)
+            deposit(prec, E, diag, ws_d, cull)
             ev[1].record()
-            lw.spectrum_fft(E, W.dt_obs, prec, out=S, ws=ws_f)
+            lw.spectrum_fft(E, W.dt_obs, prec, out=S, ws=wsf)
             ev[2].record()
             if it >= warmup:
                 torch.cuda.synchronize()
+                ms, n = lw.timing_read(lw.KERNEL_DEPOSIT)
+                kern_ms += ms
+                kern_n += n
                 dep_ms.append(ev[0].elapsed_time(ev[1]))
                 fft_ms.append(ev[1].elapsed_time(ev[2]))
-                log(f"[bench] {prec}{' culled' if cull else ''} step {it - warmup}: deposit {dep_ms[-1]:.1f} ms, "
-                    f"fft {fft_ms[-1]:.1f} ms")
+                log(f"[bench] {prec}{' culled' if cull else ''} step {it - warmup}: deposit {dep_ms[-1]:.1f} ms "
+                    f"(kernel {ms:.1f} ms in {n} launches), fft {fft_ms[-1]:.1f} ms")
         torch.cuda.synchronize()
         wall = (time.time() - t_start) / steps * 1e3
+        lw.timing_enable(False)
+        del E, ws_d
+        torch.cuda.empty_cache()
         return dict(ms_per_step=wall, deposit_ms=float(np.mean(dep_ms)), fft_ms=float(np.mean(fft_ms)),
-                    diag=diag.cpu().tolist(), S=S, E=E)
+                    kernel_ms=kern_ms / steps, launches=kern_n // steps, diag=diag.cpu().tolist(), S=S)
 
     mixed = run("mixed", args.steps, args.warmup)
-    E_mixed = mixed.pop("E")
-    del E_mixed
     S_mixed = mixed.pop("S")
     out = {}
-    res64 = None
     if not args.no_fp64:
-        res64 = run("fp64", max(1, min(args.steps, 2)), 1)
-        res64.pop("E")
+        # one all-FP64 pass of the same workload
+        res64 = run("fp64", 1, 0)
         S64 = res64.pop("S")
-        # spectral error of mixed against FP64 in the first-harmonic band of each pixel
-        tx, ty = inputs.pixel_angles(W.n_side, W.theta_max)
-        w = 2 * np.pi * np.arange(n_obs // 2 + 1) / (n_obs * W.dt_obs)
-        wt = torch.as_tensor(w, device=dev)
-        errs = []
-        for m0 in range(0, n_pix, 256):
-            m1 = min(n_pix, m0 + 256)
-            th = np.hypot(tx[m0:m1], ty[m0:m1])
-            w1 = torch.as_tensor(np.array([W.omega1(t) for t in th]), device=dev)[:, None]
-            band = (wt[None, :] >= 0.7 * w1) & (wt[None, :] <= 1.1 * w1)
-            a = S_mixed[m0:m1].double() * band
-            bb = S64[m0:m1] * band
-            num = torch.linalg.vector_norm(a - bb, dim=1)
-            den = torch.linalg.vector_norm(bb, dim=1)
-            ok = den > 0
-            errs.append((num[ok] / den[ok]).cpu().numpy())
-        errs = np.concatenate(errs) if errs else np.zeros(0)
+        harmonics = range(1, 6) if name == "precision" else range(1, 2)
         out["fp64"] = {"ms_per_step": res64["ms_per_step"], "deposit_ms": res64["deposit_ms"],
-                       "fft_ms": res64["fft_ms"]}
+                       "kernel_ms": res64["kernel_ms"], "fft_ms": res64["fft_ms"],
+                       "evals_per_s": triples / (res64["ms_per_step"] / 1e3)}
         out["mixed_vs_fp64_speedup"] = res64["ms_per_step"] / mixed["ms_per_step"]
-        out["mixed_vs_fp64_band_l2_err"] = ({"max": float(errs.max()), "median": float(np.median(errs)),
-                                            "pixels": int(errs.size)} if errs.size else None)
+        out["mixed_vs_fp64_deposit_speedup"] = res64["deposit_ms"] / mixed["deposit_ms"]
+        out["mixed_vs_fp64_band_l2_err"] = band_errors(torch, dev, W, S_mixed, S64, harmonics)
+        out["diag_fp64_equal"] = res64["diag"] == mixed["diag"]
         del S64
+        torch.cuda.empty_cache()
     if not args.no_cull:
         # culled variant (LW_CULL): particles whose arrivals miss a wavefront's window are
         # skipped after two arrival-time evaluations; same spectra, reported separately
-        cul = run("mixed", max(1, min(args.steps, 2)), 1, cull=True)
-        cul.pop("E")
+        cul = run("mixed", 1, 0, cull=True)
         S_c = cul.pop("S")
         diff = float(torch.max(torch.abs(S_c - S_mixed)) / torch.max(torch.abs(S_mixed)))
         out["culled"] = {"ms_per_step": cul["ms_per_step"], "deposit_ms": cul["deposit_ms"],
@@ -221,102 +314,164 @@ def main():
                          "diag_equal": cul["diag"] == mixed["diag"], "max_rel_diff_vs_full": diff}
         del S_c
     del S_mixed
+    if not in_call:
+        del r, b, bd
     torch.cuda.empty_cache()
 
-    # ---- roofline of the dominant kernel (the deposit): algorithmic flops of the method per
-    # evaluation (EVAL_FLOPS) x evaluations per launch / average launch time (HIP events on the
-    # stream the library launches on).  The kernel itself evaluates the field only at the ends
-    # of intervals that deposit, so it does less work than it is credited with; its own count
-    # count of VALU instructions (rocprofv3 SQ_INSTS_VALU, committed summary) is reported beside
-    # it as the share of the VALU issue slots it fills (one wavefront instruction occupies a
-    # SIMD for 4 clocks).
-    dep_s = mixed["deposit_ms"] / 1e3
-    achieved = triples * EVAL_FLOPS / dep_s / 1e12
-    profiled = args.geom == "exact" and args.particles is None  # the configuration of the summaries
-    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_EVAL_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_EVAL_TFLOPS, "traffic": deposit_traffic() if profiled else None,
-            "kernel": "k_deposit (lw_deposit_td: pre-pass + fill + deposit)",
-            "flops_per_eval": {"f32": EVAL_F32_FLOPS, "f64": EVAL_F64_FLOPS},
-            "evals_per_launch": triples}
-    valu = deposit_valu_insts() if profiled else None
-    if valu is not None:
-        roof["executed_valu_insts_per_launch"] = valu
-        roof["valu_issue_frac"] = valu * 4 / (CUS * 4 * CLOCK_GHZ * 1e9 * dep_s)
-    # FP64 and FP32 flops the launch executes (SQ_INSTS_VALU_{FMA,MUL,ADD}_{F32,F64}, committed
-    # summary) over its measured time: the VALU utilisation by precision
-    ex = deposit_executed_flops() if profiled else None
-    if ex is not None:
-        f64, f32 = ex[0] / dep_s / 1e12, ex[1] / dep_s / 1e12
-        roof["executed"] = {"f64_tflops": f64, "f64_frac": f64 / PEAK_F64_TFLOPS,
-                            "f32_tflops": f32, "f32_frac": f32 / PEAK_F32_TFLOPS}
+    profiled = args.geom == "exact" and args.particles is None
+    roof = deposit_roofline(triples, mixed["diag"][3], mixed["kernel_ms"] / 1e3, mixed["launches"],
+                            SUMMARIES.get(name), profiled)
     fft_bytes = n_pix * (3 * n_obs + n_obs // 2 + 1) * 4
     fft_gbs = fft_bytes / (mixed["fft_ms"] / 1e3) / 1e9
 
-    # ---- direct frequency-domain sum on a pixel subset (comparison path)
-    fd = None
-    if not args.no_fd:
-        n_fd_pix, n_w = 8, 4096
-        sel = torch.arange(0, n_pix, n_pix // n_fd_pix, device=dev)[:n_fd_pix]
-        w1 = W.omega1()
-        dw = 2 * np.pi / (n_obs * W.dt_obs)
-        j0 = int(0.7 * w1 / dw)
-        jstep = max(1, int((0.4 * w1 / dw) / n_w))
-        omega = torch.as_tensor((j0 + jstep * np.arange(n_w)) * dw, device=dev)
-        xs = x_det[sel].contiguous()
-        ws_fd = torch.empty(lw.workspace_bytes(lw.WS_DIRECT_FD, n_fd_pix, n_w, "mixed"), dtype=torch.uint8,
-                            device=dev)
-        Sfd = torch.empty((n_fd_pix, n_w), dtype=torch.float64, device=dev)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        lw.direct_fd(r[:64], b[:64], bd[:64], W.t_start, W.dt, xs, W.t0, omega, prec="mixed", geom=args.geom,
-                     out=Sfd, ws=ws_fd)
-        torch.cuda.synchronize()
-        e0.record()
-        lw.direct_fd(r, b, bd, W.t_start, W.dt, xs, W.t0, omega, prec="mixed", geom=args.geom, out=Sfd, ws=ws_fd)
-        e1.record()
-        torch.cuda.synchronize()
-        fd_ms = e0.elapsed_time(e1)
-        terms = W.n_p * W.n_samples * n_fd_pix * n_w
-        fd_per_pix_bin = fd_ms / (n_fd_pix * n_w)
-        td_per_pix_bin = mixed["ms_per_step"] / (n_pix * (n_obs // 2 + 1))
-        fd_tflops = terms * FD_TERM_FLOPS / (fd_ms / 1e3) / 1e12
-        fd = {"pixels": n_fd_pix, "n_omega": n_w, "ms": fd_ms, "terms_per_s": terms / (fd_ms / 1e3),
-              "td_speedup_per_pixel_bin": fd_per_pix_bin / td_per_pix_bin,
-              "roofline": {"bound": "alu", "achieved": fd_tflops, "peak": PEAK_F32_TFLOPS, "unit": "TFLOP/s",
-                           "frac": fd_tflops / PEAK_F32_TFLOPS, "flops_per_term": FD_TERM_FLOPS}}
-        log(f"[bench] direct FD {n_fd_pix} pix x {n_w} w: {fd_ms:.1f} ms")
-
-    # ---- gradient of the band objective on the differentiation workload (FP64 forward + adjoint)
+    bunch = None
+    if name == "precision" and not args.no_bunch:
+        bunch = bunch_leg(torch, dev, args)
     grad = None
     if not args.no_grad:
         grad = grad_leg(torch, dev)
-
-    # ---- FP64 CPU oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(W, args.geom, args.cpu_seconds)
 
     value = triples / (mixed["ms_per_step"] / 1e3)
+    desc = {"precision": "precision: 1e5 e-, gamma 200, a0 1, 2e4 Boris steps pushed inside the deposit, "
+                         "128x128 px, 2^18 grid",
+            "bunch": "bunch: 1e4 e-, gamma 50, a0 0.5, 2e4 Boris steps (stored), 64x64 px, 2^18 grid"}[name]
     rec = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64 tau + f32 field/trace/FFT", "data": "synthetic",
-        "config": {"workload": "bunch: 1e4 e-, 2e4 Boris steps, 64x64 px, 2^18 grid", "n_particles": W.n_p,
-                   "n_samples": W.n_samples, "n_pix": n_pix, "n_obs": n_obs, "geom": args.geom,
-                   "field": "accel", "prec": "mixed"},
+        "config": {"workload": desc, "n_particles": W.n_p, "n_samples": W.n_samples, "n_pix": n_pix,
+                   "n_obs": n_obs, "geom": args.geom, "field": "accel", "prec": "mixed",
+                   "trajectories": "pushed inside the deposit (LW_TRAJ_BORIS spans)" if in_call else "stored"},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "deposit_ms": mixed["deposit_ms"], "fft_ms": mixed["fft_ms"],
-        "deposit_evals_per_s": triples / dep_s,
+        "deposit_ms": mixed["deposit_ms"], "deposit_kernel_ms": mixed["kernel_ms"], "fft_ms": mixed["fft_ms"],
+        "deposit_evals_per_s": triples / (mixed["deposit_ms"] / 1e3),
         "fft": {"bound": "hbm", "algorithmic_bytes": fft_bytes, "achieved_GBs": fft_gbs,
                 "frac": fft_gbs / PEAK_HBM_GBS},
+        "trajectory_streaming": stream_rec,
+        "grid": diag_rec,
         "diag": mixed["diag"],
-        "direct_fd": fd,
+        "bunch": bunch,
         "grad": grad,
         "paper_serial_evals_per_s": 1.0 / 1.02e-7,
     }
     rec.update(out)
-    print(json.dumps(rec), flush=True)
-    return 0
+    return rec
+
+
+def bunch_leg(torch, dev, args):
+    """The bunch workload (1e4 e-, 2e4 stored Boris steps, 64 x 64 px, 2^18 grid) as an extra key:
+    mixed steps (deposit + FFT) with the deposit's roofline, one FP64 pass (band-L2 error of
+    mixed against it) and the direct frequency-domain sum on 64 of its pixels x 4096 frequencies."""
+    from paper_2206_03015_amd import grid, inputs, lw
+    W = inputs.workload("bunch")
+    L = W.laser
+    init = torch.as_tensor(inputs.bunch_init(W), device=dev)
+    r, b, bd = lw.trajectory_boris(init, W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
+    x_det = torch.as_tensor(inputs.pixel_positions(W.n_side, W.theta_max, W.D), device=dev)
+    n_pix, n_obs = W.n_pix, W.n_obs
+    triples = W.n_p * W.n_samples * n_pix
+    diag_rec = grid.window_diagnostics(W.t_start, W.t_start + (W.n_samples - 1) * W.dt, r[:, 0].cpu().numpy(),
+                                       r[:, -1].cpu().numpy(), x_det.cpu().numpy(), W.t0, W.dt_obs, n_obs,
+                                       W.gamma, L.lam)
+    res = {}
+    S = {}
+    for prec, steps in (("mixed", max(1, min(args.steps, 5))), ("fp64", 1)):
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        E = torch.empty((n_pix, 3, n_obs), dtype=dt, device=dev)
+        S[prec] = torch.empty((n_pix, n_obs // 2 + 1), dtype=dt, device=dev)
+        ws_d = torch.empty(lw.workspace_bytes(lw.WS_DEPOSIT, W.n_p, W.n_samples, prec), dtype=torch.uint8,
+                           device=dev)
+        ws_f = torch.empty(lw.workspace_bytes(lw.WS_FFT, n_pix, n_obs, prec), dtype=torch.uint8, device=dev)
+        diag = torch.zeros(4, dtype=torch.int64, device=dev)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        dep, fft, kern, nl = [], [], 0.0, 0
+        for it in range(steps + 1):
+            if it == 1:
+                torch.cuda.synchronize()
+                lw.timing_enable(True)
+                t0 = time.time()
+            ev[0].record()
+            lw.deposit_td(r, b, bd, W.t_start, W.dt, x_det, W.t0, W.dt_obs, n_obs, prec=prec, geom=args.geom,
+                          out=E, diag=diag, ws=ws_d)
+            ev[1].record()
+            lw.spectrum_fft(E, W.dt_obs, prec, out=S[prec], ws=ws_f)
+            ev[2].record()
+            if it >= 1:
+                torch.cuda.synchronize()
+                ms, n = lw.timing_read(lw.KERNEL_DEPOSIT)
+                kern += ms
+                nl += n
+                dep.append(ev[0].elapsed_time(ev[1]))
+                fft.append(ev[1].elapsed_time(ev[2]))
+        torch.cuda.synchronize()
+        wall = (time.time() - t0) / steps * 1e3
+        lw.timing_enable(False)
+        res[prec] = {"ms_per_step": wall, "deposit_ms": float(np.mean(dep)), "kernel_ms": kern / steps,
+                     "launches": nl // steps, "fft_ms": float(np.mean(fft)), "diag": diag.cpu().tolist(),
+                     "evals_per_s": triples / (wall / 1e3)}
+        log(f"[bench] bunch {prec}: {wall:.1f} ms per step (deposit kernel {kern / steps:.1f} ms), fft "
+            f"{np.mean(fft):.1f} ms")
+        del E, ws_d, ws_f
+        torch.cuda.empty_cache()
+    m = res["mixed"]
+    profiled = args.geom == "exact" and args.particles is None
+    out = {"workload": "bunch: 1e4 e-, gamma 50, a0 0.5, 2e4 Boris steps (stored), 64x64 px, 2^18 grid",
+           "value": m["evals_per_s"], "unit": "evals/s", "ms_per_step": m["ms_per_step"],
+           "deposit_ms": m["deposit_ms"], "deposit_kernel_ms": m["kernel_ms"], "fft_ms": m["fft_ms"],
+           "diag": m["diag"],
+           "roofline": deposit_roofline(triples, m["diag"][3], m["kernel_ms"] / 1e3, m["launches"],
+                                        SUMMARIES["bunch"], profiled),
+           "fp64": res["fp64"], "mixed_vs_fp64_speedup": res["fp64"]["ms_per_step"] / m["ms_per_step"],
+           "mixed_vs_fp64_band_l2_err": band_errors(torch, dev, W, S["mixed"], S["fp64"], range(1, 2)),
+           "grid": diag_rec}
+    fft_bytes = n_pix * (3 * n_obs + n_obs // 2 + 1) * 4
+    out["fft"] = {"achieved_GBs": fft_bytes / (m["fft_ms"] / 1e3) / 1e9,
+                  "frac": fft_bytes / (m["fft_ms"] / 1e3) / 1e9 / PEAK_HBM_GBS}
+    del S
+    torch.cuda.empty_cache()
+    if not args.no_fd:
+        out["direct_fd"] = fd_leg(torch, dev, W, r, b, bd, x_det, m["ms_per_step"], args.geom)
+    del r, b, bd
+    torch.cuda.empty_cache()
+    return out
+
+
+def fd_leg(torch, dev, W, r, b, bd, x_det, td_ms_per_step, geom, n_fd_pix=64, n_w=4096):
+    """Direct frequency-domain sum (comparison path) on n_fd_pix evenly spaced pixels x n_w
+    FFT-bin frequencies of the first-harmonic band, mixed precision."""
+    from paper_2206_03015_amd import lw
+    n_pix, n_obs = W.n_pix, W.n_obs
+    sel = torch.arange(0, n_pix, n_pix // n_fd_pix, device=dev)[:n_fd_pix]
+    w1 = W.omega1()
+    dw = 2 * np.pi / (n_obs * W.dt_obs)
+    j0 = int(0.7 * w1 / dw)
+    jstep = max(1, int((0.4 * w1 / dw) / n_w))
+    omega = torch.as_tensor((j0 + jstep * np.arange(n_w)) * dw, device=dev)
+    xs = x_det[sel].contiguous()
+    ws_fd = torch.empty(lw.workspace_bytes(lw.WS_DIRECT_FD, n_fd_pix, n_w, "mixed"), dtype=torch.uint8, device=dev)
+    Sfd = torch.empty((n_fd_pix, n_w), dtype=torch.float64, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lw.direct_fd(r[:64], b[:64], bd[:64], W.t_start, W.dt, xs, W.t0, omega, prec="mixed", geom=geom, out=Sfd,
+                 ws=ws_fd)
+    torch.cuda.synchronize()
+    e0.record()
+    lw.direct_fd(r, b, bd, W.t_start, W.dt, xs, W.t0, omega, prec="mixed", geom=geom, out=Sfd, ws=ws_fd)
+    e1.record()
+    torch.cuda.synchronize()
+    fd_ms = e0.elapsed_time(e1)
+    terms = W.n_p * W.n_samples * n_fd_pix * n_w
+    fd_per_pix_bin = fd_ms / (n_fd_pix * n_w)
+    td_per_pix_bin = td_ms_per_step / (n_pix * (n_obs // 2 + 1))
+    fd_tflops = terms * FD_TERM_FLOPS / (fd_ms / 1e3) / 1e12
+    log(f"[bench] direct FD {n_fd_pix} pix x {n_w} w: {fd_ms:.1f} ms")
+    return {"pixels": n_fd_pix, "n_omega": n_w, "ms": fd_ms, "terms_per_s": terms / (fd_ms / 1e3),
+            "td_speedup_per_pixel_bin": fd_per_pix_bin / td_per_pix_bin,
+            "roofline": {"bound": "alu", "achieved": fd_tflops, "peak": PEAK_F32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": fd_tflops / PEAK_F32_TFLOPS, "flops_per_term": FD_TERM_FLOPS}}
 
 
 def fit_leading_constant(sweeps):
@@ -721,31 +876,12 @@ def _profile_figures(path):
     return vals
 
 
-def deposit_traffic():
-    """HBM bytes per deposit launch from the committed FETCH_SIZE / WRITE_SIZE summary."""
-    vals = _profile_figures(TRAFFIC_SUMMARY)
+def _summary_value(path, key):
+    """One "- key: `value`" figure of a committed rocprofv3 summary (None when absent or when the
+    deposit sources changed since its counters were taken)."""
+    vals = _profile_figures(path)
     try:
-        return float(vals["hbm_bytes_per_launch"]) if vals else None
-    except (KeyError, ValueError):
-        return None
-
-
-def deposit_valu_insts():
-    """Executed VALU instructions (wavefront level) per deposit launch from the committed
-    SQ_INSTS_VALU summary."""
-    vals = _profile_figures(VALU_SUMMARY)
-    try:
-        return float(vals["valu_insts_per_launch"]) if vals else None
-    except (KeyError, ValueError):
-        return None
-
-
-def deposit_executed_flops():
-    """(FP64, FP32) flops executed by one deposit launch from the committed summary of the
-    SQ_INSTS_VALU_{FMA,MUL,ADD}_{F32,F64} counters."""
-    vals = _profile_figures(VALU_TYPES_SUMMARY)
-    try:
-        return (float(vals["f64_flops_per_launch"]), float(vals["f32_flops_per_launch"])) if vals else None
+        return float(vals[key]) if vals else None
     except (KeyError, ValueError):
         return None
 
@@ -780,8 +916,8 @@ def cpu_baseline(W, geom, seconds):
     cores = min(cores, os.cpu_count() or cores, n_pix)
     log(f"[bench] cpu oracle: {n_p} particles x {W.n_samples} samples x {n_pix} pixels in {t:.1f} s")
     return {"value": triples / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n_p} particles x {W.n_samples} samples x {n_pix} pixels of the bunch workload "
-                      f"(FP64 deposit only, {t:.1f} s)"}
+            "sample": f"{n_p} particles x {W.n_samples} samples x {n_pix} pixels of the {W.name} workload "
+                      f"(FP64 deposit only, trajectories from the oracle's pusher untimed, {t:.1f} s)"}
 
 
 if __name__ == "__main__":

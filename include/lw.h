@@ -323,6 +323,23 @@ lw_status lw_direct_fd_bwd(const lw_traj_t *traj, const lw_grid_t *grid, const d
                            int prec, int field_mask, int geom, const double *dS, double *d_r, double *d_beta,
                            double *d_beta_dot, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Kernel timing (a measurement aid; off by default).  lw_timing_enable(1) makes
+ * every later launch of the kernel named by `which` record a pair of HIP events
+ * on the launch's stream around it; lw_timing_enable(0) stops and discards what
+ * was recorded.  lw_timing_read waits for the recorded events (host
+ * synchronisation on them), writes the summed elapsed time in milliseconds and
+ * the number of launches, and clears them.  which: LW_KERNEL_DEPOSIT (the
+ * evaluate-and-deposit kernel of lw_deposit_td, once per call, or once per
+ * pushed span for LW_TRAJ_BORIS).  The events are owned by the library (created
+ * on first use, reused).  Returns LW_E_ARG for an unknown `which` or NULL
+ * outputs, LW_E_HIP if an event call fails.  Not meant for concurrent use from
+ * several host threads.
+ */
+#define LW_KERNEL_DEPOSIT 1
+lw_status lw_timing_enable(int on);
+lw_status lw_timing_read(int which, double *total_ms, int64_t *launches);
+
 /* Thread-local text of the last error ("" if none). */
 const char *lw_last_error(void);
 

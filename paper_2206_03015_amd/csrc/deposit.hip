@@ -774,6 +774,7 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
     k_deposit<T, G, C><<<grid, block, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge, gr->x_det, w.alpha, w.pflag,    \
                                               w.rmax2, (T *)E, dg, sh)
     // culling is a separate instantiation: the full evaluation carries none of its code
+    hipEvent_t t_start = timing_begin(LW_KERNEL_DEPOSIT, s);
     if (f64) {
         if (geom == LW_GEOM_EXACT) {
             if (cull) LW_DEPOSIT_LAUNCH(double, LW_GEOM_EXACT, true); else LW_DEPOSIT_LAUNCH(double, LW_GEOM_EXACT, false);
@@ -788,6 +789,7 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
         }
     }
 #undef LW_DEPOSIT_LAUNCH
+    timing_end(LW_KERNEL_DEPOSIT, t_start, s);
     return check_launch("lw_deposit_td");
 }
 

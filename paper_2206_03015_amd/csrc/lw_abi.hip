@@ -5,6 +5,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 namespace lw {
 
@@ -33,6 +35,55 @@ lw_status check_launch(const char *what)
     if (e != hipSuccess) return fail(LW_E_HIP, "%s: %s", what, hipGetErrorString(e));
     g_err[0] = 0;
     return LW_OK;
+}
+
+// ---- kernel timing (lw_timing_enable / lw_timing_read)
+namespace {
+struct TimedLaunch {
+    int which;
+    hipEvent_t a, b;
+};
+std::mutex g_tm;
+bool g_timing = false;
+std::vector<TimedLaunch> g_timed;  // recorded, not yet read
+std::vector<hipEvent_t> g_pool;    // idle events
+
+hipEvent_t pool_event()
+{
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+}  // namespace
+
+hipEvent_t timing_begin(int which, hipStream_t s)
+{
+    (void)which;
+    std::lock_guard<std::mutex> lk(g_tm);
+    if (!g_timing) return nullptr;
+    hipEvent_t e = pool_event();
+    if (e && hipEventRecord(e, s) != hipSuccess) {
+        g_pool.push_back(e);
+        return nullptr;
+    }
+    return e;
+}
+
+void timing_end(int which, hipEvent_t start, hipStream_t s)
+{
+    if (!start) return;
+    std::lock_guard<std::mutex> lk(g_tm);
+    hipEvent_t e = pool_event();
+    if (!g_timing || !e || hipEventRecord(e, s) != hipSuccess) {
+        g_pool.push_back(start);
+        if (e) g_pool.push_back(e);
+        return;
+    }
+    g_timed.push_back({which, start, e});
 }
 
 namespace {
@@ -106,6 +157,49 @@ using namespace lw;
 extern "C" {
 
 const char *lw_last_error(void) { return g_err; }
+
+lw_status lw_timing_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_tm);
+    g_timing = on != 0;
+    if (!g_timing) {
+        for (const TimedLaunch &t : g_timed) {
+            (void)hipEventSynchronize(t.b);
+            g_pool.push_back(t.a);
+            g_pool.push_back(t.b);
+        }
+        g_timed.clear();
+    }
+    return LW_OK;
+}
+
+lw_status lw_timing_read(int which, double *total_ms, int64_t *launches)
+{
+    if (which != LW_KERNEL_DEPOSIT) return fail(LW_E_ARG, "lw_timing_read: unknown kernel %d", which);
+    if (!total_ms || !launches) return fail(LW_E_ARG, "lw_timing_read: NULL output");
+    std::lock_guard<std::mutex> lk(g_tm);
+    double sum = 0.0;
+    int64_t n = 0;
+    lw_status st = LW_OK;
+    std::vector<TimedLaunch> keep;
+    for (const TimedLaunch &t : g_timed) {
+        if (t.which != which) {
+            keep.push_back(t);
+            continue;
+        }
+        float ms = 0.0f;
+        if (hipEventSynchronize(t.b) != hipSuccess || hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess)
+            st = fail(LW_E_HIP, "lw_timing_read: event query failed");
+        sum += ms;
+        ++n;
+        g_pool.push_back(t.a);
+        g_pool.push_back(t.b);
+    }
+    g_timed.swap(keep);
+    *total_ms = sum;
+    *launches = n;
+    return st;
+}
 
 const char *lw_version(void) { return "liblw 0.1 (gfx950)"; }
 

@@ -25,6 +25,11 @@ lw_status check_launch(const char *what);
 
 inline bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
+// kernel timing (lw_timing_enable): timing_begin returns an event recorded on s just before the
+// launch (nullptr when timing is off); timing_end records the closing event after the launch
+hipEvent_t timing_begin(int which, hipStream_t s);
+void timing_end(int which, hipEvent_t start, hipStream_t s);
+
 // ---------------------------------------------------------------------------------------------
 // Pixel geometry, shared by the arrival-time and field evaluations.
 // 1/sqrt(x) for positive normal x to double precision: the hardware estimate refined by two

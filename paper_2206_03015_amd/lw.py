@@ -26,6 +26,7 @@ TRAJ_SAMPLES = 0
 TRAJ_BORIS = 1
 WS_DEPOSIT, WS_FFT, WS_DIRECT_FD, WS_DEPOSIT_BWD, WS_FFT_BWD, WS_DIRECT_FD_BWD = 1, 2, 3, 4, 5, 6
 WS_DEPOSIT_BORIS, WS_DEPOSIT_BWD_BORIS = 7, 8
+KERNEL_DEPOSIT = 1
 
 c_d = ctypes.c_double
 c_i64 = ctypes.c_int64
@@ -71,6 +72,8 @@ _SIGS = {
     "lw_direct_fd_bwd": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), c_vp, c_i64, ctypes.c_int,
                                         ctypes.c_int, ctypes.c_int, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t,
                                         c_vp]),
+    "lw_timing_enable": (ctypes.c_int, [ctypes.c_int]),
+    "lw_timing_read": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(c_d), ctypes.POINTER(c_i64)]),
     "lw_last_error": (ctypes.c_char_p, []),
     "lw_version": (ctypes.c_char_p, []),
 }
@@ -116,6 +119,18 @@ def _need(t, dtype, shape=None, name="tensor"):
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
     return t
+
+
+def timing_enable(on=True):
+    """lw_timing_enable: record HIP events around every later launch of the timed kernels."""
+    _check(load().lw_timing_enable(1 if on else 0))
+
+
+def timing_read(which=KERNEL_DEPOSIT):
+    """lw_timing_read: (summed milliseconds, launches) of the kernel since the last read."""
+    ms, n = c_d(0.0), c_i64(0)
+    _check(load().lw_timing_read(int(which), ctypes.byref(ms), ctypes.byref(n)))
+    return float(ms.value), int(n.value)
 
 
 def workspace_bytes(which, n_a, n_b, prec="mixed"):

@@ -5,9 +5,9 @@ FP64 oracle.
 
 The FP64 comparison feeds both sides the oracle's own Boris trajectories (pushed and deposited
 500 particles at a time on the host, copied to the device), so that it isolates the deposit and
-FFT: max relative error per pixel within the rounding bound of the arrival times (never below
-1e-10).  Two FP64 Boris pushers that round differently drift apart by ~1e-14 of the positions
-after 2e4 steps, which moves the arrival times by ~1e-8 grid units; the path the benchmark
+FFT: max relative error per pixel <= 1e-10.  Two FP64 Boris pushers that round differently drift
+apart by ~1e-14 of the positions after 2e4 steps, which moves the arrival times by ~1e-8 grid
+units; the path the benchmark
 times (the library's Boris, then deposit and FFT in mixed precision) is therefore checked at
 the mixed bound: band-L2 error in the first-harmonic band <= 1e-4.  The diagnostic counters of
 the sampled pixels match exactly."""
@@ -36,7 +36,6 @@ def test_bunch_workload_full_size():
     # oracle: trajectories and the spectra of the sampled pixels, 500 particles at a time
     Eo = np.zeros((SEL.size, 3, W.n_obs))
     do = np.zeros(4, dtype=np.int64)
-    rmax = 0.0
     for k0 in range(0, W.n_p, 500):
         r, b, bd = oracle.boris(init_np[k0:k0 + 500], W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
         for dst, src in ((ro, r), (bo, b), (bdo, bd)):
@@ -44,7 +43,6 @@ def test_bunch_workload_full_size():
         Ek, dk = oracle.deposit_td(W.t_start, W.dt, r, b, bd, x[SEL], W.t0, W.dt_obs, W.n_obs)
         Eo += Ek
         do += np.asarray(dk, dtype=np.int64)
-        rmax = max(rmax, float(np.max(np.linalg.norm(r, axis=-1))))
         del r, b, bd
     So = oracle.spectrum(Eo, W.dt_obs)
 
@@ -70,10 +68,7 @@ def test_bunch_workload_full_size():
     Smb = spectra(rg, bg, bdg, "mixed")
     del rg, bg, bdg
     torch.cuda.empty_cache()
-    # rounding bound of the arrival times (magnitude M grid units, s_p samples per period)
-    M = np.max(np.abs((W.t_start + np.arange(W.n_samples) * W.dt - W.t0) / W.dt_obs)) + \
-        rmax / (inputs.C_LIGHT * W.dt_obs)
-    tol64 = max(1e-10, (2 * np.pi / W.samples_per_period) * np.finfo(float).eps * M)
+    tol64 = 1e-10
     w = 2 * np.pi * np.arange(W.n_obs // 2 + 1) / (W.n_obs * W.dt_obs)
     for j, m in enumerate(SEL):
         th = np.arccos(x[m, 2] / np.linalg.norm(x[m]))

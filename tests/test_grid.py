@@ -56,3 +56,38 @@ def test_t_u_min_far_field():
     c = grid.C_LIGHT
     expected = min(-1e-15 + np.linalg.norm(xm) / c - (xm / np.linalg.norm(xm)) @ rk / c for xm in x for rk in r)
     assert grid.t_u_min(-1e-15, x, r) == pytest.approx(expected, rel=1e-15, abs=0)
+
+
+def test_window_diagnostics_against_brute_force():
+    """The observer-window diagnostics: t_u_min / t_u_max of Eqs. tu_min, tu_max (taken at the
+    convex-hull vertices of the particles) equal the minimum / maximum over every (particle, pixel)
+    pair; the captured fractions equal a direct count of window grid points in (tau_first,
+    tau_last]; the estimates are those of Eqs. Tu_first, Tu_second, time:Tu_estimation."""
+    rng = np.random.default_rng(5)
+    c = grid.C_LIGHT
+    n_p = 3000
+    r0 = rng.normal(size=(n_p, 3)) * np.array([2e-6, 2e-6, 5e-6])
+    t_start, t_end = -5e-14, 5e-14
+    r1 = r0 + np.array([0.0, 0.0, c * (t_end - t_start) * (1 - 1e-4)])
+    th = rng.uniform(-0.02, 0.02, size=(50, 2))
+    x = np.stack([np.sin(th[:, 0]), np.cos(th[:, 0]) * np.sin(th[:, 1]), np.cos(th[:, 0]) * np.cos(th[:, 1])], -1)
+    dt_obs, n_obs = 1e-18, 1024
+    t0 = t_start - 512 * dt_obs
+    d = grid.window_diagnostics(t_start, t_end, r0, r1, x, t0, dt_obs, n_obs, 50.0, 1e-6, n_sampled=50)
+    n = x / np.linalg.norm(x, axis=1)[:, None]
+    ta0 = t_start - (n @ r0.T) / c
+    ta1 = t_end - (n @ r1.T) / c
+    assert d["t_u_min_s"] == pytest.approx(float(ta0.min()), rel=0, abs=1e-28)
+    assert d["t_u_max_s"] == pytest.approx(float(ta1.max()), rel=0, abs=1e-28)
+    tf, tl = (ta0 - t0) / dt_obs, (ta1 - t0) / dt_obs
+    u = np.arange(n_obs, dtype=float)
+    cap = np.zeros(tf.shape, bool)
+    for m in range(tf.shape[0]):  # every window grid point against every interval
+        cap[m] = np.any((u[:, None] > tf[m][None, :]) & (u[:, None] <= tl[m][None, :]), axis=0)
+    assert d["pairs_captured"] == pytest.approx(cap.mean(), abs=1e-12)
+    assert d["particles_captured"] == pytest.approx(cap.any(axis=0).mean(), abs=1e-12)
+    assert 0 < d["pairs_captured"] < 0.5
+    lb = r0.max(axis=0) - r0.min(axis=0)
+    assert d["T_u_estimate_s"] == pytest.approx(lb[0] / (50 * c) + lb[1] / (50 * c) + lb[2] / c
+                                                + (t_end - t_start) / (2 * 50.0 ** 2), rel=1e-14)
+    assert d["t_u_min_grid"] == pytest.approx((d["t_u_min_s"] - t0) / dt_obs, rel=1e-14)

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.spectrum import omega_bins
+from oracle.spectrum import intensity, omega_bins
 
 C = oracle.C_LIGHT
 
@@ -24,9 +24,11 @@ def test_single_sample_is_flat():
 
 
 def test_far_field_matches_paper_prefactor():
-    """Far field, acceleration term: 2 eps0 c D^2 S(w) equals the right-hand side of
-    Eq. inty_dft, q^2 dt^2/(16 pi^3 eps0 c) |sum_k sum_i A_k(i dt) exp(j w (i dt - n.x_k/c))|^2,
-    with A_k = n x ((n - beta) x beta_dot) / (1 - n.beta)^2 (Eq. const_phase_drop)."""
+    """Far field, acceleration term: the spectral-angular intensity of the oracle's direct sum,
+    ``intensity(S, D)`` = (2/(c mu0)) D^2 S(w), equals the right-hand side of Eq. inty_dft,
+    q^2 dt^2/(16 pi^3 eps0 c) |sum_k sum_i A_k(i dt) exp(j w (i dt - n.x_k/c))|^2, with
+    A_k = n x ((n - beta) x beta_dot) / (1 - n.beta)^2 (Eq. const_phase_drop).  (1/(c mu0) = eps0 c
+    to the 1e-10 of the CODATA values of mu0 and eps0.)"""
     rng = np.random.default_rng(3)
     n_p, n_s = 2, 50
     dt = 1e-18
@@ -50,8 +52,10 @@ def test_far_field_matches_paper_prefactor():
             A = np.cross(n, np.cross(nb, bd[k, i])) / (1 - n @ b[k, i]) ** 2
             acc += A[None, :] * np.exp(1j * w[:, None] * (i * dt - n @ r[k, i] / C))
     rhs = q * q * dt * dt / (16 * math.pi ** 3 * eps0 * C) * np.sum(np.abs(acc) ** 2, axis=1)
-    lhs = 2 * eps0 * C * D * D * S[0]
+    lhs = intensity(S[0], D)
     assert np.allclose(lhs, rhs, rtol=1e-9, atol=0)
+    # the helper scales linearly in S and quadratically in D
+    assert np.allclose(intensity(S[0], 2 * D), 4 * lhs, rtol=1e-15, atol=0)
 
 
 def _td_fd_error(n_samples, n_obs):
