@@ -307,6 +307,28 @@ __global__ __launch_bounds__(256) void k_boris(const double *__restrict__ init, 
                           });
 }
 
+// max_i |r_i|^2 over every sample of each particle's trajectory (nothing stored; the sum in the
+// order of the deposit's pre-pass, z^2 + (y^2 + x^2) with fused multiply-adds), so that
+// choices made per particle over its whole trajectory agree between the spans of a deposit
+// and its adjoint and with those of the stored samples
+__global__ __launch_bounds__(256) void k_boris_rmax2(const double *__restrict__ init, int64_t n_particles,
+                                                     int64_t n_samples, double t_start, double dt, LaserDev L,
+                                                     double *__restrict__ rmax2)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_particles) return;
+    double in[6];
+    for (int c = 0; c < 6; ++c) in[c] = init[6 * k + c];
+    PushState<double> S;
+    push_start(L, L.a0, in, t_start, dt, S);
+    double mx = fma(S.z, S.z, fma(S.y, S.y, S.x * S.x));
+    for (int64_t i = 1; i < n_samples; ++i) {
+        push_step(L, L.a0, t_start + (double)i * dt, dt, S);
+        mx = fmax(mx, fma(S.z, S.z, fma(S.y, S.y, S.x * S.x)));
+    }
+    rmax2[k] = mx;
+}
+
 // Samples s0 .. s0 + n_span - 1 of each particle into r, beta, beta_dot [n_particles][n_span][3].
 // The pusher starts from init (s0 = 0) or from the state saved by the previous span, which ends
 // at sample s0 (spans share their boundary sample), and saves its state at the last sample it
@@ -482,6 +504,15 @@ lw_status launch_boris(const lw_traj_t *t, double *r, double *beta, double *beta
     k_boris<<<(unsigned)blocks, 64, 0, s>>>(t->init, t->n_particles, t->n_samples, t->t_start, t->dt, L, r, beta,
                                            beta_dot);
     return check_launch("lw_trajectory_boris");
+}
+
+lw_status launch_boris_rmax2(const lw_traj_t *t, double *rmax2, hipStream_t s)
+{
+    if (t->n_particles == 0) return LW_OK;
+    const LaserDev L = laser_dev(t->laser);
+    const int64_t blocks = (t->n_particles + 63) / 64;
+    k_boris_rmax2<<<(unsigned)blocks, 64, 0, s>>>(t->init, t->n_particles, t->n_samples, t->t_start, t->dt, L, rmax2);
+    return check_launch("max |r|^2 of the pushed trajectories");
 }
 
 lw_status launch_boris_span(const lw_traj_t *t, int64_t s0, int64_t n_span, double *state, double *r, double *beta,

@@ -2,29 +2,43 @@
 // Sec. "Interpolation"), forward pass.
 //
 // Work decomposition (one GPU's share of the paper's detector decomposition):
-//   * a wavefront owns 64 x kPPL pixels (kPPL per lane) and a group of particles;
-//   * for each particle it stages 64 samples at a time in LDS (lane j loads sample j),
-//     every lane reads each staged sample once (a broadcast) and uses it for each of its
-//     pixels: it forms the (particle, sample, pixel) arrival time in double and tests
-//     whether the interval (tau_{i-1}, tau_i] crosses the next grid point of that
-//     pixel's window (all four tests of a sample pair first, then one branch into the
-//     crossing logic if any holds).  With one pixel per lane the broadcast reads bound
-//     this loop (LDS returns 128 B per clock); kPPL pixels per lane divide their cost;
-//   * a crossing appends (particle, sample, pixel, arrival-time form) to a per-wavefront
-//     queue in LDS; whenever 64 entries are queued, all lanes take one entry each,
-//     evaluate the Lienard-Wiechert field at the interval's two ends and add the
-//     interpolated values at the crossed grid points into a write-combining line of that
-//     pixel in LDS (a short run of consecutive grid points of its trace); an interval
-//     holding more than kLongRun grid points (an observer grid much finer than the
-//     samples) is deposited by the whole wavefront instead, 64 grid points per pass;
-//   * a line whose pixel moves past it is added to the trace with global atomics,
-//     several lines per instruction (lane l takes value l % 3N of line l / 3N).
-// The field is therefore evaluated only at samples that the interpolation reads;
-// samples whose interval holds no grid point of the window contribute nothing.  With
-// LW_CULL (a separate instantiation) a fast-path particle is skipped when its first and
-// last arrival times at the wavefront's pixels bracket no window grid point.
+//   * a pre-pass writes, for every (particle, sample), a record: the sample's arrival base d
+//     (the two large, cancelling terms of the arrival time, carried in double-double and
+//     rounded once) and, for the exact geometry with the path term in series form, the
+//     coefficients of the arrival time as a polynomial in the pixel variable b
+//     (tau = sum_j c_j b^j, b = C((1 - n_z) z - n_x x - n_y y): three fused multiply-adds per
+//     pixel); it also flags particles whose arrival times are provably increasing and finds
+//     each particle's max |r|^2;
+//   * a wavefront owns 64 x kPPL pixels (kPPL per lane) and a group of particles; for each
+//     particle it walks the samples two at a time, reading each sample's position and record
+//     with scalar loads (the values are wavefront-uniform, so they sit in scalar registers
+//     and feed the vector fused multiply-adds directly; nothing passes through LDS), forms
+//     every (sample, pixel) arrival time in double and tests whether the interval
+//     (tau_{i-1}, tau_i] crosses the next grid point of that pixel's window (all four tests of
+//     a sample pair first, then one branch into the crossing logic if any holds);
+//   * a crossing appends (sample, particle, pixel, tau_{i-1}, tau_i) to a per-wavefront queue in
+//     LDS; whenever 64 entries are queued, all lanes take one entry each, evaluate the
+//     Lienard-Wiechert field at the interval's two ends and add the interpolated values at the
+//     crossed grid points into a write-combining line of that pixel in LDS (a short run of
+//     consecutive grid points of its trace); an interval holding more than kLongRun grid points
+//     (an observer grid much finer than the samples) is deposited by the whole wavefront
+//     instead, 64 grid points per pass;
+//   * a line whose pixel moves past it is added to the trace with global atomics, several lines
+//     per instruction (lane l takes value l % 3N of line l / 3N).
+// The field is therefore evaluated only at samples that the interpolation reads; samples whose
+// interval holds no grid point of the window contribute nothing.  The arrival times the
+// queue carries are the scan's own, so every decision and weight uses one value per
+// (sample, pixel).  With LW_CULL (a separate instantiation) a fast-path particle is skipped
+// when its first and last arrival times at the wavefront's pixels bracket no window grid point.
 //
-// Fast path condition (checked per particle by a pre-pass): every sample usable and
+// Arrival-time forms (exact geometry): the polynomial records hold the path term's series
+// (first order with single-precision fields, third order with double ones; valid where
+// |r|^2 <= 1e-8 |x_m|^2 over the whole trajectory) for pixels at the records' distance
+// (|x_m| of the first pixel); a wavefront whose pixels sit at another distance, or a particle
+// outside the series bound, evaluates arrival_tau per pixel instead (series or square-root
+// form), from the same d.
+//
+// Fast path condition (checked per particle by the pre-pass): every sample usable and
 // every step shorter than c*dt by a margin well above the rounding of tau, which makes
 // tau strictly increasing for every pixel (|x - r_i| - |x - r_{i-1}| >= -|r_i - r_{i-1}|).
 // Particles that fail it take the careful path, which applies the skip rules of
@@ -37,13 +51,12 @@
 namespace lw {
 namespace {
 
-constexpr int kPPL = 2;                // pixels per lane
+constexpr int kPPL = 2;                 // pixels per lane
 constexpr int kTilePix = 64 * kPPL;     // pixels per wavefront
-constexpr int kPixBits = kPPL == 1 ? 6 : kPPL == 2 ? 7 : 8;
-static_assert((1 << kPixBits) == kTilePix, "kPPL must be 1, 2 or 4");
-constexpr int kWavesPerBlock = 1;
-constexpr int kBlockThreads = 64 * kWavesPerBlock;
-constexpr uint32_t kQCap = 64 + 2 * 64 * kPPL;  // queue ring per wavefront (63 pending + 2 x kTilePix appended between drains)
+constexpr int kPixBits = 7;
+static_assert((1 << kPixBits) == kTilePix, "tile of 128 pixels");
+constexpr int kBlockThreads = 64;
+constexpr uint32_t kQCap = 64 + kTilePix;  // queue ring: 63 pending + one sample's crossings
 // write-combining line per pixel: 16-byte segments of the trace (4 floats or 2 doubles)
 template <typename T>
 struct WcLine {
@@ -51,19 +64,40 @@ struct WcLine {
     static constexpr int P = 3 * N + 1;        // LDS stride per pixel (odd: no bank conflicts)
 };
 constexpr uint32_t kWantNone = 0u;  // below every request (segment + 1)
-// queue entry tag: (particle - first particle of the group) << kPixBits | pixel in tile, and this
-// bit when the particle's arrival times take the series form
-constexpr uint32_t kSerBit = 1u << 31;
 // intervals with more grid points than this are deposited by the whole wavefront
 constexpr int kLongRun = 8;
-constexpr int kStage = 6;  // doubles per staged sample: alpha, x, y, z, |r|^2, pad
 // wavefronts per launch to aim for (particle groups x pixel tiles): ~26 rounds of the 3072
 // resident wavefronts (12 per CU), so that the last, partly filled round is a small share
-// (bunch workload: 16384 wavefronts took 705 ms, 80000 take 655 ms)
 constexpr int kTargetWaves = 98304;
-// (|r|/|x|)^2 up to which the series form of the exact-geometry arrival time is used
+// (|r|/|x|)^2 up to which the series forms of the exact-geometry arrival time are used
 constexpr double kSeriesBound = 1e-8;
+// pixels whose |x_m| is within this relative distance of the records' distance use the records
+constexpr double kSameDistance = 4.0 * 2.220446049250313e-16;
 constexpr int kPrepassChunk = 8192;
+
+// scan modes: polynomial records (degree 3 or 5 in b, exact geometry), far field (tau = d + b),
+// or arrival_tau per pixel in one of its forms
+constexpr int kModeRec3 = 0, kModeRec5 = 1, kModeFar = 2, kModeSqrt = 3, kModeSeries = 4, kModeShort = 5;
+// arrival_tau per pixel with the form of each pixel (series where rb2 |x_m|^-2 <= kSeriesBound)
+constexpr int kModeMixed = 6;
+
+// Record of one sample (doubles), read by the scan with scalar loads:
+//   far field:          d, x, y, z
+//   exact, degree 3:    c_0, c_1, c_2, x, y, z, d, (pad)
+//   exact, degree 5:    c_0, c_1, c_2, c_3, c_4, x, y, z, d, (pad)
+// (the leading coefficient c_DEG is the same for every sample and is not stored)
+template <int GEOM, bool F64>
+struct RecLayout {
+    static constexpr int DEG = GEOM == LW_GEOM_FARFIELD ? 0 : (F64 ? 5 : 3);
+    static constexpr int X = GEOM == LW_GEOM_FARFIELD ? 1 : DEG;      // x, y, z at X, X + 1, X + 2
+    static constexpr int D = GEOM == LW_GEOM_FARFIELD ? 0 : DEG + 3;  // d
+    static constexpr int W = GEOM == LW_GEOM_FARFIELD ? 4 : DEG + 5;  // width
+};
+__host__ __device__ constexpr int rec_width(int geom, bool f64)
+{
+    return geom == LW_GEOM_FARFIELD ? RecLayout<LW_GEOM_FARFIELD, false>::W
+                                    : (f64 ? RecLayout<LW_GEOM_EXACT, true>::W : RecLayout<LW_GEOM_EXACT, false>::W);
+}
 
 __device__ __forceinline__ double next_grid(double tau, double n_obs)
 {
@@ -88,6 +122,14 @@ __device__ __forceinline__ void lds_add(T *p, T v)
 
 // |r|^2 with the operation order of the pre-pass
 __device__ __forceinline__ double sq3(double x, double y, double z) { return fma(z, z, fma(y, y, x * x)); }
+
+// a * b + c with c in a scalar register (VOP3 form: the two-operand form would need a copy of c)
+__device__ __forceinline__ double fma_vvs(double a, double b, double c)
+{
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+    return d;
+}
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 {
@@ -116,15 +158,36 @@ __device__ __forceinline__ double uniform_double(double v)
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// The records are written by the pre-pass launch and only read while the deposit kernel runs, so
+// the scan reads them through the constant address space: with a wavefront-uniform address in
+// scalar registers these become scalar loads.
+typedef const __attribute__((address_space(4))) double *cdptr;
+__device__ __forceinline__ cdptr uniform_ptr(const double *p)
+{
+    const uint64_t b = (uint64_t)reinterpret_cast<uintptr_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return (cdptr)(((uint64_t)hi << 32) | lo);
+}
+
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct DepWs {
     int *pflag;                 // [n_p] 0 = fast path
     unsigned long long *rmax2;  // [n_p] bits of max_i |r_i|^2 (non-negative doubles order as integers)
-    double *alpha;              // [n_s] (t_i - t0)/dt_obs
+    double *rec;                // [n_p][n_s][rec_width] records
 };
 
-DepWs carve(void *ws, int64_t n_p, int64_t ns)
+// records: one more than the samples (the scan loads the record after a particle's last sample
+// ahead of time and discards it)
+size_t ws_bytes_for(int64_t n_p, int64_t ns, int rw)
+{
+    const size_t np = (size_t)std::max<int64_t>(n_p, 1), nsz = (size_t)std::max<int64_t>(ns, 1);
+    return align_up(np * sizeof(int), 256) + align_up(np * sizeof(unsigned long long), 256) +
+           align_up((np * nsz + 1) * (size_t)rw * sizeof(double), 256);
+}
+
+DepWs carve(void *ws, int64_t n_p)
 {
     DepWs w;
     char *p = (char *)ws;
@@ -132,35 +195,49 @@ DepWs carve(void *ws, int64_t n_p, int64_t ns)
     p += align_up((size_t)std::max<int64_t>(n_p, 1) * sizeof(int), 256);
     w.rmax2 = (unsigned long long *)p;
     p += align_up((size_t)std::max<int64_t>(n_p, 1) * sizeof(unsigned long long), 256);
-    w.alpha = (double *)p;
+    w.rec = (double *)p;
     return w;
 }
 
 // ---------------------------------------------------------------------------------------------
-// pre-pass: one block per (particle, chunk of samples): arrival base alpha_i, sample records,
-// per-particle max |r|^2 and the fast-path flag
+// pre-pass: one block per (particle, chunk of samples): records, per-particle max |r|^2 and the
+// fast-path flag
+template <int GEOM, int DEG>
 __global__ __launch_bounds__(256) void k_prepass(const double *__restrict__ r, const double *__restrict__ beta,
-                                                 const double *__restrict__ beta_dot, int64_t n_samples,
+                                                 const double *__restrict__ beta_dot,
+                                                 const double *__restrict__ x_det, int64_t n_samples,
                                                  int64_t sample0, double t_start, double dt, double t0,
-                                                 double dt_obs, double inv_cdt,
-                                                 double *__restrict__ alpha, int *__restrict__ pflag,
-                                                 unsigned long long *__restrict__ rmax2)
+                                                 double dt_obs, double C, double *__restrict__ rec,
+                                                 int *__restrict__ pflag, unsigned long long *__restrict__ rmax2)
 {
+    using L = RecLayout<GEOM, DEG == 5>;
     __shared__ unsigned long long s_max[4];
     __shared__ int s_bad[4];
     const int64_t k = blockIdx.x;
     const int64_t i_begin = (int64_t)blockIdx.y * kPrepassChunk;
     const int64_t i_end = std::min<int64_t>(i_begin + kPrepassChunk, n_samples);
     const double cdt_step = kC * dt;
+    const double Dref = pix_geo(x_det, 0).D;  // the records' pixel distance
     double mx = 0.0;
     int bad = 0;
     for (int64_t i = i_begin + threadIdx.x; i < i_end; i += blockDim.x) {
         const int64_t s = k * n_samples + i;
-        // sample i of the arrays is sample sample0 + i of the trajectory (spans of a longer one)
-        const double ai = ((t_start + (double)(sample0 + i) * dt) - t0) / dt_obs;
-        if (k == 0) alpha[i] = ai;
         const double *ri = r + 3 * s, *bi = beta + 3 * s, *di = beta_dot + 3 * s;
         const double x = ri[0], y = ri[1], z = ri[2];
+        // sample i of the arrays is sample sample0 + i of the trajectory (spans of a longer one)
+        const double d = arrival_base(t_start, dt, (double)(sample0 + i), t0, dt_obs, z);
+        double *o = rec + (size_t)s * L::W;
+        o[L::D] = d;
+        o[L::X] = x;
+        o[L::X + 1] = y;
+        o[L::X + 2] = z;
+        if (GEOM == LW_GEOM_EXACT) {
+            double c[DEG + 1];
+            tau_poly<DEG>(d, x, y, z, C, Dref, c);
+#pragma unroll
+            for (int j = 0; j < DEG; ++j) o[j] = c[j];
+            o[L::W - 1] = 0.0;
+        }
         const double rr = sq3(x, y, z);
         bool b = !sample_usable(ri, bi, di);
         if (!b) {
@@ -168,8 +245,9 @@ __global__ __launch_bounds__(256) void k_prepass(const double *__restrict__ r, c
             if (i > 0) {
                 const double dx = x - ri[-3], dy = y - ri[-2], dz = z - ri[-1];
                 const double step = sqrt(dx * dx + dy * dy + dz * dz);
-                const double scale = fabs(ai) + (fabs(x) + fabs(y) + fabs(z)) * inv_cdt + 1.0;
-                const double margin = (cdt_step - step) * inv_cdt;  // lower bound of tau_i - tau_{i-1}
+                // bound of the rounding of tau (its terms: d, b ~ C (|x| + |y| + 2|z|), the path term)
+                const double scale = fabs(d) + 2.0 * (fabs(x) + fabs(y) + fabs(z)) * C + 1.0;
+                const double margin = (cdt_step - step) * C;  // lower bound of tau_i - tau_{i-1}
                 b = !(margin > 1e-9 + 1e-13 * scale);
             }
         }
@@ -208,56 +286,106 @@ __global__ void k_fill(T *__restrict__ p, int64_t n)
 // ---------------------------------------------------------------------------------------------
 struct DepShape {
     int64_t n_particles, n_samples, n_pix, n_obs;
-    int64_t n_tiles, n_tile_blocks, n_groups, parts_per_group;
-    double inv_cdt;
+    int64_t n_tiles, n_groups, parts_per_group;
+    double C;  // 1/(c dt_obs)
     int fmask;
 };
 
 // Per-wavefront state of the deposit kernel.
 template <typename T, int GEOM>
 struct Wave {
-
     const double *__restrict__ r;
     const double *__restrict__ beta;
     const double *__restrict__ beta_dot;
     const double *__restrict__ charge;
     const double *__restrict__ x_det;
-    const double *__restrict__ alpha;
-    const unsigned long long *__restrict__ rmax2;
+    const double *__restrict__ rec;
     T *__restrict__ E;
     DepShape sh;
-    double invD2max;  // wavefront maximum of 1/|x_m|^2
+    double cK;  // leading coefficient of the polynomial records
+    double rb2; // the current particle's bound of |r|^2 over its whole trajectory
     int lane;
     int64_t tile, k0;
     uint2 *q;          // queue ring in LDS: {sample index, (particle - k0) << kPixBits | pixel in tile}
+    double2 *qt;       // the entry's arrival times {tau_{i-1}, tau_i}
     T *wc;             // write-combining lines in LDS, [kTilePix][WcLine<T>::P] (3 components x N)
     int *wcb;          // [kTilePix] trace segment each line holds (-1: none)
     uint32_t *want;    // [kTilePix] 1 + the furthest segment holding the grid point after a hit in this drain
     int *fpix;         // [64] pixel (in tile) of the j-th line of a flush
-    double *stage;     // staged sample records in LDS, [64][kStage]
-    PixGeo gl[kPPL];   // geometry of this lane's pixels (lane + 64 h)
+    PixC pc[kPPL];     // constants of this lane's pixels (lane + 64 h)
     uint32_t qh, qn;   // queue ring head and length
-    // arrival-time form of series particles: the short expansion goes with single-precision fields
-    static constexpr int kSer = sizeof(T) == 4 ? kTauShort : kTauSeries;
-
-    __device__ __forceinline__ bool series(int64_t k) const
-    {
-        return GEOM == LW_GEOM_EXACT && __longlong_as_double((long long)rmax2[k]) * invD2max <= kSeriesBound;
-    }
-
-    template <int FORM>
-    __device__ __forceinline__ double tau_rec(const PixGeo &g, double a, const double *p) const
-    {
-        return arrival_tau<GEOM, FORM>(g, a, p[0], p[1], p[2], sq3(p[0], p[1], p[2]), sh.inv_cdt);
-    }
-
-    __device__ __forceinline__ double tau_any(const PixGeo &g, bool ser, int64_t k, int64_t i) const
-    {
-        const double *p = r + ((size_t)k * sh.n_samples + i) * 3;
-        return ser ? tau_rec<kSer>(g, alpha[i], p) : tau_rec<kTauSqrt>(g, alpha[i], p);
-    }
 
     __device__ __forceinline__ static uint32_t qwrap(uint32_t v) { return v >= kQCap ? v - kQCap : v; }
+
+    using Lay = RecLayout<GEOM, sizeof(T) == 8>;
+    // the part of a record a scan mode reads: offset and count of doubles
+    template <int MODE>
+    static constexpr int scan_off()
+    {
+        return MODE == kModeMixed ? Lay::X : 0;
+    }
+    template <int MODE>
+    static constexpr int scan_n()
+    {
+        return MODE == kModeFar || MODE == kModeMixed ? 4 : Lay::DEG + 3;
+    }
+
+    // Arrival time of pixel h from the scan values v of a sample's record (wavefront-uniform):
+    // far field {d, x, y, z}; polynomial records {c_0 .. c_{DEG-1}, x, y, z}; arrival_tau per
+    // pixel {x, y, z, d}.
+    template <int MODE>
+    __device__ __forceinline__ double tau_of(int h, const double *v) const
+    {
+        const PixC &p = pc[h];
+        if constexpr (MODE == kModeFar) {
+            return pix_b(p, v[1], v[2], v[3]) + v[0];
+        } else if constexpr (MODE == kModeRec3 || MODE == kModeRec5) {
+            constexpr int DEG = Lay::DEG;
+            const double b = pix_b(p, v[DEG], v[DEG + 1], v[DEG + 2]);
+            double u = fma_vvs(b, cK, v[DEG - 1]);
+#pragma unroll
+            for (int j = DEG - 2; j >= 0; --j) u = fma_vvs(b, u, v[j]);
+            return u;
+        } else {
+            constexpr int FORM = sizeof(T) == 8 ? kTauSeries : kTauShort;
+            const double x = v[0], y = v[1], z = v[2], rr = sq3(x, y, z);
+            if (rb2 * (p.g.invD * p.g.invD) <= kSeriesBound) return arrival_tau<GEOM, FORM>(p, v[3], x, y, z, rr, sh.C);
+            return arrival_tau<GEOM, kTauSqrt>(p, v[3], x, y, z, rr, sh.C);
+        }
+    }
+
+    // the arrival times of both pixels of this lane, the two pixels' operation chains interleaved
+    template <int MODE>
+    __device__ __forceinline__ void tau_pair(const double *v, double *t) const
+    {
+        static_assert(kPPL == 2, "two pixels per lane");
+        if constexpr (MODE == kModeRec3 || MODE == kModeRec5) {
+            constexpr int DEG = Lay::DEG;
+            const double b0 = pix_b(pc[0], v[DEG], v[DEG + 1], v[DEG + 2]);
+            const double b1 = pix_b(pc[1], v[DEG], v[DEG + 1], v[DEG + 2]);
+            double u0 = fma_vvs(b0, cK, v[DEG - 1]);
+            double u1 = fma_vvs(b1, cK, v[DEG - 1]);
+#pragma unroll
+            for (int j = DEG - 2; j >= 0; --j) {
+                u0 = fma_vvs(b0, u0, v[j]);
+                u1 = fma_vvs(b1, u1, v[j]);
+            }
+            t[0] = u0;
+            t[1] = u1;
+        } else {
+            t[0] = tau_of<MODE>(0, v);
+            t[1] = tau_of<MODE>(1, v);
+        }
+    }
+
+    // the scan values of sample i of particle k
+    template <int MODE>
+    __device__ __forceinline__ void load_scan(int64_t k, int64_t i, double *v) const
+    {
+        const double *src = rec + ((size_t)k * sh.n_samples + i) * Lay::W + scan_off<MODE>();
+#pragma unroll
+        for (int c = 0; c < scan_n<MODE>(); ++c) v[c] = src[c];
+    }
 
     // Add the lines of pixels 64 h + (bits of `mask`) to the trace and clear them: lane l of a pass
     // takes value l % 3N (component (l % 3N) / N, grid point l % N) of the (l / 3N)-th line.
@@ -287,32 +415,38 @@ struct Wave {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         const bool act = (uint32_t)lane < cnt;
-        const uint2 e = act ? q[qwrap(qh + (uint32_t)lane)] : make_uint2(1u, 0u);
+        const uint32_t slot = qwrap(qh + (uint32_t)lane);
+        const uint2 e = act ? q[slot] : make_uint2(1u, 0u);
+        const double2 tt = act ? qt[slot] : make_double2(0.0, 1.0);
         const int ml0 = (int)(e.y & (uint32_t)(kTilePix - 1));
-        // the entry's pixel geometry from the lane that owns the pixel (all lanes take part)
+        // far field: the entry's pixel direction from the lane that owns the pixel (all lanes take part)
         PixGeo g;
-        {
+        if (GEOM == LW_GEOM_FARFIELD) {
             const int own = ml0 & 63, hh = ml0 >> 6;
             auto pick = [&](double v0, double v1) {
                 const double a = __shfl(v0, own);
-                const double b = kPPL > 1 ? __shfl(v1, own) : a;
+                const double b = __shfl(v1, own);
                 return hh ? b : a;
             };
-            g.nx = pick(gl[0].nx, gl[kPPL - 1].nx);
-            g.ny = pick(gl[0].ny, gl[kPPL - 1].ny);
-            g.nz = pick(gl[0].nz, gl[kPPL - 1].nz);
-            g.D = pick(gl[0].D, gl[kPPL - 1].D);
-            g.invD = pick(gl[0].invD, gl[kPPL - 1].invD);
+            g.nx = pick(pc[0].g.nx, pc[kPPL - 1].g.nx);
+            g.ny = pick(pc[0].g.ny, pc[kPPL - 1].g.ny);
+            g.nz = pick(pc[0].g.nz, pc[kPPL - 1].g.nz);
+            g.invD = pick(pc[0].g.invD, pc[kPPL - 1].g.invD);
+            g.D = 1.0 / g.invD;
+            g.ok = true;
+        } else {
+            g.nx = g.ny = 0.0;
+            g.nz = g.D = g.invD = 1.0;
             g.ok = true;
         }
-        // the entry's interval: arrival times, fields at both ends and grid points [u0, u1)
-        double ta = 0.0;
+        // the entry's interval: fields at both ends and grid points [u0, u1)
+        const double ta = tt.x, tb = tt.y;
         int u0 = 0, u1 = 0;
         T idt = (T)0, eax = (T)0, eay = (T)0, eaz = (T)0, ebx = (T)0, eby = (T)0, ebz = (T)0;
         constexpr int NL = WcLine<T>::N;
         if (act) {
             const uint32_t i = e.x, kl = e.y;
-            const int64_t k = k0 + (int64_t)((kl & ~kSerBit) >> kPixBits);
+            const int64_t k = k0 + (int64_t)(kl >> kPixBits);
             const int ml = ml0;
             const int64_t m = tile * kTilePix + ml;
             // both samples of the interval, each value loaded once (all loads issued first)
@@ -321,18 +455,8 @@ struct Wave {
             const double rax = ra[0], ray = ra[1], raz = ra[2], rbx = ra[3], rby = ra[4], rbz = ra[5];
             const double bax = ba[0], bay = ba[1], baz = ba[2], bbx = ba[3], bby = ba[4], bbz = ba[5];
             const double dax = da[0], day = da[1], daz = da[2], dbx = da[3], dby = da[4], dbz = da[5];
-            const double ala = alpha[i - 1], alb = alpha[i];
             const double q = charge ? charge[k] : -kQe;
             const double *xm = x_det + 3 * m;
-            // arrival times in the form and operation order of the scan (same bits)
-            double tb;
-            if (kl & kSerBit) {
-                ta = arrival_tau<GEOM, kSer>(g, ala, rax, ray, raz, sq3(rax, ray, raz), sh.inv_cdt);
-                tb = arrival_tau<GEOM, kSer>(g, alb, rbx, rby, rbz, sq3(rbx, rby, rbz), sh.inv_cdt);
-            } else {
-                ta = arrival_tau<GEOM, kTauSqrt>(g, ala, rax, ray, raz, sq3(rax, ray, raz), sh.inv_cdt);
-                tb = arrival_tau<GEOM, kTauSqrt>(g, alb, rbx, rby, rbz, sq3(rbx, rby, rbz), sh.inv_cdt);
-            }
             lw_field<T, GEOM>(g, xm, rax, ray, raz, bax, bay, baz, dax, day, daz, q, sh.fmask, eax, eay, eaz);
             lw_field<T, GEOM>(g, xm, rbx, rby, rbz, bbx, bby, bbz, dbx, dby, dbz, q, sh.fmask, ebx, eby, ebz);
             // grid indices fit in 32 bits (n_obs < 2^31, checked on the host)
@@ -405,10 +529,14 @@ struct Wave {
         qn = __builtin_amdgcn_readfirstlane(qn - cnt);
     }
 
-    // Append the lanes with `hit` set (callers drain before 2 x kTilePix more can arrive).
-    __device__ __forceinline__ void push(bool hit, uint64_t mask, uint32_t i, uint32_t tag)
+    // Append the lanes with `hit` set (callers drain before kTilePix more can arrive).
+    __device__ __forceinline__ void push(bool hit, uint64_t mask, uint32_t i, uint32_t tag, double ta, double tb)
     {
-        if (hit) q[qwrap(qh + qn + lanes_below(mask))] = make_uint2(i, tag);
+        if (hit) {
+            const uint32_t slot = qwrap(qh + qn + lanes_below(mask));
+            q[slot] = make_uint2(i, tag);
+            qt[slot] = make_double2(ta, tb);
+        }
         qn = __builtin_amdgcn_readfirstlane(qn + (uint32_t)__popcll(mask));  // wavefront-uniform
     }
 
@@ -417,102 +545,100 @@ struct Wave {
         while (qn >= 64) drain(64);
     }
 
-    // Fast path: tau strictly increasing, all samples usable.  Samples go through LDS in
-    // chunks of 64 (lane j loads sample c0 + j with vector loads one chunk ahead); every lane
-    // then reads the staged samples by broadcast, two per trip, each for its kPPL pixels.
-    template <int FORM>
-    __device__ void fast_particle(const PixGeo *g, const bool *lane_ok, const bool *pix_in, int64_t k,
-                                  unsigned long long &c1, unsigned long long &c2, unsigned long long &c3)
+    // queue the crossings of the intervals (tp[h], tv[h]] ending at sample jj (at most kTilePix)
+    __device__ __forceinline__ void hits(uint32_t jj, uint32_t tag0, const double *tp, const double *tv,
+                                         double *gnext, double nob)
     {
-        const int64_t ns = sh.n_samples;
+#pragma unroll
+        for (int h = 0; h < kPPL; ++h) {
+            const bool hit = tv[h] >= gnext[h];
+            const uint64_t mask = __ballot(hit);
+            if (mask) {
+                if (hit) {
+                    const double f = floor(tv[h]) + 1.0;
+                    gnext[h] = f >= nob ? INFINITY : f;
+                }
+                push(hit, mask, jj, tag0 + 64u * (uint32_t)h, tp[h], tv[h]);
+            }
+        }
+    }
+
+    // Scan of a fast-path particle from sample j on: every arrival time is evaluated and tested
+    // against the pixel's next grid point, crossings are queued; returns the next sample to scan
+    // once the queue holds 64 or more entries (the caller drains it), or n_samples.  Records are
+    // wavefront-uniform loads into two alternating buffers: the next sample's load is issued
+    // once the current one has arrived, before the current sample's arithmetic.
+    template <int MODE>
+    __device__ __forceinline__ int scan_run(int64_t k, int j, int ns, uint32_t tag0, double *tau, double *gnext,
+                                            double nob)
+    {
+        constexpr int NV = scan_n<MODE>();
+        constexpr int W = Lay::W;
+        cdptr p = uniform_ptr(rec + ((size_t)k * sh.n_samples + j) * W + scan_off<MODE>());
+        double A[NV], B[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) A[c] = p[c];
+        // sample j from the scan values V: its arrival times, their tests and the queue; leaves the
+        // scan (returning the next sample) when the queue needs draining
+#define LW_SCAN_STEP(V)                                                                                               \
+    {                                                                                                                 \
+        double t[kPPL];                                                                                               \
+        tau_pair<MODE>(V, t);                                                                                         \
+        uint64_t any = 0;                                                                                             \
+        _Pragma("unroll") for (int h = 0; h < kPPL; ++h) any |= __ballot(t[h] >= gnext[h]);                          \
+        if (any) {                                                                                                    \
+            hits((uint32_t)j, tag0, tau, t, gnext, nob);                                                              \
+            if (qn >= 64) {                                                                                           \
+                _Pragma("unroll") for (int h = 0; h < kPPL; ++h) tau[h] = t[h];                                       \
+                return j + 1;                                                                                         \
+            }                                                                                                         \
+        }                                                                                                             \
+        _Pragma("unroll") for (int h = 0; h < kPPL; ++h) tau[h] = t[h];                                               \
+    }
+        for (;;) {
+            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the record of sample j is in
+            __builtin_amdgcn_sched_barrier(0);
+            p += W;  // the next sample's record (past the last one: the next particle's, or padding)
+#pragma unroll
+            for (int c = 0; c < NV; ++c) B[c] = p[c];
+            __builtin_amdgcn_sched_barrier(0);
+            LW_SCAN_STEP(A)
+            if (++j >= ns) return j;
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            __builtin_amdgcn_sched_barrier(0);
+            p += W;
+#pragma unroll
+            for (int c = 0; c < NV; ++c) A[c] = p[c];
+            __builtin_amdgcn_sched_barrier(0);
+            LW_SCAN_STEP(B)
+            if (++j >= ns) return j;
+        }
+#undef LW_SCAN_STEP
+    }
+
+    // Fast path: tau strictly increasing, all samples usable.
+    template <int MODE>
+    __device__ __forceinline__ void fast_particle(const bool *lane_ok, const bool *pix_in, int64_t k,
+                                                  unsigned long long &c1, unsigned long long &c2,
+                                                  unsigned long long &c3)
+    {
+        constexpr int NV = scan_n<MODE>();
+        const int ns = (int)sh.n_samples;
         const double nob = (double)sh.n_obs;
-        const double *s0 = r + (size_t)k * ns * 3;
-        const uint32_t tag0 = ((uint32_t)(k - k0) << kPixBits) | (uint32_t)lane | (FORM == kTauSqrt ? 0u : kSerBit);
-        double pa, px, py, pz, prr;
-        // unconditional (clamped) loads, so that they stay in flight until the next chunk
-        auto fetch = [&](int64_t c0) {
-            const int64_t idx = std::min<int64_t>(c0 + lane, ns - 1);
-            const double *p = s0 + (size_t)idx * 3;
-            pa = alpha[idx];
-            px = p[0];
-            py = p[1];
-            pz = p[2];
-            prr = GEOM == LW_GEOM_EXACT ? sq3(px, py, pz) : 0.0;
-        };
-        fetch(0);
+        const uint32_t tag0 = ((uint32_t)(k - k0) << kPixBits) | (uint32_t)lane;
         double tau[kPPL], tau0[kPPL], gnext[kPPL];
-        for (int64_t c0 = 0; c0 < ns; c0 += 64) {
-            double *st = stage + lane * kStage;
-            st[0] = pa;
-            st[1] = px;
-            st[2] = py;
-            st[3] = pz;
-            st[4] = prr;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            fetch(c0 + 64);
-            const int cnt = (int)std::min<int64_t>(64, ns - c0);
-            int j = 0;
-            if (c0 == 0) {
+        {
+            double v[NV];
+            load_scan<MODE>(k, 0, v);
 #pragma unroll
-                for (int h = 0; h < kPPL; ++h) {
-                    tau[h] = tau0[h] =
-                        arrival_tau<GEOM, FORM>(g[h], stage[0], stage[1], stage[2], stage[3], stage[4], sh.inv_cdt);
-                    gnext[h] = lane_ok[h] ? next_grid(tau[h], nob) : INFINITY;
-                }
-                j = 1;
+            for (int h = 0; h < kPPL; ++h) {
+                tau[h] = tau0[h] = tau_of<MODE>(h, v);
+                gnext[h] = lane_ok[h] ? next_grid(tau[h], nob) : INFINITY;
             }
-            // queue the crossings of the arrival times tv of sample jj
-            auto hits = [&](int jj, const double *tv) {
-#pragma unroll
-                for (int h = 0; h < kPPL; ++h) {
-                    const bool hit = tv[h] >= gnext[h];
-                    const uint64_t mask = __ballot(hit);
-                    if (mask) {
-                        if (hit) {
-                            const double f = floor(tv[h]) + 1.0;
-                            gnext[h] = f >= nob ? INFINITY : f;
-                        }
-                        push(hit, mask, (uint32_t)(c0 + jj), tag0 + 64u * (uint32_t)h);
-                    }
-                }
-            };
-            auto step = [&](int jj, const double *e) {
-#pragma unroll
-                for (int h = 0; h < kPPL; ++h)
-                    tau[h] = arrival_tau<GEOM, FORM>(g[h], e[0], e[1], e[2], e[3], e[4], sh.inv_cdt);
-                hits(jj, tau);
-            };
-            for (; j + 1 < cnt; j += 2) {
-                double v[2][5];
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-#pragma unroll
-                    for (int c = 0; c < 5; ++c) v[u][c] = stage[(j + u) * kStage + c];
-                // every arrival time is evaluated; one test per pixel on the later sample of the
-                // pair (arrival times increase) decides whether the crossing logic runs
-                double t0v[kPPL], t1v[kPPL];
-                bool any = false;
-#pragma unroll
-                for (int h = 0; h < kPPL; ++h) {
-                    t0v[h] = arrival_tau<GEOM, FORM>(g[h], v[0][0], v[0][1], v[0][2], v[0][3], v[0][4], sh.inv_cdt);
-                    t1v[h] = arrival_tau<GEOM, FORM>(g[h], v[1][0], v[1][1], v[1][2], v[1][3], v[1][4], sh.inv_cdt);
-                    any |= (t0v[h] >= gnext[h]) | (t1v[h] >= gnext[h]);
-                }
-                if (__ballot(any)) {
-                    hits(j, t0v);
-                    hits(j + 1, t1v);
-                    pump();
-                }
-#pragma unroll
-                for (int h = 0; h < kPPL; ++h) tau[h] = t1v[h];
-            }
-            for (; j < cnt; ++j) {
-                step(j, stage + j * kStage);
-                pump();
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+        }
+        for (int j = 1; j < ns;) {
+            j = scan_run<MODE>(k, j, ns, tag0, tau, gnext, nob);
+            pump();
         }
 #pragma unroll
         for (int h = 0; h < kPPL; ++h) {
@@ -530,20 +656,22 @@ struct Wave {
     // particle deposits into this wavefront's pixels only if some pixel has a window grid point
     // in (tau_first, tau_last].  If none has, the counters follow from the two end points and
     // the particle is skipped; the results are those of the full scan.
-    template <int FORM>
-    __device__ bool outside(const PixGeo *g, const bool *lane_ok, const bool *pix_in, int64_t k,
-                            unsigned long long &c1, unsigned long long &c2)
+    template <int MODE>
+    __device__ __forceinline__ bool outside(const bool *lane_ok, const bool *pix_in, int64_t k, unsigned long long &c1,
+                                            unsigned long long &c2)
     {
+        constexpr int NV = scan_n<MODE>();
         const int64_t ns = sh.n_samples;
         const double nob = (double)sh.n_obs;
-        const double *p0 = r + (size_t)k * ns * 3, *p1 = p0 + (size_t)(ns - 1) * 3;
-        const double a0 = alpha[0], a1 = alpha[ns - 1];
+        double v0[NV], v1[NV];
+        load_scan<MODE>(k, 0, v0);
+        load_scan<MODE>(k, ns - 1, v1);
         double tf[kPPL], tl[kPPL];
         bool in = false;
 #pragma unroll
         for (int h = 0; h < kPPL; ++h) {
-            tf[h] = arrival_tau<GEOM, FORM>(g[h], a0, p0[0], p0[1], p0[2], sq3(p0[0], p0[1], p0[2]), sh.inv_cdt);
-            tl[h] = arrival_tau<GEOM, FORM>(g[h], a1, p1[0], p1[1], p1[2], sq3(p1[0], p1[1], p1[2]), sh.inv_cdt);
+            tf[h] = tau_of<MODE>(h, v0);
+            tl[h] = tau_of<MODE>(h, v1);
             in |= lane_ok[h] && grid_count(tl[h], nob) > grid_count(tf[h], nob);
         }
         if (__ballot(in)) return false;
@@ -557,28 +685,34 @@ struct Wave {
         return true;
     }
 
-    // Careful path: the skip rules of lw_deposit_td interval by interval.
-    __device__ void careful_particle(const PixGeo &g, bool lane_ok, bool pix_in, int64_t m, int h, int64_t k,
-                                     unsigned long long &c0, unsigned long long &c1, unsigned long long &c2,
-                                     unsigned long long &c3)
+    // Careful path: the skip rules of lw_deposit_td interval by interval, pixel h of this lane,
+    // with the arrival times of the fast path's MODE (the same values wherever a particle takes
+    // the fast path in one span and the careful path in another).
+    template <int MODE, int H>
+    __device__ __forceinline__ void careful_particle(bool lane_ok, bool pix_in, int64_t m, int64_t k,
+                                                     unsigned long long &c0, unsigned long long &c1,
+                                                     unsigned long long &c2, unsigned long long &c3)
     {
+        constexpr int NV = scan_n<MODE>();
         const int64_t ns = sh.n_samples;
         const double nob = (double)sh.n_obs;
-        const bool ser = series(k);
         const double q = charge ? charge[k] : -kQe;
         bool prev_ok = false;
         double tprev = 0.0;
-        const uint32_t tag = ((uint32_t)(k - k0) << kPixBits) | (uint32_t)(lane + 64 * h) | (ser ? kSerBit : 0u);
+        const uint32_t tag = ((uint32_t)(k - k0) << kPixBits) | (uint32_t)(lane + 64 * H);
         for (int64_t i = 0; i < ns; ++i) {
             const size_t s = (size_t)k * ns + i;
+            double v[NV];
+            load_scan<MODE>(k, i, v);
+            const double x = r[3 * s], y = r[3 * s + 1], z = r[3 * s + 2];
             bool ok = lane_ok && sample_usable(r + 3 * s, beta + 3 * s, beta_dot + 3 * s);
+            const double tv = tau_of<MODE>(H, v);
             double tau = NAN;
             if (ok) {
-                tau = tau_any(g, ser, k, i);
+                tau = tv;
                 T ex, ey, ez;
-                lw_field<T, GEOM>(g, x_det + 3 * m, r[3 * s], r[3 * s + 1], r[3 * s + 2], beta[3 * s],
-                                  beta[3 * s + 1], beta[3 * s + 2], beta_dot[3 * s], beta_dot[3 * s + 1],
-                                  beta_dot[3 * s + 2], q, sh.fmask, ex, ey, ez);
+                lw_field<T, GEOM>(pc[H].g, x_det + 3 * m, x, y, z, beta[3 * s], beta[3 * s + 1], beta[3 * s + 2],
+                                  beta_dot[3 * s], beta_dot[3 * s + 1], beta_dot[3 * s + 2], q, sh.fmask, ex, ey, ez);
                 ok = isfinite(tau) && isfinite((double)ex) && isfinite((double)ey) && isfinite((double)ez);
             }
             bool hit = false;
@@ -596,81 +730,105 @@ struct Wave {
             }
             const uint64_t mask = __ballot(hit);
             if (mask) {
-                push(hit, mask, (uint32_t)i, tag);
+                push(hit, mask, (uint32_t)i, tag, tprev, tau);
                 pump();
             }
             prev_ok = ok;
             tprev = tau;
         }
     }
+
+    // One particle in scan mode MODE: culled (LW_CULL), fast or careful path.
+    template <int MODE, bool CULL>
+    __device__ __forceinline__ void particle(bool fast, const bool *lane_ok, const bool *pix_in, const int64_t *m,
+                                             int64_t k, unsigned long long &c0, unsigned long long &c1,
+                                             unsigned long long &c2, unsigned long long &c3)
+    {
+        static_assert(kPPL == 2, "careful path written for two pixels per lane");
+        if (fast) {
+            if (CULL && outside<MODE>(lane_ok, pix_in, k, c1, c2)) return;
+            fast_particle<MODE>(lane_ok, pix_in, k, c1, c2, c3);
+        } else {
+            careful_particle<MODE, 0>(lane_ok[0], pix_in[0], m[0], k, c0, c1, c2, c3);
+            careful_particle<MODE, 1>(lane_ok[1], pix_in[1], m[1], k, c0, c1, c2, c3);
+        }
+    }
 };
 
 template <typename T, int GEOM, bool CULL>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_deposit(const double *__restrict__ r, const double *__restrict__ beta,
-                                                 const double *__restrict__ beta_dot,
-                                                 const double *__restrict__ charge, const double *__restrict__ x_det,
-                                                 const double *__restrict__ alpha,
-                                                 const int *__restrict__ pflag,
-                                                 const unsigned long long *__restrict__ rmax2, T *__restrict__ E,
-                                                 unsigned long long *__restrict__ diag, DepShape sh)
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_deposit(
+    const double *__restrict__ r, const double *__restrict__ beta, const double *__restrict__ beta_dot,
+    const double *__restrict__ charge, const double *__restrict__ x_det, const double *__restrict__ rec,
+    const int *__restrict__ pflag, const unsigned long long *__restrict__ rmax2, const double *__restrict__ rbound2,
+    T *__restrict__ E, unsigned long long *__restrict__ diag, DepShape sh)
 {
-    __shared__ uint2 q_all[kWavesPerBlock][kQCap];
-    __shared__ T wc_all[kWavesPerBlock][kTilePix * WcLine<T>::P];
-    __shared__ int wcb_all[kWavesPerBlock][kTilePix];
-    __shared__ uint32_t want_all[kWavesPerBlock][kTilePix];
-    __shared__ int fpix_all[kWavesPerBlock][64];
-    __shared__ double stage_all[kWavesPerBlock][64 * kStage];
+    constexpr bool kF64 = sizeof(T) == 8;
+    constexpr int kRec = kF64 ? kModeRec5 : kModeRec3;
+    __shared__ uint2 q_all[kQCap];
+    __shared__ double2 qt_all[kQCap];
+    __shared__ T wc_all[kTilePix * WcLine<T>::P];
+    __shared__ int wcb_all[kTilePix];
+    __shared__ uint32_t want_all[kTilePix];
+    __shared__ int fpix_all[64];
     __shared__ unsigned long long red[4];
     const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
     if (threadIdx.x < 4) red[threadIdx.x] = 0ull;
     __syncthreads();
 
-    // block -> (particle group, tile block); consecutive groups on one XCD share trajectory lines in L2
+    // block -> (particle group, tile); consecutive groups on one XCD share trajectory lines in L2
     const int64_t b = blockIdx.x;
     const int64_t xcd = b & 7, slot = b >> 3;
-    const int64_t grp = (slot / sh.n_tile_blocks) * 8 + xcd;
-    const int64_t tile = (slot % sh.n_tile_blocks) * kWavesPerBlock + wv;
+    const int64_t grp = (slot / sh.n_tiles) * 8 + xcd;
+    const int64_t tile = slot % sh.n_tiles;
     const int64_t k0 = grp * sh.parts_per_group;
     const int64_t k1 = grp < sh.n_groups ? std::min(k0 + sh.parts_per_group, sh.n_particles) : k0;
-    const bool wave_live = tile < sh.n_tiles;
 
+    Wave<T, GEOM> w;
     int64_t m[kPPL];
     bool pix_in[kPPL], lane_ok[kPPL];
-    PixGeo g[kPPL];
     double id2 = 0.0;
+    const double Dref = pix_geo(x_det, 0).D;  // the records' pixel distance
+    bool far_off = false;                     // a pixel of this wavefront at another distance
 #pragma unroll
     for (int h = 0; h < kPPL; ++h) {
         m[h] = tile * kTilePix + 64 * h + lane;
-        pix_in[h] = wave_live && m[h] < sh.n_pix;
-        g[h] = pix_geo(x_det, pix_in[h] ? m[h] : 0);
-        lane_ok[h] = pix_in[h] && g[h].ok;
-        if (lane_ok[h]) id2 = fmax(id2, g[h].invD * g[h].invD);
+        pix_in[h] = m[h] < sh.n_pix;
+        w.pc[h] = pix_const(x_det, pix_in[h] ? m[h] : 0, sh.C);
+        lane_ok[h] = pix_in[h] && w.pc[h].g.ok;
+        if (lane_ok[h]) {
+            id2 = fmax(id2, w.pc[h].g.invD * w.pc[h].g.invD);
+            far_off |= !(fabs(w.pc[h].g.D - Dref) <= kSameDistance * Dref);
+        }
     }
     for (int off = 32; off > 0; off >>= 1) id2 = fmax(id2, __shfl_xor(id2, off));
+    const double invD2max = uniform_double(id2);
+    const bool rec_ok = GEOM == LW_GEOM_EXACT && __ballot(far_off) == 0;
+    {
+        double c[6];
+        if (kF64)
+            tau_poly<5>(0.0, 0.0, 0.0, 0.0, sh.C, Dref, c);
+        else
+            tau_poly<3>(0.0, 0.0, 0.0, 0.0, sh.C, Dref, c);
+        w.cK = c[kF64 ? 5 : 3];
+    }
 
-    Wave<T, GEOM> w;
     w.r = r;
     w.beta = beta;
     w.beta_dot = beta_dot;
     w.charge = charge;
     w.x_det = x_det;
-    w.alpha = alpha;
-    w.rmax2 = rmax2;
+    w.rec = rec;
     w.E = E;
     w.sh = sh;
-    w.invD2max = uniform_double(id2);
     w.lane = lane;
     w.tile = tile;
     w.k0 = k0;
-    w.q = q_all[wv];
-    w.wc = wc_all[wv];
-    w.wcb = wcb_all[wv];
-    w.want = want_all[wv];
-    w.fpix = fpix_all[wv];
-    w.stage = stage_all[wv];
-#pragma unroll
-    for (int h = 0; h < kPPL; ++h) w.gl[h] = g[h];
+    w.q = q_all;
+    w.qt = qt_all;
+    w.wc = wc_all;
+    w.wcb = wcb_all;
+    w.want = want_all;
+    w.fpix = fpix_all;
     w.qh = 0;
     w.qn = 0;
     for (int j = lane; j < kTilePix * WcLine<T>::P; j += 64) w.wc[j] = (T)0;
@@ -682,19 +840,18 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     __builtin_amdgcn_wave_barrier();
 
     unsigned long long c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-    for (int64_t k = wave_live ? k0 : k1; k < k1; ++k) {
-        if (pflag[k] == 0) {
-            if (GEOM == LW_GEOM_EXACT && w.series(k)) {
-                if (CULL && w.template outside<Wave<T, GEOM>::kSer>(g, lane_ok, pix_in, k, c1, c2)) continue;
-                w.template fast_particle<Wave<T, GEOM>::kSer>(g, lane_ok, pix_in, k, c1, c2, c3);
-            } else {
-                if (CULL && w.template outside<kTauSqrt>(g, lane_ok, pix_in, k, c1, c2)) continue;
-                w.template fast_particle<kTauSqrt>(g, lane_ok, pix_in, k, c1, c2, c3);
-            }
-        } else {
-#pragma unroll
-            for (int h = 0; h < kPPL; ++h) w.careful_particle(g[h], lane_ok[h], pix_in[h], m[h], h, k, c0, c1, c2, c3);
-        }
+    for (int64_t k = k0; k < k1; ++k) {
+        // series forms where |r|^2 <= 1e-8 |x_m|^2 over the whole trajectory (the max over the
+        // whole trajectory when given, else over the samples of this call), decided per pixel
+        w.rb2 = rbound2 ? rbound2[k] : __longlong_as_double((long long)rmax2[k]);
+        const bool all_ser = GEOM == LW_GEOM_EXACT && w.rb2 * invD2max <= kSeriesBound;
+        const bool fast = pflag[k] == 0;
+        if (GEOM == LW_GEOM_FARFIELD)
+            w.template particle<kModeFar, CULL>(fast, lane_ok, pix_in, m, k, c0, c1, c2, c3);
+        else if (all_ser && rec_ok)
+            w.template particle<kRec, CULL>(fast, lane_ok, pix_in, m, k, c0, c1, c2, c3);
+        else
+            w.template particle<kModeMixed, CULL>(fast, lane_ok, pix_in, m, k, c0, c1, c2, c3);
     }
     while (w.qn > 0) w.drain(w.qn < 64 ? w.qn : 64);
 #pragma unroll
@@ -709,17 +866,29 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     if (diag && threadIdx.x < 4 && red[threadIdx.x]) atomicAdd(diag + threadIdx.x, red[threadIdx.x]);
 }
 
+template <int GEOM>
+void launch_prepass(bool f64, dim3 grid, hipStream_t s, const double *r, const double *b, const double *bd,
+                    const double *x_det, int64_t ns, int64_t sample0, double t_start, double dt, double t0,
+                    double dt_obs, double C, const DepWs &w)
+{
+    if (f64)
+        k_prepass<GEOM, 5><<<grid, 256, 0, s>>>(r, b, bd, x_det, ns, sample0, t_start, dt, t0, dt_obs, C, w.rec,
+                                               w.pflag, w.rmax2);
+    else
+        k_prepass<GEOM, 3><<<grid, 256, 0, s>>>(r, b, bd, x_det, ns, sample0, t_start, dt, t0, dt_obs, C, w.rec,
+                                               w.pflag, w.rmax2);
+}
+
 }  // namespace
 
-size_t deposit_ws_bytes(int64_t n_particles, int64_t n_samples)
+size_t deposit_ws_bytes(int64_t n_particles, int64_t n_samples, int prec)
 {
-    const size_t np = (size_t)std::max<int64_t>(n_particles, 1), ns = (size_t)std::max<int64_t>(n_samples, 1);
-    return align_up(np * sizeof(int), 256) + align_up(np * sizeof(unsigned long long), 256) +
-           align_up(ns * sizeof(double), 256);
+    return ws_bytes_for(n_particles, n_samples, rec_width(LW_GEOM_EXACT, prec == LW_PREC_FP64));
 }
 
 lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int fmask, int geom, bool accumulate,
-                         void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s, int64_t sample0)
+                         void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s, int64_t sample0,
+                         const double *rbound2)
 {
     const int64_t n_p = t->n_particles, ns = t->n_samples, n_pix = gr->n_pix, n_obs = gr->n_obs;
     const bool cull = (geom & LW_CULL) != 0;
@@ -727,25 +896,7 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
     const size_t trace_elems = (size_t)n_pix * 3 * (size_t)n_obs;
     const bool f64 = prec == LW_PREC_FP64;
     if (n_obs > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: n_obs must be below 2^31");
-    DepShape sh;
-    sh.n_particles = n_p;
-    sh.n_samples = ns;
-    sh.n_pix = n_pix;
-    sh.n_obs = n_obs;
-    sh.n_tiles = (n_pix + kTilePix - 1) / kTilePix;
-    sh.n_tile_blocks = (sh.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    int64_t groups = std::max<int64_t>(1, (kTargetWaves + std::max<int64_t>(sh.n_tiles, 1) - 1) /
-                                              std::max<int64_t>(sh.n_tiles, 1));
-    groups = std::max<int64_t>(1, std::min<int64_t>(groups, n_p));
-    sh.parts_per_group = std::max<int64_t>(1, (n_p + groups - 1) / groups);
-    sh.n_groups = (n_p + sh.parts_per_group - 1) / sh.parts_per_group;
-    sh.fmask = fmask;
-    const int64_t chunks = (ns + kPrepassChunk - 1) / kPrepassChunk;
-    const int64_t blocks = (sh.n_groups + 7) / 8 * 8 * sh.n_tile_blocks;
-    if (sh.parts_per_group >= (int64_t(1) << (31 - kPixBits)))
-        return fail(LW_E_SHAPE, "lw_deposit_td: too many particles per pixel tile group");
-    if (n_p > 0x7fffffff || chunks > 65535) return fail(LW_E_SHAPE, "lw_deposit_td: too many samples");
-    if (blocks > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: problem too large for one launch");
+    if (ns > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: too many samples");
     if (!accumulate) {
         if (trace_elems) {
             const int blocks = (int)std::min<size_t>((trace_elems + 255) / 256, 65536);
@@ -757,40 +908,76 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
         if (diag) k_fill<unsigned long long><<<1, 64, 0, s>>>((unsigned long long *)diag, 4);
     }
     if (n_p == 0 || n_pix == 0 || ns == 0) return check_launch("deposit fill");
-    const DepWs w = carve(ws, n_p, ns);
-    const double inv_cdt = 1.0 / (kC * gr->dt_obs);
-    sh.inv_cdt = inv_cdt;
-    const int fill_blocks = (int)std::min<int64_t>((n_p + 255) / 256, 65536);
-    k_fill<int><<<fill_blocks, 256, 0, s>>>(w.pflag, n_p);
-    k_fill<unsigned long long><<<fill_blocks, 256, 0, s>>>(w.rmax2, n_p);
-    {
-        k_prepass<<<dim3((unsigned)n_p, (unsigned)chunks), 256, 0, s>>>(
-            t->r, t->beta, t->beta_dot, ns, sample0, t->t_start, t->dt, gr->t0, gr->dt_obs, inv_cdt, w.alpha, w.pflag,
-            w.rmax2);
-    }
-    unsigned long long *dg = (unsigned long long *)diag;
-    const dim3 grid((unsigned)blocks), block(kBlockThreads);
-#define LW_DEPOSIT_LAUNCH(T, G, C)                                                                                  \
-    k_deposit<T, G, C><<<grid, block, 0, s>>>(t->r, t->beta, t->beta_dot, t->charge, gr->x_det, w.alpha, w.pflag,    \
-                                              w.rmax2, (T *)E, dg, sh)
-    // culling is a separate instantiation: the full evaluation carries none of its code
-    hipEvent_t t_start = timing_begin(LW_KERNEL_DEPOSIT, s);
-    if (f64) {
-        if (geom == LW_GEOM_EXACT) {
-            if (cull) LW_DEPOSIT_LAUNCH(double, LW_GEOM_EXACT, true); else LW_DEPOSIT_LAUNCH(double, LW_GEOM_EXACT, false);
+    const int rw = rec_width(geom, f64);
+    // particles per launch: all of them, or as many as the workspace holds records for
+    int64_t chunk = n_p;
+    while (chunk > 1 && ws_bytes_for(chunk, ns, rw) > ws_bytes) chunk = std::max<int64_t>(1, chunk / 2);
+    if (ws_bytes_for(chunk, ns, rw) > ws_bytes)
+        return fail(LW_E_WORKSPACE, "lw_deposit_td: workspace of %zu bytes holds no particle (%zu needed)", ws_bytes,
+                    ws_bytes_for(1, ns, rw));
+    const double C = 1.0 / (kC * gr->dt_obs);
+    const int64_t n_chunks_s = (ns + kPrepassChunk - 1) / kPrepassChunk;
+    if (n_chunks_s > 65535) return fail(LW_E_SHAPE, "lw_deposit_td: too many samples");
+    for (int64_t p0 = 0; p0 < n_p; p0 += chunk) {
+        const int64_t np = std::min<int64_t>(chunk, n_p - p0);
+        DepShape sh;
+        sh.n_particles = np;
+        sh.n_samples = ns;
+        sh.n_pix = n_pix;
+        sh.n_obs = n_obs;
+        sh.n_tiles = (n_pix + kTilePix - 1) / kTilePix;
+        int64_t groups = std::max<int64_t>(1, (kTargetWaves + sh.n_tiles - 1) / sh.n_tiles);
+        groups = std::max<int64_t>(1, std::min<int64_t>(groups, np));
+        sh.parts_per_group = std::max<int64_t>(1, (np + groups - 1) / groups);
+        sh.n_groups = (np + sh.parts_per_group - 1) / sh.parts_per_group;
+        sh.fmask = fmask;
+        sh.C = C;
+        const int64_t blocks = (sh.n_groups + 7) / 8 * 8 * sh.n_tiles;
+        if (sh.parts_per_group >= (int64_t(1) << (32 - kPixBits)))
+            return fail(LW_E_SHAPE, "lw_deposit_td: too many particles per pixel tile group");
+        if (np > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: too many particles");
+        if (blocks > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: problem too large for one launch");
+        const DepWs w = carve(ws, np);
+        const double *r = t->r + (size_t)p0 * ns * 3, *b = t->beta + (size_t)p0 * ns * 3,
+                     *bd = t->beta_dot + (size_t)p0 * ns * 3;
+        const double *charge = t->charge ? t->charge + p0 : nullptr;
+        const double *rb2 = rbound2 ? rbound2 + p0 : nullptr;
+        const int fill_blocks = (int)std::min<int64_t>((np + 255) / 256, 65536);
+        k_fill<int><<<fill_blocks, 256, 0, s>>>(w.pflag, np);
+        k_fill<unsigned long long><<<fill_blocks, 256, 0, s>>>(w.rmax2, np);
+        const dim3 pgrid((unsigned)np, (unsigned)n_chunks_s);
+        if (geom == LW_GEOM_EXACT)
+            launch_prepass<LW_GEOM_EXACT>(f64, pgrid, s, r, b, bd, gr->x_det, ns, sample0, t->t_start, t->dt, gr->t0,
+                                          gr->dt_obs, C, w);
+        else
+            launch_prepass<LW_GEOM_FARFIELD>(f64, pgrid, s, r, b, bd, gr->x_det, ns, sample0, t->t_start, t->dt,
+                                             gr->t0, gr->dt_obs, C, w);
+        unsigned long long *dg = (unsigned long long *)diag;
+        const dim3 grid((unsigned)blocks), block(kBlockThreads);
+#define LW_DEPOSIT_LAUNCH(T, G, CU)                                                                                   \
+    k_deposit<T, G, CU><<<grid, block, 0, s>>>(r, b, bd, charge, gr->x_det, w.rec, w.pflag, w.rmax2, rb2, (T *)E, dg, \
+                                               sh)
+        // culling is a separate instantiation: the full evaluation carries none of its code
+        hipEvent_t t_start = timing_begin(LW_KERNEL_DEPOSIT, s);
+        if (f64) {
+            if (geom == LW_GEOM_EXACT) {
+                if (cull) LW_DEPOSIT_LAUNCH(double, LW_GEOM_EXACT, true); else LW_DEPOSIT_LAUNCH(double, LW_GEOM_EXACT, false);
+            } else {
+                if (cull) LW_DEPOSIT_LAUNCH(double, LW_GEOM_FARFIELD, true); else LW_DEPOSIT_LAUNCH(double, LW_GEOM_FARFIELD, false);
+            }
         } else {
-            if (cull) LW_DEPOSIT_LAUNCH(double, LW_GEOM_FARFIELD, true); else LW_DEPOSIT_LAUNCH(double, LW_GEOM_FARFIELD, false);
+            if (geom == LW_GEOM_EXACT) {
+                if (cull) LW_DEPOSIT_LAUNCH(float, LW_GEOM_EXACT, true); else LW_DEPOSIT_LAUNCH(float, LW_GEOM_EXACT, false);
+            } else {
+                if (cull) LW_DEPOSIT_LAUNCH(float, LW_GEOM_FARFIELD, true); else LW_DEPOSIT_LAUNCH(float, LW_GEOM_FARFIELD, false);
+            }
         }
-    } else {
-        if (geom == LW_GEOM_EXACT) {
-            if (cull) LW_DEPOSIT_LAUNCH(float, LW_GEOM_EXACT, true); else LW_DEPOSIT_LAUNCH(float, LW_GEOM_EXACT, false);
-        } else {
-            if (cull) LW_DEPOSIT_LAUNCH(float, LW_GEOM_FARFIELD, true); else LW_DEPOSIT_LAUNCH(float, LW_GEOM_FARFIELD, false);
-        }
-    }
 #undef LW_DEPOSIT_LAUNCH
-    timing_end(LW_KERNEL_DEPOSIT, t_start, s);
-    return check_launch("lw_deposit_td");
+        timing_end(LW_KERNEL_DEPOSIT, t_start, s);
+        const lw_status st = check_launch("lw_deposit_td");
+        if (st != LW_OK) return st;
+    }
+    return LW_OK;
 }
 
 }  // namespace lw

@@ -13,7 +13,11 @@
 // Gather form, no atomics: a wavefront owns 62 consecutive samples of one particle (lanes
 // 1..62; lanes 0 and 63 are halo samples), loops over every pixel, takes the neighbours'
 // arrival times and fields by lane shuffles, evaluates the field only where an adjacent
-// interval holds grid points, and accumulates its samples' gradients in registers.
+// interval holds grid points, and accumulates its samples' gradients in registers.  Arrival
+// times are those of the deposit: the compensated base d of the sample plus the pixel terms,
+// with the exact geometry's path term in its third-order series where the particle's max |r|^2
+// over the whole trajectory is <= 1e-8 |x_m|^2 (the FP64 deposit's choice), else its square
+// root form.
 #include "lw_internal.h"
 
 #include <algorithm>
@@ -32,6 +36,30 @@ struct BwdShape {
     int fmask;
 };
 
+// max_i |r_i|^2 over the usable samples of each particle (the deposit pre-pass's rule and sum
+// order): one block per particle
+__global__ __launch_bounds__(256) void k_rmax2(const double *__restrict__ r, const double *__restrict__ beta,
+                                               const double *__restrict__ beta_dot, int64_t n_samples,
+                                               double *__restrict__ rmax2)
+{
+    __shared__ double s_max[4];
+    const int64_t k = blockIdx.x;
+    double mx = 0.0;
+    for (int64_t i = threadIdx.x; i < n_samples; i += blockDim.x) {
+        const size_t o = 3 * (size_t)(k * n_samples + i);
+        const double *ri = r + o;
+        if (sample_usable(ri, beta + o, beta_dot + o)) mx = fmax(mx, fma(ri[2], ri[2], fma(ri[1], ri[1], ri[0] * ri[0])));
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, s_max[w]);
+        rmax2[k] = m;
+    }
+}
+
 __device__ __forceinline__ int64_t grid_count_b(double tau, double n_obs)
 {
     return (int64_t)fmin(fmax(floor(tau) + 1.0, 0.0), n_obs);
@@ -42,10 +70,11 @@ __global__ __launch_bounds__(256) void k_deposit_bwd(const double *__restrict__ 
                                                      const double *__restrict__ beta_dot,
                                                      const double *__restrict__ charge,
                                                      const double *__restrict__ x_det, const double *__restrict__ dE,
-                                                     double *__restrict__ d_r, double *__restrict__ d_beta,
-                                                     double *__restrict__ d_beta_dot, BwdShape sh)
+                                                     const double *__restrict__ rbound2, double *__restrict__ d_r,
+                                                     double *__restrict__ d_beta, double *__restrict__ d_beta_dot,
+                                                     BwdShape sh)
 {
-    __shared__ PixGeo s_geo[kWavesPerBlock][64];
+    __shared__ PixC s_geo[kWavesPerBlock][64];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wv;
@@ -69,32 +98,35 @@ __global__ __launch_bounds__(256) void k_deposit_bwd(const double *__restrict__ 
     }
     const double rr = fma(rs[2], rs[2], fma(rs[1], rs[1], rs[0] * rs[0]));
     // sample i of the arrays is sample sample0 + i of the trajectory (spans of a longer one)
-    const double alpha = ((sh.t_start + (double)(sh.sample0 + i) * sh.dt) - sh.t0) / sh.dt_obs;
+    const double dbase = arrival_base(sh.t_start, sh.dt, (double)(sh.sample0 + i), sh.t0, sh.dt_obs, rs[2]);
+    const double rb2 = rbound2[k];
     const double q = charge ? charge[k] : -kQe;
     const double nob = (double)sh.n_obs;
     double gr[3] = {0, 0, 0}, gb[3] = {0, 0, 0}, ga[3] = {0, 0, 0};
-    PixGeo *geo = s_geo[wv];
+    PixC *geo = s_geo[wv];
 
     for (int64_t m0 = 0; m0 < sh.n_pix; m0 += 64) {
         {
             const int64_t mm = std::min<int64_t>(m0 + lane, sh.n_pix - 1);
-            geo[lane] = pix_geo(x_det, mm);
+            geo[lane] = pix_const(x_det, mm, sh.inv_cdt);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         const int cnt = (int)std::min<int64_t>(64, sh.n_pix - m0);
         for (int j = 0; j < cnt; ++j) {
             const int64_t m = m0 + j;
-            const PixGeo g = geo[j];
+            const PixC pcm = geo[j];
+            const PixGeo &g = pcm.g;
             const bool ok = usable && g.ok;
-            // the exact geometry's correction as its third-order series where |r|^2 <= 1e-8 |x|^2
-            // (exact to rounding, the FP64 deposit's form there), else with its square root
+            // the exact geometry's correction as its third-order series where the particle's
+            // |r|^2 <= 1e-8 |x|^2 over its whole trajectory (exact to rounding, the FP64
+            // deposit's form there), else with its square root
             double tau = 0.0;
             if (ok) {
-                if (GEOM == LW_GEOM_EXACT && rr * g.invD * g.invD <= kSeriesBoundBwd)
-                    tau = arrival_tau<GEOM, kTauSeries>(g, alpha, rs[0], rs[1], rs[2], rr, sh.inv_cdt);
+                if (GEOM == LW_GEOM_EXACT && rb2 * (g.invD * g.invD) <= kSeriesBoundBwd)
+                    tau = arrival_tau<GEOM, kTauSeries>(pcm, dbase, rs[0], rs[1], rs[2], rr, sh.inv_cdt);
                 else
-                    tau = arrival_tau<GEOM, kTauSqrt>(g, alpha, rs[0], rs[1], rs[2], rr, sh.inv_cdt);
+                    tau = arrival_tau<GEOM, kTauSqrt>(pcm, dbase, rs[0], rs[1], rs[2], rr, sh.inv_cdt);
             }
             const double tl = __shfl_up(tau, 1), tr = __shfl_down(tau, 1);
             const int okl = __shfl_up((int)ok, 1), okr = __shfl_down((int)ok, 1);
@@ -168,8 +200,14 @@ __global__ __launch_bounds__(256) void k_deposit_bwd(const double *__restrict__ 
 
 }  // namespace
 
+size_t deposit_bwd_ws_bytes(int64_t n_particles)
+{
+    return ((size_t)std::max<int64_t>(n_particles, 1) * sizeof(double) + 255) / 256 * 256;
+}
+
 lw_status launch_deposit_bwd(const lw_traj_t *t, const lw_grid_t *gr, int fmask, int geom, const double *dE,
-                             double *d_r, double *d_beta, double *d_beta_dot, hipStream_t s, int64_t sample0)
+                             double *d_r, double *d_beta, double *d_beta_dot, void *ws, size_t ws_bytes,
+                             hipStream_t s, int64_t sample0, const double *rbound2)
 {
     if (t->n_particles == 0 || gr->n_pix == 0 || t->n_samples < 2) return LW_OK;
     BwdShape sh;
@@ -187,13 +225,21 @@ lw_status launch_deposit_bwd(const lw_traj_t *t, const lw_grid_t *gr, int fmask,
     sh.fmask = fmask;
     const int64_t waves = sh.n_particles * sh.n_chunks;
     const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
-    if (blocks > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td_bwd: problem too large for one launch");
+    if (blocks > 0x7fffffff || sh.n_particles > 0x7fffffff)
+        return fail(LW_E_SHAPE, "lw_deposit_td_bwd: problem too large for one launch");
+    if (!rbound2) {  // max |r|^2 of each particle over the samples given (its whole trajectory)
+        if (!ws || ws_bytes < deposit_bwd_ws_bytes(t->n_particles))
+            return fail(LW_E_WORKSPACE, "lw_deposit_td_bwd: workspace of %zu bytes < %zu needed", ws_bytes,
+                        deposit_bwd_ws_bytes(t->n_particles));
+        k_rmax2<<<(unsigned)t->n_particles, 256, 0, s>>>(t->r, t->beta, t->beta_dot, t->n_samples, (double *)ws);
+        rbound2 = (const double *)ws;
+    }
     if (geom == LW_GEOM_EXACT)
         k_deposit_bwd<LW_GEOM_EXACT><<<(unsigned)blocks, 64 * kWavesPerBlock, 0, s>>>(
-            t->r, t->beta, t->beta_dot, t->charge, gr->x_det, dE, d_r, d_beta, d_beta_dot, sh);
+            t->r, t->beta, t->beta_dot, t->charge, gr->x_det, dE, rbound2, d_r, d_beta, d_beta_dot, sh);
     else
         k_deposit_bwd<LW_GEOM_FARFIELD><<<(unsigned)blocks, 64 * kWavesPerBlock, 0, s>>>(
-            t->r, t->beta, t->beta_dot, t->charge, gr->x_det, dE, d_r, d_beta, d_beta_dot, sh);
+            t->r, t->beta, t->beta_dot, t->charge, gr->x_det, dE, rbound2, d_r, d_beta, d_beta_dot, sh);
     return check_launch("lw_deposit_td_bwd");
 }
 

@@ -67,10 +67,11 @@ __device__ __forceinline__ void stage_sample(const double *__restrict__ r, const
     double kap;
     lw_field<T, GEOM>(g, xm, r[s], r[s + 1], r[s + 2], beta[s], beta[s + 1], beta[s + 2], beta_dot[s], beta_dot[s + 1],
                       beta_dot[s + 2], q, sh.fmask, ex, ey, ez, &kap);
-    // arrival time relative to t0 (s), formed in units of u = cdt / c
+    // arrival time relative to t0 (s), formed in units of u = cdt / c (its compensated base d and
+    // the pixel terms, as in the deposit)
     const double u = sh.cdt / kC;
-    const double alpha = ((sh.t_start + (double)i * sh.dt) - sh.t0) / u;
-    ta = arrival_tau<GEOM, kTauSqrt>(g, alpha, r[s], r[s + 1], r[s + 2], 0.0, sh.inv_cdt) * u;
+    const double d = arrival_base(sh.t_start, sh.dt, (double)i, sh.t0, u, r[s + 2]);
+    ta = arrival_tau<GEOM, kTauSqrt>(pix_const_of(g, sh.inv_cdt), d, r[s], r[s + 1], r[s + 2], 0.0, sh.inv_cdt) * u;
     const T tk = (T)kap;
     ex *= tk;
     ey *= tk;
@@ -359,7 +360,7 @@ __global__ __launch_bounds__(256) void k_direct_fd_bwd(const double *__restrict_
     const bool usable = in && sample_usable(rs, bs, as);
     const double q = charge ? charge[k] : -kQe;
     const double u = sh.cdt / kC;
-    const double alpha = ((sh.t_start + (double)i * sh.dt) - sh.t0) / u;
+    const double d = arrival_base(sh.t_start, sh.dt, (double)i, sh.t0, u, rs[2]);
     double gr[3] = {0, 0, 0}, gb[3] = {0, 0, 0}, ga[3] = {0, 0, 0};
     for (int64_t m = 0; m < sh.n_pix; ++m) {
         const PixGeo g = pix_geo(x_det, m);
@@ -369,7 +370,7 @@ __global__ __launch_bounds__(256) void k_direct_fd_bwd(const double *__restrict_
         if (ok) {
             lw_field<double, GEOM>(g, xm, rs[0], rs[1], rs[2], bs[0], bs[1], bs[2], as[0], as[1], as[2], q, sh.fmask,
                                    E[0], E[1], E[2], &kap);
-            ta = arrival_tau<GEOM, kTauSqrt>(g, alpha, rs[0], rs[1], rs[2], 0.0, sh.inv_cdt) * u;
+            ta = arrival_tau<GEOM, kTauSqrt>(pix_const_of(g, sh.inv_cdt), d, rs[0], rs[1], rs[2], 0.0, sh.inv_cdt) * u;
             for (int c = 0; c < 3; ++c) A[c] = E[c] * kap;
             ok = isfinite(ta) && isfinite(A[0]) && isfinite(A[1]) && isfinite(A[2]);
         }

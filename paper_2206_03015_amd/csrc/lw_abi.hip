@@ -207,9 +207,9 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec)
 {
     switch (which) {
     case LW_WS_DEPOSIT:
-        return deposit_ws_bytes(n_a, n_b);
+        return deposit_ws_bytes(n_a, n_b, prec);
     case LW_WS_DEPOSIT_BWD:
-        return 0;
+        return deposit_bwd_ws_bytes(n_a);
     case LW_WS_FFT:
     case LW_WS_FFT_BWD:
         return fft_ws_bytes(n_a, n_b, prec);
@@ -217,9 +217,10 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec)
     case LW_WS_DIRECT_FD_BWD:
         return direct_fd_ws_bytes(n_a, n_b);
     case LW_WS_DEPOSIT_BORIS:
-        return n_b >= 1 ? boris_plan_ws_bytes(boris_plan_default(n_a, n_b)) : 0;
+        return n_b >= 1 ? boris_plan_ws_bytes(boris_plan_default(n_a, n_b, prec), prec) : 0;
     case LW_WS_DEPOSIT_BWD_BORIS:
-        return n_b >= 1 ? boris_plan_ws_bytes(boris_plan_default(n_a, n_b, true), true) : 0;
+        return n_b >= 1 ? boris_plan_ws_bytes(boris_plan_default(n_a, n_b, LW_PREC_FP64, true), LW_PREC_FP64, true)
+                        : 0;
     default:
         return 0;
     }
@@ -248,14 +249,16 @@ lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, 
     if (ws && !aligned(ws, 256)) return fail(LW_E_ALIGN, "%s: workspace must be 256-byte aligned", fn);
     if (boris) {
         const bool work = traj->n_particles > 0 && grid->n_pix > 0;
-        const BorisPlan plan = boris_plan_fit(traj->n_particles, traj->n_samples, traj->span, ws_bytes);
+        const BorisPlan plan = boris_plan_fit(traj->n_particles, traj->n_samples, traj->span, ws_bytes, prec);
         const int64_t lmin = std::min<int64_t>(traj->n_samples, 2);
         if (work && (!ws || plan.batch < 1 || plan.span < lmin))
             return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes holds no span (one particle needs %zu)", fn,
-                        ws_bytes, boris_plan_ws_bytes(BorisPlan{1, traj->span > 0 ? traj->span : lmin}));
+                        ws_bytes, boris_plan_ws_bytes(BorisPlan{1, traj->span > 0 ? traj->span : lmin}, prec));
         return launch_deposit_boris(traj, grid, prec, field_mask, gc, acc, E, diag, ws, ws_bytes, stream);
     }
-    const size_t need = deposit_ws_bytes(traj->n_particles, traj->n_samples);
+    // any workspace that holds one particle's records is accepted (the particles are then taken
+    // in chunks); lw_workspace_bytes gives the size that takes them all at once
+    const size_t need = deposit_ws_bytes(1, traj->n_samples, prec);
     if (traj->n_particles > 0 && grid->n_pix > 0 && (!ws || ws_bytes < need))
         return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes < %zu needed", fn, ws_bytes, need);
     return launch_deposit(traj, grid, prec, field_mask, gc, acc, E, diag, ws, ws_bytes, stream);
@@ -360,8 +363,6 @@ lw_status lw_deposit_td_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int pr
                             const void *dE, double *d_r, double *d_beta, double *d_beta_dot, void *ws,
                             size_t ws_bytes, hipStream_t stream)
 {
-    (void)ws;
-    (void)ws_bytes;
     const char *fn = "lw_deposit_td_bwd";
     lw_status st = check_traj_samples(traj, fn);
     if (st != LW_OK) return st;
@@ -374,9 +375,13 @@ lw_status lw_deposit_td_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int pr
     if (traj->n_particles > 0 && grid->n_pix > 0 && (!dE || !d_r || !d_beta || !d_beta_dot))
         return fail(LW_E_ARG, "%s: dE, d_r, d_beta, d_beta_dot must be non-NULL", fn);
     if ((dE && !aligned(dE, 16)) || (d_r && !aligned(d_r, 8)) || (d_beta && !aligned(d_beta, 8)) ||
-        (d_beta_dot && !aligned(d_beta_dot, 8)))
+        (d_beta_dot && !aligned(d_beta_dot, 8)) || (ws && !aligned(ws, 256)))
         return fail(LW_E_ALIGN, "%s: misaligned pointer", fn);
-    return launch_deposit_bwd(traj, grid, field_mask, geom, (const double *)dE, d_r, d_beta, d_beta_dot, stream);
+    const size_t need = deposit_bwd_ws_bytes(traj->n_particles);
+    if (traj->n_particles > 0 && grid->n_pix > 0 && traj->n_samples >= 2 && (!ws || ws_bytes < need))
+        return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes < %zu needed", fn, ws_bytes, need);
+    return launch_deposit_bwd(traj, grid, field_mask, geom, (const double *)dE, d_r, d_beta, d_beta_dot, ws, ws_bytes,
+                              stream);
 }
 
 lw_status lw_deposit_td_bwd_boris(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom,
@@ -398,10 +403,12 @@ lw_status lw_deposit_td_bwd_boris(const lw_traj_t *traj, const lw_grid_t *grid, 
         (ws && !aligned(ws, 256)))
         return fail(LW_E_ALIGN, "%s: misaligned pointer", fn);
     if (work && grid->n_pix > 0 && traj->n_samples >= 2) {
-        const BorisPlan plan = boris_plan_fit(traj->n_particles, traj->n_samples, traj->span, ws_bytes, true);
+        const BorisPlan plan =
+            boris_plan_fit(traj->n_particles, traj->n_samples, traj->span, ws_bytes, LW_PREC_FP64, true);
         if (!ws || plan.batch < 1 || plan.span < 2)
             return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes holds no span (one particle needs %zu)", fn,
-                        ws_bytes, boris_plan_ws_bytes(BorisPlan{1, traj->span > 0 ? traj->span : 2}, true));
+                        ws_bytes,
+                        boris_plan_ws_bytes(BorisPlan{1, traj->span > 0 ? traj->span : 2}, LW_PREC_FP64, true));
     }
     return launch_deposit_bwd_boris(traj, grid, field_mask, geom, (const double *)dE, grad_init, grad_a0, ws, ws_bytes,
                                     stream);

@@ -69,13 +69,73 @@ __device__ __forceinline__ PixGeo pix_geo(const double *x_det, int64_t m)
     return g;
 }
 
-// Arrival time in grid units of sample (r, |r|^2 = rr) at pixel g:
-//   far field (Eq. far_adv):            tau = alpha - s/(c dt_obs),     s = n.r
-//   exact (Eq. advanced_condition):     tau = alpha - s/(c dt_obs) + |r_perp|^2 / (c dt_obs (|x - r| + |x| - s))
-// with alpha = (t_i - t0)/dt_obs and r_perp = r - s n.  The exact correction is the identity
-// |x - r| - |x| = -s + |r_perp|^2/(|x - r| + |x| - s), free of cancellation.
-// FORM (exact geometry only):
-//   kTauSqrt    the correction with its square root and divide;
+// ---------------------------------------------------------------------------------------------
+// Arrival time in grid units, tau = (t_i + (|x_m - r_i| - |x_m|)/c - t0)/dt_obs (exact geometry,
+// Eq. advanced_condition) or (t_i - n.r_i/c - t0)/dt_obs (far field, Eq. far_adv), split as
+//   tau = d + b (+ corr),   d = (t_i - t0 - z_i/c)/dt_obs,   b = C ((1 - n_z) z - n_x x - n_y y),
+// with C = 1/(c dt_obs) and corr = C |r_perp|^2/(|x - r| + |x| - s), s = n.r, r_perp = r - s n (the
+// identity |x - r| - |x| = -s + |r_perp|^2/(|x - r| + |x| - s), free of cancellation).  d holds
+// the two terms of size t_i/dt_obs (up to ~1e8 grid units) that cancel; it is formed once per
+// sample with every step in double-double arithmetic and rounded once, so its error is that of
+// one rounding of the (window-sized) result.  b is of the size of the transverse offsets and
+// (1 - n_z) is formed without cancellation.
+
+// s + e = a + b exactly (Knuth's two-sum)
+__host__ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
+{
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// d of sample idx (t_idx = t_start + idx dt) at height z
+__host__ __device__ __forceinline__ double arrival_base(double t_start, double dt, double idx, double t0, double dt_obs,
+                                                        double z)
+{
+    const double p = idx * dt, pe = fma(idx, dt, -p);  // idx dt = p + pe
+    double s, se, a, ae, n, ne;
+    two_sum(t_start, p, s, se);  // t_idx = s + se + pe
+    two_sum(s, -t0, a, ae);      // t_idx - t0 = a + alo
+    const double alo = ae + (se + pe);
+    const double q = z / kC;
+    const double qr = fma(-q, kC, z) / kC;  // z/c = q + qr (the division's residual is exact)
+    two_sum(a, -q, n, ne);                  // t_idx - t0 - z/c = n + nlo
+    const double nlo = ne + (alo - qr);
+    const double h = n / dt_obs;
+    const double rem = fma(-h, dt_obs, n);
+    return h + (rem + nlo) / dt_obs;
+}
+
+// Constants of one pixel: geometry and the coefficients of b.
+struct PixC {
+    PixGeo g;
+    double o, px, py;  // C (1 - n_z), -C n_x, -C n_y
+};
+
+__device__ __forceinline__ PixC pix_const_of(const PixGeo &g, double C)
+{
+    PixC p;
+    p.g = g;
+    const double nx = p.g.nx, ny = p.g.ny, nz = p.g.nz;
+    const double omz = nz > 0.0 ? (nx * nx + ny * ny) / (1.0 + nz) : 1.0 - nz;
+    p.o = C * omz;
+    p.px = -C * nx;
+    p.py = -C * ny;
+    return p;
+}
+
+__device__ __forceinline__ PixC pix_const(const double *x_det, int64_t m, double C)
+{
+    return pix_const_of(pix_geo(x_det, m), C);
+}
+
+__device__ __forceinline__ double pix_b(const PixC &p, double x, double y, double z)
+{
+    return fma(p.py, y, fma(p.px, x, p.o * z));
+}
+
+// The path correction corr (exact geometry) in one of three forms:
+//   kTauSqrt    with its square root and divide;
 //   kTauSeries  (valid when |r| <= 1e-4 |x|, checked by the caller) with x = s/|x| and
 //               q = |r_perp|^2/(|x| - s)^2:  1/(|x| - s) = (1 + x + x^2 + x^3 + O(x^4))/|x|,
 //               1/(|x - r| + |x| - s) = (1/(|x| - s)) (1/2 - q/8 + O(q^2)), |r_perp|^2 = |r|^2 - s^2;
@@ -85,15 +145,16 @@ __device__ __forceinline__ PixGeo pix_geo(const double *x_det, int64_t m)
 // Written with explicit fma so that every evaluation of the same (pixel, sample) gives the same bits.
 constexpr int kTauSqrt = 0, kTauSeries = 1, kTauShort = 2;
 template <int GEOM, int FORM>
-__device__ __forceinline__ double arrival_tau(const PixGeo &g, double alpha, double rx, double ry, double rz, double rr,
-                                              double inv_cdt)
+__device__ __forceinline__ double arrival_tau(const PixC &p, double d, double rx, double ry, double rz, double rr,
+                                              double C)
 {
-    const double s = fma(g.nz, rz, fma(g.ny, ry, g.nx * rx));
-    double tau = fma(-s, inv_cdt, alpha);
+    double tau = d + pix_b(p, rx, ry, rz);
     if (GEOM == LW_GEOM_EXACT) {
+        const PixGeo &g = p.g;
+        const double s = fma(g.nz, rz, fma(g.ny, ry, g.nx * rx));
         if (FORM == kTauShort) {
             const double p2 = fma(-s, s, rr);
-            const double k1 = 0.5 * inv_cdt * g.invD;  // loop invariants
+            const double k1 = 0.5 * C * g.invD;  // loop invariants
             const double k2 = k1 * g.invD;
             tau = fma(p2, fma(s, k2, k1), tau);
         } else if (FORM == kTauSeries) {
@@ -103,16 +164,57 @@ __device__ __forceinline__ double arrival_tau(const PixGeo &g, double alpha, dou
             const double y = g.invD * h;
             const double py = p2 * y;
             const double q = py * y;
-            tau = fma(py, fma(q, -0.125 * inv_cdt, 0.5 * inv_cdt), tau);
+            tau = fma(py, fma(q, -0.125 * C, 0.5 * C), tau);
         } else {
             const double px = fma(-s, g.nx, rx), py = fma(-s, g.ny, ry), pz = fma(-s, g.nz, rz);
             const double p2 = fma(pz, pz, fma(py, py, px * px));
             const double ds = g.D - s;
             const double R = sqrt(fma(ds, ds, p2));
-            tau += p2 * inv_cdt / (R + ds);
+            tau += p2 * C / (R + ds);
         }
     }
     return tau;
+}
+
+// The series forms as polynomials in b for pixels at one distance D (the scan's records):
+// with s = z - b/C, |r_perp|^2 = (rho + 2 z' b - b^2)/C^2 (rho = C^2 (x^2 + y^2), z' = C z),
+// x = s/D = u - e b (u = z/D, e = 1/(C D)) and K = e/2,
+//   kTauShort:  corr = K P (1 + x)                                    (degree 3 in b)
+//   kTauSeries: corr = K P [(1 + x + x^2 + x^3) - (P e^2/4)(1 + 3 x)]  (degree 5 in b)
+// with P = rho + 2 z' b - b^2 (the same truncations as arrival_tau's series forms), and
+// tau(b) = d + b + corr(b) = sum_j c[j] b^j.  The leading coefficient does not depend on the
+// sample (K e, resp. 7 K e^3/4).
+template <int DEG>
+__host__ __device__ __forceinline__ void tau_poly(double d, double x, double y, double z, double C, double D,
+                                                  double *c)
+{
+    const double zp = C * z, cx = C * x, cy = C * y;
+    const double rho = fma(cy, cy, cx * cx);
+    const double e = 1.0 / (C * D), K = 0.5 * e, u = z / D;
+    const double P[3] = {rho, 2.0 * zp, -1.0};
+    double T[4] = {0.0, 0.0, 0.0, 0.0};  // the bracket, a polynomial in b
+    if (DEG == 3) {
+        T[0] = 1.0 + u;
+        T[1] = -e;
+    } else {
+        // S(x) = 1 + x + x^2 + x^3 with x = u - e b
+        const double u2 = u * u, e2 = e * e;
+        T[0] = 1.0 + u + u2 + u2 * u;
+        T[1] = -e * (1.0 + 2.0 * u + 3.0 * u2);
+        T[2] = e2 * (1.0 + 3.0 * u);
+        T[3] = -e2 * e;
+        // minus (e^2/4) P (1 + 3u - 3e b)
+        const double f = 0.25 * e2, a0 = 1.0 + 3.0 * u, a1 = -3.0 * e;
+        T[0] -= f * (P[0] * a0);
+        T[1] -= f * (P[0] * a1 + P[1] * a0);
+        T[2] -= f * (P[1] * a1 + P[2] * a0);
+        T[3] -= f * (P[2] * a1);
+    }
+    for (int j = 0; j <= DEG; ++j) c[j] = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j + i <= DEG && j < 4; ++j) c[i + j] += K * (P[i] * T[j]);
+    c[0] += d;
+    c[1] += 1.0;
 }
 
 // Lienard-Wiechert field of one sample at one pixel.  Geometry (n, R, n - beta, kappa) in
@@ -271,11 +373,15 @@ __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAd
 
 // host-side launch helpers (defined in the kernel files)
 // sample0: index of the first sample of traj within a longer trajectory (its arrival times use
-// t_start + (sample0 + i) dt); 0 for whole trajectories
+// t_start + (sample0 + i) dt); 0 for whole trajectories.  rbound2: per particle, max |r|^2 over
+// the whole trajectory (nullptr: the max over the samples given), which decides the series forms
+// of the arrival time per particle and pixel.
 lw_status launch_deposit(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom,
                          bool accumulate, void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s,
-                         int64_t sample0 = 0);
-size_t deposit_ws_bytes(int64_t n_particles, int64_t n_samples);
+                         int64_t sample0 = 0, const double *rbound2 = nullptr);
+// workspace of a deposit launch that holds the records of all its particles (a smaller one makes
+// it process the particles in chunks)
+size_t deposit_ws_bytes(int64_t n_particles, int64_t n_samples, int prec);
 lw_status launch_fft(const void *E, int64_t n_pix, int64_t n_obs, double dt_obs, int prec, void *S, void *ws,
                      size_t ws_bytes, hipStream_t s);
 size_t fft_ws_bytes(int64_t n_pix, int64_t n_obs, int prec);
@@ -288,6 +394,8 @@ lw_status launch_direct_fd_bwd(const lw_traj_t *traj, const lw_grid_t *grid, con
                                double *d_beta_dot, void *ws, size_t ws_bytes, hipStream_t s);
 size_t direct_fd_ws_bytes(int64_t n_pix, int64_t n_omega);
 lw_status launch_boris(const lw_traj_t *traj, double *r, double *beta, double *beta_dot, hipStream_t s);
+// max |r|^2 over every sample of each trajectory of traj (LW_TRAJ_BORIS), [n_particles]
+lw_status launch_boris_rmax2(const lw_traj_t *traj, double *rmax2, hipStream_t s);
 // samples s0 .. s0 + n_span - 1 of every particle of traj (LW_TRAJ_BORIS), starting from init
 // (s0 = 0) or from the pusher state [n_particles][9] left by the span that ended at sample s0
 lw_status launch_boris_span(const lw_traj_t *traj, int64_t s0, int64_t n_span, double *state, double *r,
@@ -300,17 +408,21 @@ lw_status launch_boris_bwd(const lw_traj_t *traj, const double *g_r, const doubl
 lw_status launch_boris_bwd_span(const lw_traj_t *traj, int64_t s0, int64_t n_span, double *tstate,
                                 const double *g_r, const double *g_beta, const double *g_beta_dot, double *grad_init,
                                 double *grad_a0, hipStream_t s);
+// adjoint of the deposit; rbound2 as for launch_deposit (nullptr: computed from the samples into
+// ws, which then needs deposit_bwd_ws_bytes(n_particles) bytes)
 lw_status launch_deposit_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int field_mask, int geom, const double *dE,
-                             double *d_r, double *d_beta, double *d_beta_dot, hipStream_t s, int64_t sample0 = 0);
+                             double *d_r, double *d_beta, double *d_beta_dot, void *ws, size_t ws_bytes,
+                             hipStream_t s, int64_t sample0 = 0, const double *rbound2 = nullptr);
+size_t deposit_bwd_ws_bytes(int64_t n_particles);
 // trajectories recomputed from LW_TRAJ_BORIS initial conditions (boris_stream.hip): the deposit
 // and its adjoint push batches of particles over spans of samples.
 struct BorisPlan {
     int64_t batch, span;  // particles per batch, samples per span (spans share their boundary sample)
 };
 // bwd: the adjoint's plan (sample arrays and their gradients, tangent states)
-BorisPlan boris_plan_default(int64_t n_p, int64_t ns, bool bwd = false);
-BorisPlan boris_plan_fit(int64_t n_p, int64_t ns, int64_t span_req, size_t ws_bytes, bool bwd = false);
-size_t boris_plan_ws_bytes(const BorisPlan &p, bool bwd = false);
+BorisPlan boris_plan_default(int64_t n_p, int64_t ns, int prec, bool bwd = false);
+BorisPlan boris_plan_fit(int64_t n_p, int64_t ns, int64_t span_req, size_t ws_bytes, int prec, bool bwd = false);
+size_t boris_plan_ws_bytes(const BorisPlan &p, int prec, bool bwd = false);
 lw_status launch_deposit_boris(const lw_traj_t *t, const lw_grid_t *gr, int prec, int fmask, int geom,
                                bool accumulate, void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s);
 lw_status launch_deposit_bwd_boris(const lw_traj_t *t, const lw_grid_t *gr, int fmask, int geom, const double *dE,

@@ -302,8 +302,9 @@ def deposit_td_bwd(r, beta, beta_dot, t_start, dt, x_det, t0, dt_obs, n_obs, dE,
     d_r, d_b, d_bd = out
     for t, nm in ((d_r, "d_r"), (d_b, "d_beta"), (d_bd, "d_beta_dot")):
         _need(t, torch.float64, tuple(r.shape), nm)
+    ws = _workspace(workspace_bytes(WS_DEPOSIT_BWD, tr.n_particles, tr.n_samples, "fp64"), r.device)
     _check(lib.lw_deposit_td_bwd(ctypes.byref(tr), ctypes.byref(gr), PREC["fp64"], int(field_mask), GEOM[geom],
-                                 _ptr(dE), _ptr(d_r), _ptr(d_b), _ptr(d_bd), None, 0, _stream()))
+                                 _ptr(dE), _ptr(d_r), _ptr(d_b), _ptr(d_bd), _ptr(ws), ws.numel(), _stream()))
     return d_r, d_b, d_bd
 
 
