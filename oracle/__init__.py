@@ -8,6 +8,10 @@ imports this package.
 
 Functions and what pins each one (tests named in brackets):
 
+* ``arrival_tau`` -- arrival times in grid units, formed in extended precision (the
+  large terms t_i/dt_obs and n.r/(c dt_obs) cancel).  Pinned by: 50-digit evaluations of
+  the definition on the same double inputs at the sizes of the largest workloads
+  (|error| <= 1e-11 grid units) [test_oracle_eval.py].
 * ``eval_one`` / ``eval_samples`` -- per-sample arrival time and LW field
   (Eqs. lw_fields_retarded, advanced_condition, far_efield, far_adv).
   Pinned by: Coulomb field of a charge at rest; the closed-form field of a
@@ -93,6 +97,8 @@ def lib():
         L.orc_direct_fd.argtypes = [i64, i64, d, d, dp, dp, dp, ctypes.c_void_p, i64, dp, d, dp, i64,
                                     ctypes.c_int, ctypes.c_int, dp]
         L.orc_boris.argtypes = [i64, i64, d, d, dp, d, d, d, d, dp, dp, dp]
+        L.orc_arrival_tau.argtypes = [i64, dp, dp, ctypes.c_void_p, d, d, d, d, ctypes.c_int, dp]
+        L.orc_arrival_tau.restype = None
         L.orc_laser_fields.argtypes = [i64, dp, dp, d, d, d, d, dp, dp]
         L.orc_laser_fields.restype = None
         _lib = L
@@ -118,6 +124,19 @@ def eval_one(x, r, beta, beta_dot, q=-Q_E, field_mask=FIELD_ACCEL, geom=GEOM_EXA
     kap = np.zeros(1)
     lib().orc_eval(_p(x), _p(r), _p(b), _p(bd), float(q), int(field_mask), int(geom), _p(tt), _p(E), _p(kap))
     return tt[0], E, kap[0]
+
+
+def arrival_tau(x, r, i, t_start, dt, t0, dt_obs, geom=GEOM_EXACT):
+    """Arrival times (grid units) of single samples: sample i[j] emitted from r[j] seen at x[j]
+    (the extended-precision evaluation that deposit_td, eval_samples and direct_fd use)."""
+    x = _f64(x).reshape(-1, 3)
+    r = _f64(r).reshape(-1, 3)
+    i = np.ascontiguousarray(np.asarray(i, dtype=np.int64).reshape(-1))
+    n = x.shape[0]
+    tau = np.empty(n)
+    lib().orc_arrival_tau(n, _p(x), _p(r), i.ctypes.data, float(t_start), float(dt), float(t0), float(dt_obs),
+                          int(geom), _p(tau))
+    return tau
 
 
 def _traj_args(r, beta, beta_dot, charge):

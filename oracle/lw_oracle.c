@@ -123,6 +123,54 @@ static void eval_one(const double *x, const double *r, const double *b, const do
     if (kappa_out) *kappa_out = kappa;
 }
 
+/*
+ * Arrival time of sample i (emitted at t_i = t_start + i*dt from r) at observer x, in grid units
+ * of the observer grid that starts at |x|/c + t0:
+ *     exact (Eq. advanced_condition):  tau = (t_i + (|x - r| - |x|)/c - t0) / dt_obs
+ *     far field (Eq. far_adv):         tau = (t_i - n_m.r/c - t0) / dt_obs
+ * The definition is a real-number relation between the double inputs.  Its two large terms,
+ * t_i/dt_obs and n_m.r/(c dt_obs), reach ~1e8 grid units at the largest workloads and cancel to
+ * the size of the window, so one double rounding of them moves tau by ~1e-8 grid units, far
+ * more than the 1e-10 spectral agreement asked of double-precision results.  The oracle
+ * therefore forms this one expression in long double (x87, 64-bit significand: ~1e-11 grid
+ * units), with |x - r| - |x| through the cancellation-free identity of eval_one.
+ */
+/* the arrival time minus |x|/c + t0, in seconds */
+static long double arrival_time_ld(const double *x, const double *r, double t_start, double dt, int64_t i, double t0,
+                                   int geom)
+{
+    const long double c = O_C;
+    long double X[3] = {x[0], x[1], x[2]}, Rv[3] = {r[0], r[1], r[2]};
+    long double D = sqrtl(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+    long double n[3] = {X[0] / D, X[1] / D, X[2] / D};
+    long double s = n[0] * Rv[0] + n[1] * Rv[1] + n[2] * Rv[2];
+    long double shift;
+    if (geom == O_GEOM_FARFIELD) {
+        shift = -s / c;
+    } else {
+        long double rp[3] = {Rv[0] - s * n[0], Rv[1] - s * n[1], Rv[2] - s * n[2]};
+        long double d[3] = {X[0] - Rv[0], X[1] - Rv[1], X[2] - Rv[2]};
+        long double R = sqrtl(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        shift = (-s + (rp[0] * rp[0] + rp[1] * rp[1] + rp[2] * rp[2]) / (R + D - s)) / c;
+    }
+    long double ti = (long double)t_start + (long double)i * (long double)dt;
+    return ti + shift - (long double)t0;
+}
+
+static double arrival_tau_ld(const double *x, const double *r, double t_start, double dt, int64_t i, double t0,
+                             double dt_obs, int geom)
+{
+    return (double)(arrival_time_ld(x, r, t_start, dt, i, t0, geom) / (long double)dt_obs);
+}
+
+/* Exported arrival time of single samples (used by the precision pin): tau[j] for x[j], r[j], i[j]. */
+void orc_arrival_tau(int64_t n, const double *x, const double *r, const int64_t *i, double t_start, double dt,
+                     double t0, double dt_obs, int geom, double *tau)
+{
+    for (int64_t j = 0; j < n; ++j)
+        tau[j] = arrival_tau_ld(x + 3 * j, r + 3 * j, t_start, dt, i[j], t0, dt_obs, geom);
+}
+
 /* Exported single-sample evaluation (used by the closed-form pins). */
 void orc_eval(const double *x, const double *r, const double *b, const double *bd, double q, int fmask, int geom,
               double *tt, double *E, double *kappa)
@@ -232,8 +280,7 @@ int orc_deposit_td(int64_t n_p, int64_t n_samples, double t_start, double dt, co
                     if (!ok[i]) continue;
                     double tt;
                     eval_one(x, r + s, beta + s, beta_dot + s, q, fmask, geom, &tt, Ea + 3 * i, NULL);
-                    double ti = t_start + (double)i * dt;
-                    tau[i] = ((ti + tt) - t0) / dt_obs;
+                    tau[i] = arrival_tau_ld(x, r + s, t_start, dt, i, t0, dt_obs, geom);
                     ok[i] = (unsigned char)(isfinite(tau[i]) && isfinite(Ea[3 * i]) && isfinite(Ea[3 * i + 1]) &&
                                             isfinite(Ea[3 * i + 2]));
                 }
@@ -283,7 +330,7 @@ int orc_eval_samples(int64_t n_p, int64_t n_samples, double t_start, double dt, 
                 double tt, kap;
                 eval_one(x_det + 3 * m, r + 3 * s, beta + 3 * s, beta_dot + 3 * s, q, fmask, geom, &tt, E + 3 * o,
                          &kap);
-                tau[o] = ((t_start + (double)i * dt + tt) - t0) / dt_obs;
+                tau[o] = arrival_tau_ld(x_det + 3 * m, r + 3 * s, t_start, dt, i, t0, dt_obs, geom);
                 if (kappa) kappa[o] = kap;
             }
         }
@@ -325,9 +372,13 @@ int orc_direct_fd(int64_t n_p, int64_t n_samples, double t_start, double dt, con
                 if (!sample_ok(r + 3 * s, beta + 3 * s, beta_dot + 3 * s)) continue;
                 double tt, Ev[3], kap;
                 eval_one(x_det + 3 * m, r + 3 * s, beta + 3 * s, beta_dot + 3 * s, q, fmask, geom, &tt, Ev, &kap);
-                double ta = (t_start + (double)i * dt + tt) - t0;
+                /* arrival time relative to t0 (s), in the extended precision of arrival_tau_ld, and
+                   the phase reduced to one revolution before its cosine and sine */
+                long double ta = arrival_time_ld(x_det + 3 * m, r + 3 * s, t_start, dt, i, t0, geom);
                 for (int64_t w = 0; w < n_omega; ++w) {
-                    double ph = omega[w] * ta;
+                    long double cyc = (long double)omega[w] * ta / (2.0L * 3.14159265358979323846264338327950288L);
+                    cyc -= floorl(cyc);
+                    double ph = (double)(cyc * 2.0L * 3.14159265358979323846264338327950288L);
                     double cs = cos(ph), sn = sin(ph);
                     for (int c = 0; c < 3; ++c) {
                         acc[6 * w + 2 * c] += Ev[c] * kap * cs;

@@ -178,3 +178,52 @@ def test_exact_tends_to_far_field():
     for a, b in zip(errs, errs[1:]):
         assert 7.0 < a / b < 13.0
     assert rng is not None
+
+
+@pytest.mark.parametrize("geom", [EXACT, FAR])
+def test_arrival_time_in_grid_units_against_50_digits(geom):
+    """The arrival time in grid units, tau = (t_i + shift - t0)/dt_obs, at the sizes of the
+    largest workloads (gamma 200: t_i up to 1e-13 s, |r| up to 60 um, dt_obs = 1.9 zs, so
+    t_i/dt_obs and n.r/(c dt_obs) reach ~5e7 grid units and cancel to the window's size), with
+    each sample's window origin t0 placed so that tau lies inside a 2^18-point window, against
+    the definition in 50-digit arithmetic on the same double inputs.  A double evaluation loses
+    ~1e-8 grid units here; the oracle's extended-precision sum stays within 5e-11: a few
+    roundings of the 64-bit significand on terms of ~5e7 grid units (~2e-12 each) plus the final
+    double rounding of tau < 2^18 (up to 2.9e-11)."""
+    mp.mp.dps = 50
+    rng = np.random.default_rng(11)
+    n = 200
+    t_start, dt, dt_obs = -8.33e-14, 8.33e-18, 1.94e-21
+    i = rng.integers(0, 20001, size=n)
+    beta = 1.0 - 1.25e-5
+    th = rng.uniform(-0.014, 0.014, size=(n, 2))
+    x = np.stack([np.sin(th[:, 0]), np.cos(th[:, 0]) * np.sin(th[:, 1]), np.cos(th[:, 0]) * np.cos(th[:, 1])], -1)
+    t_i = t_start + i * dt
+    z0 = rng.normal(size=n) * 5e-6
+    r = np.stack([rng.normal(size=n) * 6e-6, rng.normal(size=n) * 6e-6, z0 + beta * C * t_i], -1)
+    worst, worst_double, big = 0.0, 0.0, 0.0
+    for j in range(n):
+        X = [mp.mpf(v) for v in x[j]]
+        Rv = [mp.mpf(v) for v in r[j]]
+        D = mp.sqrt(sum(v * v for v in X))
+        if geom == EXACT:
+            shift = (mp.sqrt(sum((X[c] - Rv[c]) ** 2 for c in range(3))) - D) / C
+        else:
+            shift = -sum(X[c] / D * Rv[c] for c in range(3)) / C
+        ti = mp.mpf(t_start) + int(i[j]) * mp.mpf(dt)
+        # a window origin that puts this arrival at a random place of a 2^18-point window
+        t0 = float(ti + shift) - rng.uniform(0.0, 2.0 ** 18) * dt_obs
+        tau = oracle.arrival_tau(x[j], r[j], [i[j]], t_start, dt, t0, dt_obs, geom)[0]
+        ref = (ti + shift - mp.mpf(t0)) / mp.mpf(dt_obs)
+        assert 0.0 <= float(ref) < 2.0 ** 18 + 1
+        worst = max(worst, abs(float(tau - ref)))
+        big = max(big, abs(float(ti / mp.mpf(dt_obs))))
+        # the same expression in plain double arithmetic (the oracle's shift, summed in double)
+        tt, _, _ = oracle.eval_one(x[j], r[j], np.zeros(3), np.zeros(3), Q, ACC, geom)
+        tau_double = ((t_start + float(i[j]) * dt + tt) - t0) / dt_obs
+        worst_double = max(worst_double, abs(float(tau_double - ref)))
+    print(f"max |tau - tau_50digits| = {worst:.2e} grid units, plain double {worst_double:.2e} "
+          f"(largest cancelling term {big:.1e})")
+    assert big > 3e7  # the comparison is meaningful: the cancelling terms are this large
+    assert worst <= 5e-11
+    assert worst_double > 4 * 5e-11  # a double evaluation would not pass
