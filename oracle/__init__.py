@@ -52,6 +52,8 @@ from .trajectory import planewave_trajectory  # noqa: F401
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lw_oracle.c")
 _LIB = os.path.join(_HERE, "liblw_oracle.so")
+# LW_ORACLE_LIBRARY loads another build of lw_oracle.c (the sanitized one from build_sanitized()).
+_LIB_OVERRIDE = os.environ.get("LW_ORACLE_LIBRARY")
 
 C_LIGHT = 299792458.0
 Q_E = 1.602176634e-19
@@ -75,15 +77,33 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_sanitized(out: str) -> str:
+    """The same oracle with AddressSanitizer + UndefinedBehaviorSanitizer (any report aborts).
+    A process that loads it needs gcc's libasan preloaded (``asan_runtime()``)."""
+    subprocess.check_call(
+        ["gcc", "-O1", "-g", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+         "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+         _SRC, "-o", out, "-lm"]
+    )
+    return out
+
+
+def asan_runtime() -> str:
+    return subprocess.check_output(["gcc", "-print-file-name=libasan.so"], text=True).strip()
+
+
 _lib = None
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = ctypes.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            L = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            L = ctypes.CDLL(_LIB)
         dp = ctypes.POINTER(ctypes.c_double)
         i64 = ctypes.c_int64
         d = ctypes.c_double

@@ -13,7 +13,8 @@ import os
 import torch  # noqa: F401  (loads the HIP runtime liblw.so binds to)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblw.so")
+# LW_LIBRARY selects another build of the same library (e.g. one with host-side sanitizers).
+LIB_PATH = os.environ.get("LW_LIBRARY") or os.path.join(HERE, "liblw.so")
 
 LW_OK = 0
 PREC = {"fp64": 0, "mixed": 1}

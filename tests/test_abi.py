@@ -9,7 +9,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "lw.h")
-LIB = os.path.join(ROOT, "paper_2206_03015_amd", "liblw.so")
+LIB = os.environ.get("LW_LIBRARY") or os.path.join(ROOT, "paper_2206_03015_amd", "liblw.so")
 
 
 def declared_functions():
