@@ -740,20 +740,16 @@ def spectra_error(S, S_ref):
     return float(e.max()), float(e.mean())
 
 
-def accuracy(torch, dev):
-    """The accuracy experiment of Sec. "Accuracy": one electron (gamma 5) along +z through 7
-    periods of a counter-propagating 1 um plane wave (sin^2 envelope, a0 = 0.5), 101 observers
-    in the y-z plane over +-2/gamma at 1 m.  The time-domain spectra (FP64 Boris trajectory of
-    2e4 steps -> deposit on N_Tu = 2 N_w grid points with dt_obs = pi/w_max -> FFT) and the
-    direct frequency-domain sum at the same N_w + 1 bins (same trajectory) are compared with a
-    converged reference: the FP64 direct sum over a 16x finer Boris trajectory (its distance to
-    the 8x one is reported).  N_w in {4096, 8192, 16384} (the paper's 5e3, 1e4, 2e4 rounded to
-    powers of two for the FFT); w_max = 3 w1(0).  At N_w = 4096 the time-domain spectra are
-    also taken on 2x, 4x and 8x finer observer grids (the same bins)."""
+def accuracy_setup(torch, dev, n_theta=101, n_s=20000):
+    """Inputs of the accuracy experiment (Sec. "Accuracy"): one electron (gamma 5) along +z
+    through 7 periods of a counter-propagating 1 um plane wave (sin^2 envelope, a0 = 0.5), its
+    FP64 Boris trajectory of n_s steps on the device, n_theta observers in the y-z plane over
+    +-2/gamma at 1 m, w_max = 3 w1(0) and dt_obs = pi/w_max (N_Tu = 2 N_w: the FFT bins are
+    j w_max/N_w), and an observer-window origin before the earliest arrival."""
     from paper_2206_03015_amd import inputs, lw
     c = inputs.C_LIGHT
     gamma, a0, lam, n_cycles = 5.0, 0.5, 1e-6, 7.0
-    n_theta, theta_max, D, n_s, fine = 101, 2.0 / gamma, 1.0, 20000, 16
+    theta_max, D = 2.0 / gamma, 1.0
     t_sim = 1.05 * n_cycles * lam / (2.0 * c)
     t_start = -0.5 * t_sim
     uz = math.sqrt(gamma * gamma - 1.0)
@@ -761,23 +757,37 @@ def accuracy(torch, dev):
     init = torch.as_tensor(np.array([[0.0, 0.0, z0, 0.0, 0.0, uz]]), device=dev)
     th = np.linspace(-theta_max, theta_max, n_theta)
     xd = np.stack([np.zeros_like(th), np.sin(th), np.cos(th)], axis=-1) * D
-    x = torch.as_tensor(xd, device=dev)
     w_l = 2.0 * np.pi * c / lam
     w1 = 4.0 * gamma ** 2 * w_l / (1.0 + 0.5 * a0 * a0)
     w_max = 3.0 * w1
     dt_obs = np.pi / w_max
+    t_first = t_start - np.cos(th) * z0 / c
+    t0 = float(np.min(t_first)) - 16.0 * dt_obs
 
     def traj(n):
         dt = t_sim / (n - 1)
         return dt, lw.trajectory_boris(init, n, t_start, dt, a0, lam, 0.0, n_cycles)
 
-    dt, (r, b, bd) = traj(n_s + 1)
-    dtf, (rf, bf, bdf) = traj(fine * n_s + 1)
-    dth, (rh, bh, bdh) = traj(fine // 2 * n_s + 1)
-    # observer window: starts before the earliest arrival of the first sample, far longer than
-    # the pulse (zero padding), so the FFT bins are j w_max / N_w
-    t_first = t_start - np.cos(th) * z0 / c
-    t0 = float(np.min(t_first)) - 16.0 * dt_obs
+    return dict(gamma=gamma, a0=a0, lam=lam, n_cycles=n_cycles, t_start=t_start, t_sim=t_sim, theta=th,
+                x_det=torch.as_tensor(xd, device=dev), w_max=w_max, dt_obs=dt_obs, t0=t0, traj=traj, n_s=n_s)
+
+
+def accuracy(torch, dev):
+    """The accuracy experiment of Sec. "Accuracy" (set-up of accuracy_setup): the time-domain
+    spectra (FP64 Boris trajectory of 2e4 steps -> deposit on N_Tu = 2 N_w grid points -> FFT) and
+    the direct frequency-domain sum at the same N_w + 1 bins (same trajectory) are compared with
+    a converged reference: the FP64 direct sum over a 16x finer Boris trajectory (its distance to
+    the 8x one is reported).  N_w in {4096, 8192, 16384} (the paper's 5e3, 1e4, 2e4 rounded to
+    powers of two for the FFT).  At N_w = 4096 the time-domain spectra are also taken on 2x, 4x
+    and 8x finer observer grids (the same bins)."""
+    from paper_2206_03015_amd import lw
+    A = accuracy_setup(torch, dev)
+    gamma, a0, lam, n_cycles, t_start = A["gamma"], A["a0"], A["lam"], A["n_cycles"], A["t_start"]
+    x, w_max, dt_obs, t0, n_s, fine = A["x_det"], A["w_max"], A["dt_obs"], A["t0"], A["n_s"], 16
+    n_theta = x.shape[0]
+    dt, (r, b, bd) = A["traj"](n_s + 1)
+    dtf, (rf, bf, bdf) = A["traj"](fine * n_s + 1)
+    dth, (rh, bh, bdh) = A["traj"](fine // 2 * n_s + 1)
     rows = []
     for n_w in (4096, 8192, 16384):
         n_obs = 2 * n_w

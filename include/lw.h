@@ -171,11 +171,13 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec);
  * grid:       pixels and observer grid.
  * prec:       LW_PREC_FP64 (E is double) or LW_PREC_MIXED (E is float; tau and
  *             the crossing decisions are still computed in double).  In the exact
- *             geometry, a particle with max_i |r_i|^2 <= 1e-8 |x_m|^2 (the max over
- *             the pushed span for LW_TRAJ_BORIS) has its path
- *             correction expanded in |r|/|x_m|: to third order in FP64 mode (exact to
- *             rounding), to first order in MIXED mode (relative error of the
- *             correction <= 1.25e-8); other particles use the square-root form.
+ *             geometry, a particle with max_i |r_i|^2 <= 1e-8 |x_m|^2 over its whole
+ *             trajectory (for LW_TRAJ_BORIS the max over every pushed sample, found
+ *             by a first pass of the pusher) has its path correction expanded in
+ *             |r|/|x_m|: to third order in FP64 mode (exact to rounding), to first
+ *             order in MIXED mode (relative error of the correction <= 1.25e-8);
+ *             other particles use the square-root form.  The arrival base
+ *             (t_i - t0 - z_i/c)/dt_obs is summed in double-double and rounded once.
  * field_mask: LW_FIELD_ACCEL and/or LW_FIELD_VELOCITY (non-zero).
  * geom:       LW_GEOM_EXACT or LW_GEOM_FARFIELD, optionally | LW_ACCUMULATE, | LW_CULL.
  * E:          [n_pix][3][n_obs] float or double, overwritten (or accumulated).
@@ -183,7 +185,13 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec);
  *             intervals touching an unusable sample, grid points of deposited
  *             intervals outside [0, n_obs), deposited grid points}; overwritten
  *             (or accumulated).
- * ws:         >= lw_workspace_bytes(LW_WS_DEPOSIT, n_particles, n_samples, prec) bytes.
+ * ws:         per-sample records of the arrival time (arrival base, position and,
+ *             in the exact geometry, its coefficients in the pixel variable: 64 B per
+ *             sample with MIXED, 80 B with FP64) plus 16 B per particle.
+ *             lw_workspace_bytes(LW_WS_DEPOSIT, n_particles, n_samples, prec) holds
+ *             every particle's records; any workspace that holds one particle's
+ *             (lw_workspace_bytes(LW_WS_DEPOSIT, 1, n_samples, prec)) is accepted,
+ *             and the particles are then deposited in as many launches as needed.
  * Contributions are summed with device atomics: results are reproducible to
  * rounding, not bit-for-bit, across runs.
  */
@@ -278,10 +286,11 @@ lw_status lw_spectrum_fft_bwd(const void *E, const void *dS, int64_t n_pix, int6
  * weights is taken piecewise (the trace is not differentiable where a grid
  * point coincides with an arrival time).  prec: FP64 only in this version
  * (MIXED returns LW_E_UNSUPPORTED).  traj: kind LW_TRAJ_SAMPLES.  dE: double
- * [n_pix][3][n_obs].  ws, ws_bytes: reserved (pass NULL, 0).  Arrival times of
- * the exact geometry use the third-order series of the path correction where
- * |r_i|^2 <= 1e-8 |x_m|^2 (exact to rounding, as in the FP64 deposit), else the
- * sqrt/divide form.
+ * [n_pix][3][n_obs].  ws: >= lw_workspace_bytes(LW_WS_DEPOSIT_BWD, n_particles,
+ * n_samples, prec) bytes (each particle's max |r_i|^2).  Arrival times take the
+ * forward deposit's forms: the compensated arrival base, and in the exact
+ * geometry the third-order series of the path correction for particles with
+ * max_i |r_i|^2 <= 1e-8 |x_m|^2 (exact to rounding), else the square-root form.
  */
 lw_status lw_deposit_td_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom,
                             const void *dE, double *d_r, double *d_beta, double *d_beta_dot, void *ws,
