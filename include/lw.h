@@ -215,6 +215,25 @@ lw_status lw_spectrum_fft(const void *E, int64_t n_pix, int64_t n_obs, double dt
                           size_t ws_bytes, hipStream_t stream);
 
 /*
+ * lw_spectrum_fft_noalloc -- lw_spectrum_fft for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same transform and outputs, with the library's own static scratch
+ * array (lw_noalloc_scratch_bytes() = 64 MiB per GPU, held from library load until the
+ * process ends) in place of the workspace.  It calls no allocating routine.  E, S, n_pix,
+ * n_obs, dt_obs, prec as for lw_spectrum_fft; E and S are caller-owned device memory.
+ * One pixel pair's intermediate, 3 n_obs complex values (24 n_obs bytes in MIXED, 48 n_obs
+ * in FP64), must fit the scratch: n_obs <= 2^21 (MIXED) or 2^20 (FP64); larger n_obs
+ * return LW_E_WORKSPACE.  Pixels are transformed in batches of as many pairs as fit.
+ * Every call on one GPU shares that GPU's scratch: calls that may overlap on one GPU
+ * (different streams or host threads without ordering between them) race and give
+ * undefined results; calls ordered on one stream are safe.  The scratch needs no
+ * clearing (each batch writes it fully before reading it).
+ */
+lw_status lw_spectrum_fft_noalloc(const void *E, int64_t n_pix, int64_t n_obs, double dt_obs, int prec, void *S,
+                                  hipStream_t stream);
+size_t lw_noalloc_scratch_bytes(void);
+
+/*
  * lw_direct_fd -- the frequency-domain method (Eq. inty_dft, Algorithm 1)
  * generalised to the exact geometry and the velocity term:
  *   F_c(w) = (dt/sqrt(2 pi)) sum_k sum_{i=0}^{n_samples-1} E_{k,i,c} kappa_{k,i}

@@ -26,6 +26,14 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+
+// Scratch of lw_spectrum_fft_noalloc: a fixed device array that every GPU the library runs on
+// holds from the load of the code object until the process ends.  In host code the name is
+// only a stand-in for the symbol; its device address (one per GPU) comes from
+// hipGetSymbolAddress and is the only form in which host code uses it.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
 
 namespace lw {
 namespace {
@@ -951,6 +959,49 @@ lw_status launch_fft(const void *E, int64_t n_pix, int64_t n_obs, double dt_obs,
 }  // namespace lw
 
 namespace lw {
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mx;
+void *g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch` per GPU, once looked up
+
+// the current device's address of `scratch` (looked up once per device, with it current)
+lw_status noalloc_scratch(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return fail(LW_E_HIP, "lw_spectrum_fft_noalloc: no current device (or device index >= %d)", kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mx);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LW_E_HIP, "lw_spectrum_fft_noalloc: hipGetSymbolAddress(scratch) failed on device %d: %s",
+                        dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LW_OK;
+}
+}  // namespace
+
+size_t fft_noalloc_scratch_bytes() { return kNoallocScratchBytes; }
+
+lw_status launch_fft_noalloc(const void *E, int64_t n_pix, int64_t n_obs, double dt_obs, int prec, void *S,
+                             hipStream_t s)
+{
+    if (n_pix == 0) return LW_OK;
+    const size_t per = prec == LW_PREC_FP64 ? per_pair_bytes<double>(n_obs) : per_pair_bytes<float>(n_obs);
+    if (per > kNoallocScratchBytes)
+        return fail(LW_E_WORKSPACE,
+                    "lw_spectrum_fft_noalloc: one pixel pair of n_obs = %lld needs %zu bytes of scratch, more than "
+                    "the %zu-byte static scratch (use lw_spectrum_fft with a workspace)",
+                    (long long)n_obs, per, kNoallocScratchBytes);
+    void *ptr = nullptr;
+    const lw_status st = noalloc_scratch(&ptr);
+    if (st != LW_OK) return st;
+    return launch_fft(E, n_pix, n_obs, dt_obs, prec, S, ptr, kNoallocScratchBytes, s);
+}
+
 lw_status launch_fft_bwd(const void *E, const void *dS, int64_t n_pix, int64_t n_obs, double dt_obs, int prec,
                          void *dE, void *ws, size_t ws_bytes, hipStream_t s)
 {

@@ -279,6 +279,23 @@ lw_status lw_spectrum_fft(const void *E, int64_t n_pix, int64_t n_obs, double dt
     return launch_fft(E, n_pix, n_obs, dt_obs, prec, S, ws, ws_bytes, stream);
 }
 
+lw_status lw_spectrum_fft_noalloc(const void *E, int64_t n_pix, int64_t n_obs, double dt_obs, int prec, void *S,
+                                  hipStream_t stream)
+{
+    const char *fn = "lw_spectrum_fft_noalloc";
+    if (prec != LW_PREC_FP64 && prec != LW_PREC_MIXED) return fail(LW_E_ARG, "%s: unknown prec %d", fn, prec);
+    if (n_pix < 0) return fail(LW_E_SHAPE, "%s: n_pix < 0", fn);
+    if (!pow2(n_obs) || n_obs < 4 || n_obs > (int64_t(1) << 22))
+        return fail(LW_E_SHAPE, "%s: n_obs must be a power of two in [4, 2^22] (got %lld)", fn, (long long)n_obs);
+    if (!finite_pos(dt_obs)) return fail(LW_E_ARG, "%s: dt_obs must be positive and finite", fn);
+    if (n_pix > 0 && (!E || !S)) return fail(LW_E_ARG, "%s: E and S must be non-NULL", fn);
+    if ((E && !aligned(E, 16)) || (S && !aligned(S, 16)))
+        return fail(LW_E_ALIGN, "%s: E and S must be 16-byte aligned", fn);
+    return launch_fft_noalloc(E, n_pix, n_obs, dt_obs, prec, S, stream);
+}
+
+size_t lw_noalloc_scratch_bytes(void) { return fft_noalloc_scratch_bytes(); }
+
 lw_status lw_direct_fd(const lw_traj_t *traj, const lw_grid_t *grid, const double *omega, int64_t n_omega, int prec,
                        int field_mask, int geom, double *S, void *ws, size_t ws_bytes, hipStream_t stream)
 {

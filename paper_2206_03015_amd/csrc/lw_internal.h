@@ -385,6 +385,10 @@ size_t deposit_ws_bytes(int64_t n_particles, int64_t n_samples, int prec);
 lw_status launch_fft(const void *E, int64_t n_pix, int64_t n_obs, double dt_obs, int prec, void *S, void *ws,
                      size_t ws_bytes, hipStream_t s);
 size_t fft_ws_bytes(int64_t n_pix, int64_t n_obs, int prec);
+// lw_spectrum_fft with the library's static scratch array instead of a workspace
+lw_status launch_fft_noalloc(const void *E, int64_t n_pix, int64_t n_obs, double dt_obs, int prec, void *S,
+                             hipStream_t s);
+size_t fft_noalloc_scratch_bytes();
 lw_status launch_fft_bwd(const void *E, const void *dS, int64_t n_pix, int64_t n_obs, double dt_obs, int prec,
                          void *dE, void *ws, size_t ws_bytes, hipStream_t s);
 lw_status launch_direct_fd(const lw_traj_t *traj, const lw_grid_t *grid, const double *omega, int64_t n_omega,

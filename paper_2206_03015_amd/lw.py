@@ -60,6 +60,8 @@ _SIGS = {
     "lw_deposit_td": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_int,
                                      ctypes.c_int, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "lw_spectrum_fft": (ctypes.c_int, [c_vp, c_i64, c_i64, c_d, ctypes.c_int, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "lw_spectrum_fft_noalloc": (ctypes.c_int, [c_vp, c_i64, c_i64, c_d, ctypes.c_int, c_vp, c_vp]),
+    "lw_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "lw_direct_fd": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), c_vp, c_i64, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_int, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "lw_trajectory_boris": (ctypes.c_int, [ctypes.POINTER(Traj), c_vp, c_vp, c_vp, c_vp]),
@@ -210,6 +212,24 @@ def spectrum_fft(E, dt_obs, prec=None, out=None, ws=None):
     _check(lib.lw_spectrum_fft(_ptr(E), n_pix, n_obs, float(dt_obs), PREC[prec], _ptr(out), _ptr(ws), ws.numel(),
                                _stream()))
     return out
+
+
+def spectrum_fft_noalloc(E, dt_obs, out, prec=None):
+    """lw_spectrum_fft_noalloc: the spectrum of E into the caller's S (`out`), with the library's
+    static scratch instead of a workspace (nothing is allocated)."""
+    lib = load()
+    if prec is None:
+        prec = "fp64" if E.dtype == torch.float64 else "mixed"
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    n_pix, _, n_obs = (int(v) for v in E.shape)
+    _need(E, dtype, (n_pix, 3, n_obs), "E")
+    _need(out, dtype, (n_pix, n_obs // 2 + 1), "S")
+    _check(lib.lw_spectrum_fft_noalloc(_ptr(E), n_pix, n_obs, float(dt_obs), PREC[prec], _ptr(out), _stream()))
+    return out
+
+
+def noalloc_scratch_bytes():
+    return int(load().lw_noalloc_scratch_bytes())
 
 
 def direct_fd(r, beta, beta_dot, t_start, dt, x_det, t0, omega, prec="mixed", field_mask=FIELD_ACCEL,
