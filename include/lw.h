@@ -185,13 +185,15 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec);
  *             intervals touching an unusable sample, grid points of deposited
  *             intervals outside [0, n_obs), deposited grid points}; overwritten
  *             (or accumulated).
- * ws:         per-sample records of the arrival time (arrival base, position and,
- *             in the exact geometry, its coefficients in the pixel variable: 64 B per
- *             sample with MIXED, 80 B with FP64) plus 16 B per particle.
- *             lw_workspace_bytes(LW_WS_DEPOSIT, n_particles, n_samples, prec) holds
- *             every particle's records; any workspace that holds one particle's
- *             (lw_workspace_bytes(LW_WS_DEPOSIT, 1, n_samples, prec)) is accepted,
- *             and the particles are then deposited in as many launches as needed.
+ * ws:         a pixel table (2 MiB: 16384 pixels; larger grids are deposited in
+ *             passes of 16384 pixels), 16 B per particle and per-sample records of
+ *             the arrival time (arrival base, position and, in the exact geometry,
+ *             its coefficients in the pixel variable: 64 B per sample with MIXED,
+ *             80 B with FP64).  lw_workspace_bytes(LW_WS_DEPOSIT, n_particles,
+ *             n_samples, prec) holds every particle's records; any workspace that
+ *             holds one particle's (lw_workspace_bytes(LW_WS_DEPOSIT, 1, n_samples,
+ *             prec)) is accepted, and the particles are then deposited in as many
+ *             launches as needed.
  * Contributions are summed with device atomics: results are reproducible to
  * rounding, not bit-for-bit, across runs.
  */

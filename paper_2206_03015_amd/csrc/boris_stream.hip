@@ -45,7 +45,7 @@ size_t plan_bytes(int64_t B, int64_t L, int prec, bool bwd)
 }
 
 // bytes per (particle, sample) of a plan: samples (72), records (forward) or gradients (adjoint)
-size_t per_sample_bytes(int prec, bool bwd) { return bwd ? 144 : 72 + (prec == LW_PREC_FP64 ? 48 : 32); }
+size_t per_sample_bytes(int prec, bool bwd) { return bwd ? 144 : 72 + (prec == LW_PREC_FP64 ? 80 : 64); }
 
 // longest span (<= lmax) of B particles within `bytes` (0 if not even one sample fits)
 int64_t fit_span(int64_t B, int64_t lmax, size_t bytes, int prec, bool bwd)

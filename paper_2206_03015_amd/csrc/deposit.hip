@@ -8,28 +8,29 @@
 //     coefficients of the arrival time as a polynomial in the pixel variable b
 //     (tau = sum_j c_j b^j, b = C((1 - n_z) z - n_x x - n_y y): three fused multiply-adds per
 //     pixel); it also flags particles whose arrival times are provably increasing and finds
-//     each particle's max |r|^2;
-//   * a wavefront owns 64 x kPPL pixels (kPPL per lane) and a group of particles; for each
-//     particle it walks the samples two at a time, reading each sample's position and record
-//     with scalar loads (the values are wavefront-uniform, so they sit in scalar registers
-//     and feed the vector fused multiply-adds directly; nothing passes through LDS), forms
-//     every (sample, pixel) arrival time in double and tests whether the interval
-//     (tau_{i-1}, tau_i] crosses the next grid point of that pixel's window (all four tests of
-//     a sample pair first, then one branch into the crossing logic if any holds);
-//   * a crossing appends (sample, particle, pixel, tau_{i-1}, tau_i) to a per-wavefront queue in
-//     LDS; whenever 64 entries are queued, all lanes take one entry each, evaluate the
-//     Lienard-Wiechert field at the interval's two ends and add the interpolated values at the
-//     crossed grid points into a write-combining line of that pixel in LDS (a short run of
-//     consecutive grid points of its trace); an interval holding more than kLongRun grid points
-//     (an observer grid much finer than the samples) is deposited by the whole wavefront
-//     instead, 64 grid points per pass;
-//   * a line whose pixel moves past it is added to the trace with global atomics, several lines
-//     per instruction (lane l takes value l % 3N of line l / 3N).
-// The field is therefore evaluated only at samples that the interpolation reads; samples whose
-// interval holds no grid point of the window contribute nothing.  The arrival times the
-// queue carries are the scan's own, so every decision and weight uses one value per
-// (sample, pixel).  With LW_CULL (a separate instantiation) a fast-path particle is skipped
-// when its first and last arrival times at the wavefront's pixels bracket no window grid point.
+//     each particle's max |r|^2; a pixel table holds each pixel's constants;
+//   * fast path (k_scan): a wavefront owns a tile of kTilePix pixels and a group of particles.
+//     For each particle it walks the samples in chunks of 64 (lane j holds sample 63 q + j of
+//     chunk q, so consecutive chunks share one sample and every interval has both ends in one
+//     chunk), two chunks at a time with the next two prefetched.  The records sit in vector
+//     registers; for each pixel of the tile the pixel's constants come from the table with
+//     scalar loads and its next grid point from the lane that stores it, and every lane forms
+//     the arrival time of its sample and compares it with that grid point.  If any lane reaches
+//     it, the crossed grid points of every interval of the chunk follow from the two ends'
+//     arrival times (neighbouring lane); each sample that ends or starts a crossing interval
+//     evaluates the Lienard-Wiechert field once, the interval's start field comes from the
+//     neighbouring lane, and the interpolated values go to the trace with global atomics (the
+//     crossed grid points of consecutive intervals are consecutive, so these are contiguous).
+//     An interval holding more than kLongRun grid points (an observer grid much finer than the
+//     samples) is deposited by the whole wavefront, 64 grid points per pass;
+//   * careful path (k_careful, particles the pre-pass could not clear): lanes own pixels; the
+//     skip rules of lw_deposit_td are applied interval by interval, crossings go through a queue
+//     in LDS and write-combining lines of the trace (see Wave).
+// The field is therefore evaluated only at samples that the interpolation reads.  Every decision
+// and weight uses one arrival-time value per (sample, pixel): both orientations evaluate it with
+// the same operations (tau_eval).  With LW_CULL (a separate instantiation) a fast-path particle
+// is skipped when its first and last arrival times at the wavefront's pixels bracket no window
+// grid point.
 //
 // Arrival-time forms (exact geometry): the polynomial records hold the path term's series
 // (first order with single-precision fields, third order with double ones; valid where
@@ -41,8 +42,6 @@
 // Fast path condition (checked per particle by the pre-pass): every sample usable and
 // every step shorter than c*dt by a margin well above the rounding of tau, which makes
 // tau strictly increasing for every pixel (|x - r_i| - |x - r_{i-1}| >= -|r_i - r_{i-1}|).
-// Particles that fail it take the careful path, which applies the skip rules of
-// lw_deposit_td interval by interval.
 #include "lw_internal.h"
 
 #include <algorithm>
@@ -56,7 +55,9 @@ constexpr int kTilePix = 64 * kPPL;     // pixels per wavefront
 constexpr int kPixBits = 7;
 static_assert((1 << kPixBits) == kTilePix, "tile of 128 pixels");
 constexpr int kBlockThreads = 64;
-constexpr uint32_t kQCap = 64 + kTilePix;  // queue ring: 63 pending + one sample's crossings
+// queue ring: up to 63 pending entries plus one push (at most 64 crossings: one sample's pixels
+// of one half of the tile on the careful path, one chunk's intervals on the fast path)
+constexpr uint32_t kQCap = 128;
 // write-combining line per pixel: 16-byte segments of the trace (4 floats or 2 doubles)
 template <typename T>
 struct WcLine {
@@ -74,6 +75,11 @@ constexpr double kSeriesBound = 1e-8;
 // pixels whose |x_m| is within this relative distance of the records' distance use the records
 constexpr double kSameDistance = 4.0 * 2.220446049250313e-16;
 constexpr int kPrepassChunk = 8192;
+// pixel table: kPT doubles per pixel (o, px, py, ok, nx, ny, nz, D, invD, padding), at most
+// kPixTabMax pixels per pass (its share of the workspace); larger grids take several passes
+constexpr int kPT = 16;
+constexpr int64_t kPixTabMax = 16384;
+static_assert(kPixTabMax % kTilePix == 0, "whole tiles per pixel pass");
 
 // scan modes: polynomial records (degree 3 or 5 in b, exact geometry), far field (tau = d + b),
 // or arrival_tau per pixel in one of its forms
@@ -123,14 +129,6 @@ __device__ __forceinline__ void lds_add(T *p, T v)
 // |r|^2 with the operation order of the pre-pass
 __device__ __forceinline__ double sq3(double x, double y, double z) { return fma(z, z, fma(y, y, x * x)); }
 
-// a * b + c with c in a scalar register (VOP3 form: the two-operand form would need a copy of c)
-__device__ __forceinline__ double fma_vvs(double a, double b, double c)
-{
-    double d;
-    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
-    return d;
-}
-
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -170,20 +168,107 @@ __device__ __forceinline__ cdptr uniform_ptr(const double *p)
     return (cdptr)(((uint64_t)hi << 32) | lo);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Pixel table and the arrival time shared by both orientations of the scan
+
+// rows [0, n_rows): the pixels [0, n_pix), then padding rows (all zero, not usable) up to the end
+// of the last tile, whose arrival times stay finite
+__global__ void k_pixtab(const double *__restrict__ x_det, int64_t n_pix, int64_t n_rows, double C,
+                         double *__restrict__ pt)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n_rows) return;
+    double *o = pt + m * kPT;
+    if (m >= n_pix) {
+#pragma unroll
+        for (int j = 0; j < kPT; ++j) o[j] = 0.0;
+        return;
+    }
+    const PixC p = pix_const(x_det, m, C);
+    o[0] = p.o;
+    o[1] = p.px;
+    o[2] = p.py;
+    o[3] = p.g.ok ? 1.0 : 0.0;
+    o[4] = p.g.nx;
+    o[5] = p.g.ny;
+    o[6] = p.g.nz;
+    o[7] = p.g.D;
+    o[8] = p.g.invD;
+#pragma unroll
+    for (int j = 9; j < kPT; ++j) o[j] = 0.0;
+}
+
+// a pixel's constants from its table row (per lane, or wavefront-uniform through scalar loads)
+template <typename P>
+__device__ __forceinline__ PixC pixc_row(P row)
+{
+    PixC p;
+    p.o = row[0];
+    p.px = row[1];
+    p.py = row[2];
+    p.g.ok = row[3] != 0.0;
+    p.g.nx = row[4];
+    p.g.ny = row[5];
+    p.g.nz = row[6];
+    p.g.D = row[7];
+    p.g.invD = row[8];
+    return p;
+}
+
+// The part of a record a scan mode reads: offset OFF and count N of doubles; X: offset of the
+// position within them; LEAD: the value (c_0 or d) that carries the arrival time's constant term
+// (-inf there makes the arrival time -inf: no crossing)
+template <int GEOM, bool F64, int MODE>
+struct ScanVals {
+    using L = RecLayout<GEOM, F64>;
+    static constexpr bool kRecMode = MODE == kModeRec3 || MODE == kModeRec5;
+    static constexpr int OFF = MODE == kModeMixed ? L::X : 0;
+    static constexpr int N = (MODE == kModeFar || MODE == kModeMixed) ? 4 : L::DEG + 3;
+    static constexpr int X = MODE == kModeFar ? 1 : (MODE == kModeMixed ? 0 : L::DEG);
+    static constexpr int LEAD = MODE == kModeMixed ? 3 : 0;
+};
+
+// Arrival time of one (sample, pixel) in scan mode MODE from the record values v and the pixel
+// constants P: far field tau = d + b; polynomial records tau = sum_j c_j b^j (c_DEG = cK); else
+// arrival_tau in the pixel's form (series where rb2 |x_m|^-2 <= kSeriesBound).  Both orientations
+// (lanes over pixels, v uniform; lanes over samples, P uniform) run these same operations, so a
+// (sample, pixel) gets the same bits wherever it is evaluated.
+template <int GEOM, bool F64, int MODE>
+__device__ __forceinline__ double tau_eval(const PixC &P, const double *v, double cK, double rb2, double C)
+{
+    if constexpr (MODE == kModeFar) {
+        return pix_b(P, v[1], v[2], v[3]) + v[0];
+    } else if constexpr (MODE == kModeRec3 || MODE == kModeRec5) {
+        constexpr int DEG = RecLayout<GEOM, F64>::DEG;
+        const double b = pix_b(P, v[DEG], v[DEG + 1], v[DEG + 2]);
+        double u = fma(b, cK, v[DEG - 1]);
+#pragma unroll
+        for (int j = DEG - 2; j >= 0; --j) u = fma(b, u, v[j]);
+        return u;
+    } else {
+        constexpr int FORM = F64 ? kTauSeries : kTauShort;
+        const double x = v[0], y = v[1], z = v[2], rr = sq3(x, y, z);
+        if (rb2 * (P.g.invD * P.g.invD) <= kSeriesBound) return arrival_tau<GEOM, FORM>(P, v[3], x, y, z, rr, C);
+        return arrival_tau<GEOM, kTauSqrt>(P, v[3], x, y, z, rr, C);
+    }
+}
+
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct DepWs {
+    double *pt;                 // [kPixTabMax][kPT] pixel table of the current pass
     int *pflag;                 // [n_p] 0 = fast path
     unsigned long long *rmax2;  // [n_p] bits of max_i |r_i|^2 (non-negative doubles order as integers)
     double *rec;                // [n_p][n_s][rec_width] records
 };
 
-// records: one more than the samples (the scan loads the record after a particle's last sample
-// ahead of time and discards it)
+constexpr size_t kPixTabBytes = (size_t)kPixTabMax * kPT * sizeof(double);
+
+// pixel table, flags, bounds and records (one record more than the samples: padding)
 size_t ws_bytes_for(int64_t n_p, int64_t ns, int rw)
 {
     const size_t np = (size_t)std::max<int64_t>(n_p, 1), nsz = (size_t)std::max<int64_t>(ns, 1);
-    return align_up(np * sizeof(int), 256) + align_up(np * sizeof(unsigned long long), 256) +
+    return kPixTabBytes + align_up(np * sizeof(int), 256) + align_up(np * sizeof(unsigned long long), 256) +
            align_up((np * nsz + 1) * (size_t)rw * sizeof(double), 256);
 }
 
@@ -191,6 +276,8 @@ DepWs carve(void *ws, int64_t n_p)
 {
     DepWs w;
     char *p = (char *)ws;
+    w.pt = (double *)p;
+    p += kPixTabBytes;
     w.pflag = (int *)p;
     p += align_up((size_t)std::max<int64_t>(n_p, 1) * sizeof(int), 256);
     w.rmax2 = (unsigned long long *)p;
@@ -291,7 +378,9 @@ struct DepShape {
     int fmask;
 };
 
-// Per-wavefront state of the deposit kernel.
+// Per-wavefront state of the careful path (k_careful): lanes own pixels (kPPL each); a particle's
+// samples are taken one at a time, with the skip rules applied per interval; crossings are queued
+// in LDS and drained 64 at a time into write-combining lines of the trace.
 template <typename T, int GEOM>
 struct Wave {
     const double *__restrict__ r;
@@ -300,6 +389,7 @@ struct Wave {
     const double *__restrict__ charge;
     const double *__restrict__ x_det;
     const double *__restrict__ rec;
+    const double *__restrict__ pt;  // pixel table of this pass
     T *__restrict__ E;
     DepShape sh;
     double cK;  // leading coefficient of the polynomial records
@@ -330,52 +420,11 @@ struct Wave {
         return MODE == kModeFar || MODE == kModeMixed ? 4 : Lay::DEG + 3;
     }
 
-    // Arrival time of pixel h from the scan values v of a sample's record (wavefront-uniform):
-    // far field {d, x, y, z}; polynomial records {c_0 .. c_{DEG-1}, x, y, z}; arrival_tau per
-    // pixel {x, y, z, d}.
+    // Arrival time of pixel h from the scan values v of a sample's record (wavefront-uniform)
     template <int MODE>
     __device__ __forceinline__ double tau_of(int h, const double *v) const
     {
-        const PixC &p = pc[h];
-        if constexpr (MODE == kModeFar) {
-            return pix_b(p, v[1], v[2], v[3]) + v[0];
-        } else if constexpr (MODE == kModeRec3 || MODE == kModeRec5) {
-            constexpr int DEG = Lay::DEG;
-            const double b = pix_b(p, v[DEG], v[DEG + 1], v[DEG + 2]);
-            double u = fma_vvs(b, cK, v[DEG - 1]);
-#pragma unroll
-            for (int j = DEG - 2; j >= 0; --j) u = fma_vvs(b, u, v[j]);
-            return u;
-        } else {
-            constexpr int FORM = sizeof(T) == 8 ? kTauSeries : kTauShort;
-            const double x = v[0], y = v[1], z = v[2], rr = sq3(x, y, z);
-            if (rb2 * (p.g.invD * p.g.invD) <= kSeriesBound) return arrival_tau<GEOM, FORM>(p, v[3], x, y, z, rr, sh.C);
-            return arrival_tau<GEOM, kTauSqrt>(p, v[3], x, y, z, rr, sh.C);
-        }
-    }
-
-    // the arrival times of both pixels of this lane, the two pixels' operation chains interleaved
-    template <int MODE>
-    __device__ __forceinline__ void tau_pair(const double *v, double *t) const
-    {
-        static_assert(kPPL == 2, "two pixels per lane");
-        if constexpr (MODE == kModeRec3 || MODE == kModeRec5) {
-            constexpr int DEG = Lay::DEG;
-            const double b0 = pix_b(pc[0], v[DEG], v[DEG + 1], v[DEG + 2]);
-            const double b1 = pix_b(pc[1], v[DEG], v[DEG + 1], v[DEG + 2]);
-            double u0 = fma_vvs(b0, cK, v[DEG - 1]);
-            double u1 = fma_vvs(b1, cK, v[DEG - 1]);
-#pragma unroll
-            for (int j = DEG - 2; j >= 0; --j) {
-                u0 = fma_vvs(b0, u0, v[j]);
-                u1 = fma_vvs(b1, u1, v[j]);
-            }
-            t[0] = u0;
-            t[1] = u1;
-        } else {
-            t[0] = tau_of<MODE>(0, v);
-            t[1] = tau_of<MODE>(1, v);
-        }
+        return tau_eval<GEOM, sizeof(T) == 8, MODE>(pc[h], v, cK, rb2, sh.C);
     }
 
     // the scan values of sample i of particle k
@@ -419,21 +468,10 @@ struct Wave {
         const uint2 e = act ? q[slot] : make_uint2(1u, 0u);
         const double2 tt = act ? qt[slot] : make_double2(0.0, 1.0);
         const int ml0 = (int)(e.y & (uint32_t)(kTilePix - 1));
-        // far field: the entry's pixel direction from the lane that owns the pixel (all lanes take part)
+        // far field: the entry's pixel direction from the pixel table
         PixGeo g;
         if (GEOM == LW_GEOM_FARFIELD) {
-            const int own = ml0 & 63, hh = ml0 >> 6;
-            auto pick = [&](double v0, double v1) {
-                const double a = __shfl(v0, own);
-                const double b = __shfl(v1, own);
-                return hh ? b : a;
-            };
-            g.nx = pick(pc[0].g.nx, pc[kPPL - 1].g.nx);
-            g.ny = pick(pc[0].g.ny, pc[kPPL - 1].g.ny);
-            g.nz = pick(pc[0].g.nz, pc[kPPL - 1].g.nz);
-            g.invD = pick(pc[0].g.invD, pc[kPPL - 1].g.invD);
-            g.D = 1.0 / g.invD;
-            g.ok = true;
+            g = pixc_row(pt + (size_t)(tile * kTilePix + ml0) * kPT).g;
         } else {
             g.nx = g.ny = 0.0;
             g.nz = g.D = g.invD = 1.0;
@@ -545,146 +583,6 @@ struct Wave {
         while (qn >= 64) drain(64);
     }
 
-    // queue the crossings of the intervals (tp[h], tv[h]] ending at sample jj (at most kTilePix)
-    __device__ __forceinline__ void hits(uint32_t jj, uint32_t tag0, const double *tp, const double *tv,
-                                         double *gnext, double nob)
-    {
-#pragma unroll
-        for (int h = 0; h < kPPL; ++h) {
-            const bool hit = tv[h] >= gnext[h];
-            const uint64_t mask = __ballot(hit);
-            if (mask) {
-                if (hit) {
-                    const double f = floor(tv[h]) + 1.0;
-                    gnext[h] = f >= nob ? INFINITY : f;
-                }
-                push(hit, mask, jj, tag0 + 64u * (uint32_t)h, tp[h], tv[h]);
-            }
-        }
-    }
-
-    // Scan of a fast-path particle from sample j on: every arrival time is evaluated and tested
-    // against the pixel's next grid point, crossings are queued; returns the next sample to scan
-    // once the queue holds 64 or more entries (the caller drains it), or n_samples.  Records are
-    // wavefront-uniform loads into two alternating buffers: the next sample's load is issued
-    // once the current one has arrived, before the current sample's arithmetic.
-    template <int MODE>
-    __device__ __forceinline__ int scan_run(int64_t k, int j, int ns, uint32_t tag0, double *tau, double *gnext,
-                                            double nob)
-    {
-        constexpr int NV = scan_n<MODE>();
-        constexpr int W = Lay::W;
-        cdptr p = uniform_ptr(rec + ((size_t)k * sh.n_samples + j) * W + scan_off<MODE>());
-        double A[NV], B[NV];
-#pragma unroll
-        for (int c = 0; c < NV; ++c) A[c] = p[c];
-        // sample j from the scan values V: its arrival times, their tests and the queue; leaves the
-        // scan (returning the next sample) when the queue needs draining
-#define LW_SCAN_STEP(V)                                                                                               \
-    {                                                                                                                 \
-        double t[kPPL];                                                                                               \
-        tau_pair<MODE>(V, t);                                                                                         \
-        uint64_t any = 0;                                                                                             \
-        _Pragma("unroll") for (int h = 0; h < kPPL; ++h) any |= __ballot(t[h] >= gnext[h]);                          \
-        if (any) {                                                                                                    \
-            hits((uint32_t)j, tag0, tau, t, gnext, nob);                                                              \
-            if (qn >= 64) {                                                                                           \
-                _Pragma("unroll") for (int h = 0; h < kPPL; ++h) tau[h] = t[h];                                       \
-                return j + 1;                                                                                         \
-            }                                                                                                         \
-        }                                                                                                             \
-        _Pragma("unroll") for (int h = 0; h < kPPL; ++h) tau[h] = t[h];                                               \
-    }
-        for (;;) {
-            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the record of sample j is in
-            __builtin_amdgcn_sched_barrier(0);
-            p += W;  // the next sample's record (past the last one: the next particle's, or padding)
-#pragma unroll
-            for (int c = 0; c < NV; ++c) B[c] = p[c];
-            __builtin_amdgcn_sched_barrier(0);
-            LW_SCAN_STEP(A)
-            if (++j >= ns) return j;
-            __builtin_amdgcn_s_waitcnt(0xc07f);
-            __builtin_amdgcn_sched_barrier(0);
-            p += W;
-#pragma unroll
-            for (int c = 0; c < NV; ++c) A[c] = p[c];
-            __builtin_amdgcn_sched_barrier(0);
-            LW_SCAN_STEP(B)
-            if (++j >= ns) return j;
-        }
-#undef LW_SCAN_STEP
-    }
-
-    // Fast path: tau strictly increasing, all samples usable.
-    template <int MODE>
-    __device__ __forceinline__ void fast_particle(const bool *lane_ok, const bool *pix_in, int64_t k,
-                                                  unsigned long long &c1, unsigned long long &c2,
-                                                  unsigned long long &c3)
-    {
-        constexpr int NV = scan_n<MODE>();
-        const int ns = (int)sh.n_samples;
-        const double nob = (double)sh.n_obs;
-        const uint32_t tag0 = ((uint32_t)(k - k0) << kPixBits) | (uint32_t)lane;
-        double tau[kPPL], tau0[kPPL], gnext[kPPL];
-        {
-            double v[NV];
-            load_scan<MODE>(k, 0, v);
-#pragma unroll
-            for (int h = 0; h < kPPL; ++h) {
-                tau[h] = tau0[h] = tau_of<MODE>(h, v);
-                gnext[h] = lane_ok[h] ? next_grid(tau[h], nob) : INFINITY;
-            }
-        }
-        for (int j = 1; j < ns;) {
-            j = scan_run<MODE>(k, j, ns, tag0, tau, gnext, nob);
-            pump();
-        }
-#pragma unroll
-        for (int h = 0; h < kPPL; ++h) {
-            if (lane_ok[h]) {
-                const int64_t inside = grid_count(tau[h], nob) - grid_count(tau0[h], nob);
-                c3 += (unsigned long long)inside;
-                c2 += (unsigned long long)((int64_t)(floor(tau[h]) - floor(tau0[h])) - inside);
-            } else if (pix_in[h]) {
-                c1 += (unsigned long long)(ns - 1);
-            }
-        }
-    }
-
-    // Culling (LW_CULL, fast-path particles only): arrival times are strictly increasing, so the
-    // particle deposits into this wavefront's pixels only if some pixel has a window grid point
-    // in (tau_first, tau_last].  If none has, the counters follow from the two end points and
-    // the particle is skipped; the results are those of the full scan.
-    template <int MODE>
-    __device__ __forceinline__ bool outside(const bool *lane_ok, const bool *pix_in, int64_t k, unsigned long long &c1,
-                                            unsigned long long &c2)
-    {
-        constexpr int NV = scan_n<MODE>();
-        const int64_t ns = sh.n_samples;
-        const double nob = (double)sh.n_obs;
-        double v0[NV], v1[NV];
-        load_scan<MODE>(k, 0, v0);
-        load_scan<MODE>(k, ns - 1, v1);
-        double tf[kPPL], tl[kPPL];
-        bool in = false;
-#pragma unroll
-        for (int h = 0; h < kPPL; ++h) {
-            tf[h] = tau_of<MODE>(h, v0);
-            tl[h] = tau_of<MODE>(h, v1);
-            in |= lane_ok[h] && grid_count(tl[h], nob) > grid_count(tf[h], nob);
-        }
-        if (__ballot(in)) return false;
-#pragma unroll
-        for (int h = 0; h < kPPL; ++h) {
-            if (lane_ok[h])
-                c2 += (unsigned long long)(int64_t)(floor(tl[h]) - floor(tf[h]));
-            else if (pix_in[h])
-                c1 += (unsigned long long)(ns - 1);
-        }
-        return true;
-    }
-
     // Careful path: the skip rules of lw_deposit_td interval by interval, pixel h of this lane,
     // with the arrival times of the fast path's MODE (the same values wherever a particle takes
     // the fast path in one span and the careful path in another).
@@ -738,32 +636,40 @@ struct Wave {
         }
     }
 
-    // One particle in scan mode MODE: culled (LW_CULL), fast or careful path.
-    template <int MODE, bool CULL>
-    __device__ __forceinline__ void particle(bool fast, const bool *lane_ok, const bool *pix_in, const int64_t *m,
-                                             int64_t k, unsigned long long &c0, unsigned long long &c1,
-                                             unsigned long long &c2, unsigned long long &c3)
+    // One particle in scan mode MODE, both pixels of this lane
+    template <int MODE>
+    __device__ __forceinline__ void particle(const bool *lane_ok, const bool *pix_in, const int64_t *m, int64_t k,
+                                             unsigned long long &c0, unsigned long long &c1, unsigned long long &c2,
+                                             unsigned long long &c3)
     {
         static_assert(kPPL == 2, "careful path written for two pixels per lane");
-        if (fast) {
-            if (CULL && outside<MODE>(lane_ok, pix_in, k, c1, c2)) return;
-            fast_particle<MODE>(lane_ok, pix_in, k, c1, c2, c3);
-        } else {
-            careful_particle<MODE, 0>(lane_ok[0], pix_in[0], m[0], k, c0, c1, c2, c3);
-            careful_particle<MODE, 1>(lane_ok[1], pix_in[1], m[1], k, c0, c1, c2, c3);
-        }
+        careful_particle<MODE, 0>(lane_ok[0], pix_in[0], m[0], k, c0, c1, c2, c3);
+        careful_particle<MODE, 1>(lane_ok[1], pix_in[1], m[1], k, c0, c1, c2, c3);
     }
 };
 
-template <typename T, int GEOM, bool CULL>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_deposit(
+// careful path: the particles the pre-pass flagged (a wavefront whose group holds none exits)
+template <typename T, int GEOM>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_careful(
     const double *__restrict__ r, const double *__restrict__ beta, const double *__restrict__ beta_dot,
     const double *__restrict__ charge, const double *__restrict__ x_det, const double *__restrict__ rec,
-    const int *__restrict__ pflag, const unsigned long long *__restrict__ rmax2, const double *__restrict__ rbound2,
-    T *__restrict__ E, unsigned long long *__restrict__ diag, DepShape sh)
+    const double *__restrict__ pt, const int *__restrict__ pflag, const unsigned long long *__restrict__ rmax2,
+    const double *__restrict__ rbound2, T *__restrict__ E, unsigned long long *__restrict__ diag, DepShape sh)
 {
     constexpr bool kF64 = sizeof(T) == 8;
     constexpr int kRec = kF64 ? kModeRec5 : kModeRec3;
+    // block -> (particle group, tile) as in k_scan
+    const int64_t b = blockIdx.x;
+    const int64_t xcd = b & 7, slot = b >> 3;
+    const int64_t grp = (slot / sh.n_tiles) * 8 + xcd;
+    const int64_t tile = slot % sh.n_tiles;
+    const int64_t k0 = grp * sh.parts_per_group;
+    const int64_t k1 = grp < sh.n_groups ? std::min(k0 + sh.parts_per_group, sh.n_particles) : k0;
+    {
+        bool any = false;
+        for (int64_t k = k0 + (threadIdx.x & 63); k < k1; k += 64) any |= pflag[k] != 0;
+        if (__ballot(any) == 0) return;  // whole block (one wavefront)
+    }
     __shared__ uint2 q_all[kQCap];
     __shared__ double2 qt_all[kQCap];
     __shared__ T wc_all[kTilePix * WcLine<T>::P];
@@ -775,14 +681,6 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     if (threadIdx.x < 4) red[threadIdx.x] = 0ull;
     __syncthreads();
 
-    // block -> (particle group, tile); consecutive groups on one XCD share trajectory lines in L2
-    const int64_t b = blockIdx.x;
-    const int64_t xcd = b & 7, slot = b >> 3;
-    const int64_t grp = (slot / sh.n_tiles) * 8 + xcd;
-    const int64_t tile = slot % sh.n_tiles;
-    const int64_t k0 = grp * sh.parts_per_group;
-    const int64_t k1 = grp < sh.n_groups ? std::min(k0 + sh.parts_per_group, sh.n_particles) : k0;
-
     Wave<T, GEOM> w;
     int64_t m[kPPL];
     bool pix_in[kPPL], lane_ok[kPPL];
@@ -793,7 +691,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     for (int h = 0; h < kPPL; ++h) {
         m[h] = tile * kTilePix + 64 * h + lane;
         pix_in[h] = m[h] < sh.n_pix;
-        w.pc[h] = pix_const(x_det, pix_in[h] ? m[h] : 0, sh.C);
+        w.pc[h] = pixc_row(pt + (pix_in[h] ? m[h] : 0) * kPT);
         lane_ok[h] = pix_in[h] && w.pc[h].g.ok;
         if (lane_ok[h]) {
             id2 = fmax(id2, w.pc[h].g.invD * w.pc[h].g.invD);
@@ -818,6 +716,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     w.charge = charge;
     w.x_det = x_det;
     w.rec = rec;
+    w.pt = pt;
     w.E = E;
     w.sh = sh;
     w.lane = lane;
@@ -841,17 +740,17 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
 
     unsigned long long c0 = 0, c1 = 0, c2 = 0, c3 = 0;
     for (int64_t k = k0; k < k1; ++k) {
+        if (pflag[k] == 0) continue;  // fast path: k_scan
         // series forms where |r|^2 <= 1e-8 |x_m|^2 over the whole trajectory (the max over the
         // whole trajectory when given, else over the samples of this call), decided per pixel
         w.rb2 = rbound2 ? rbound2[k] : __longlong_as_double((long long)rmax2[k]);
         const bool all_ser = GEOM == LW_GEOM_EXACT && w.rb2 * invD2max <= kSeriesBound;
-        const bool fast = pflag[k] == 0;
         if (GEOM == LW_GEOM_FARFIELD)
-            w.template particle<kModeFar, CULL>(fast, lane_ok, pix_in, m, k, c0, c1, c2, c3);
+            w.template particle<kModeFar>(lane_ok, pix_in, m, k, c0, c1, c2, c3);
         else if (all_ser && rec_ok)
-            w.template particle<kRec, CULL>(fast, lane_ok, pix_in, m, k, c0, c1, c2, c3);
+            w.template particle<kRec>(lane_ok, pix_in, m, k, c0, c1, c2, c3);
         else
-            w.template particle<kModeMixed, CULL>(fast, lane_ok, pix_in, m, k, c0, c1, c2, c3);
+            w.template particle<kModeMixed>(lane_ok, pix_in, m, k, c0, c1, c2, c3);
     }
     while (w.qn > 0) w.drain(w.qn < 64 ? w.qn : 64);
 #pragma unroll
@@ -859,6 +758,338 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
 
     // counters: block reduction in LDS, then one global atomic per counter
     if (c0) atomicAdd(&red[0], c0);
+    if (c1) atomicAdd(&red[1], c1);
+    if (c2) atomicAdd(&red[2], c2);
+    if (c3) atomicAdd(&red[3], c3);
+    __syncthreads();
+    if (diag && threadIdx.x < 4 && red[threadIdx.x]) atomicAdd(diag + threadIdx.x, red[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Fast path.  Lanes over samples: lane j of chunk q holds sample 63 q + j (chunks share their
+// boundary sample, so interval (63 q + j - 1, 63 q + j] has both ends in chunk q for j >= 1).
+
+template <typename T, int GEOM>
+struct ScanWave {
+    static constexpr bool F64 = sizeof(T) == 8;
+    using Lay = RecLayout<GEOM, F64>;
+    // chunks per block: three with single-precision fields, two with double ones (their larger
+    // records and drain take the registers a third chunk would need)
+    static constexpr int NB = F64 ? 2 : 3;
+    Wave<T, GEOM> d;       // queue, drain and write-combining lines (shared with the careful path)
+    double *pcl;           // LDS: o, px, py, g of the tile's pixels, [kTilePix + 1][4] (one padding row);
+                           // g: the pixel's next grid point above the arrival times scanned so far
+    uint64_t okmask[kPPL]; // pixels 64 h + l of the tile that take part (in the pass, geometry ok)
+
+    // Issue the loads of the records of chunks q .. q + NB - 1 (lane = sample) into R; valid[c]
+    // is false for samples past the last one and chunks past the last one (q + c >= nq), whose
+    // constant term the caller sets to -inf once the loads are in (mask_block), so that the loads
+    // can stay in flight meanwhile.
+    template <int MODE>
+    __device__ __forceinline__ void load_block(const double *rk, int q, int nq, double (*R)[ScanVals<GEOM, F64, MODE>::N],
+                                               bool *valid, bool use_first, const double (&first)[NB]) const
+    {
+        using SV = ScanVals<GEOM, F64, MODE>;
+        const int ns = (int)d.sh.n_samples;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            const int s = 63 * (q + c) + d.lane;
+            valid[c] = s < ns && q + c < nq;
+            const double *src = rk + (size_t)(valid[c] ? s : ns - 1) * Lay::W;
+            R[c][0] = use_first ? first[c] : src[0];
+#pragma unroll
+            for (int v = 1; v < SV::N; ++v) R[c][v] = src[v];
+        }
+    }
+    // The first scan value of each record of chunks q .. q + NB - 1, loaded one block ahead: it
+    // brings the records' cache lines in while the current block is scanned (the rest of each
+    // record is loaded at the block's start, from the cache).
+    template <int MODE>
+    __device__ __forceinline__ void touch_block(const double *rk, int q, double (&first)[NB]) const
+    {
+        const int ns = (int)d.sh.n_samples;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            const int s = std::min(63 * (q + c) + d.lane, ns - 1);
+            first[c] = rk[(size_t)s * Lay::W];
+        }
+    }
+    template <int MODE>
+    __device__ __forceinline__ static void mask_block(double (*R)[ScanVals<GEOM, F64, MODE>::N], const bool *valid)
+    {
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            if (!valid[c]) R[c][ScanVals<GEOM, F64, MODE>::LEAD] = -INFINITY;
+    }
+
+    // Crossings of pixel p (tile-local) in the chunks of a block that reached its next grid point:
+    // the intervals that hold grid points of the window are queued with their two arrival times
+    // (the field and the deposit follow in the drain, 64 intervals at a time).
+    __device__ __forceinline__ void crossings(int64_t k, int q0, int nq, int p, const double *t)
+    {
+        const int ns = (int)d.sh.n_samples;
+        const double nob = (double)d.sh.n_obs;
+        const uint32_t tag = ((uint32_t)(k - d.k0) << kPixBits) | (uint32_t)p;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            if (q0 + c >= nq) break;
+            const int s = 63 * (q0 + c) + d.lane;
+            const bool iv = d.lane >= 1 && s < ns;  // this lane ends an interval
+            const double tb = t[c];
+            const double ta = __shfl_up(tb, 1);
+            // arrival times increase on the fast path: the interval holds grid points iff the
+            // count of window grid points up to its end exceeds that up to its start
+            const bool hit = iv && (int)fmin(fmax(floor(tb) + 1.0, 0.0), nob) > (int)fmin(fmax(floor(ta) + 1.0, 0.0), nob);
+            const uint64_t mask = __ballot(hit);
+            if (mask) {
+                d.push(hit, mask, (uint32_t)s, tag, ta, tb);
+                d.pump();
+            }
+        }
+    }
+
+    // Scan of a fast-path particle over all its intervals (each pixel's next grid point is in pcl)
+    template <int MODE>
+    __device__ __forceinline__ void scan(int64_t k, const double *rk)
+    {
+        using SV = ScanVals<GEOM, F64, MODE>;
+        constexpr int NV = SV::N;
+        const int ns = (int)d.sh.n_samples;
+        const int nq = (ns - 1 + 62) / 63;  // chunks (ns >= 2)
+        const double nob = (double)d.sh.n_obs;
+        double R[NB][NV], first[NB] = {};
+        bool vr[NB];
+        for (int q0 = 0; q0 < nq; q0 += NB) {
+            // this block's records, all in before the pixel loop, so that no wait inside it also
+            // waits for the drain's atomics; the next block's first values are loaded meanwhile
+            // (a whole prefetched block would take registers that cost a wavefront per SIMD)
+            load_block<MODE>(rk, q0, nq, R, vr, q0 > 0, first);
+            mask_block<MODE>(R, vr);
+            __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
+            if (q0 + NB < nq) touch_block<MODE>(rk, q0 + NB, first);
+            // the block's last sample: chunk c_last, lane l_last (uniform)
+            const int s_last = std::min(63 * (q0 + NB), ns - 1);
+            const int c_last = (s_last - 1) / 63 - q0;
+            const int l_last = s_last - 63 * (q0 + c_last);
+            // every pixel of the tile: one that takes no part (past the pass's last pixel, or its
+            // geometry not usable) has next grid point +inf, so its arrival times never reach it
+#pragma unroll
+            for (int h = 0; h < kPPL; ++h) {
+                cdptr row = uniform_ptr(d.pt + (size_t)(d.tile * kTilePix + 64 * h) * kPT);
+                // o, px, py, g of the next pixel, read from LDS one iteration ahead (the same address
+                // in every lane; one padding row past the tile's last pixel)
+                double no = pcl[4 * (64 * h)], npx = pcl[4 * (64 * h) + 1], npy = pcl[4 * (64 * h) + 2],
+                       ng = pcl[4 * (64 * h) + 3];
+#pragma unroll 2
+                for (int l = 0; l < 64; ++l, row += kPT) {
+                    const int p = 64 * h + l;
+                    PixC P;
+                    const double g = ng;
+                    if constexpr (MODE == kModeMixed) {
+                        P = pixc_row(row);  // the whole geometry, scalar loads
+                    } else {
+                        P.o = no;
+                        P.px = npx;
+                        P.py = npy;
+                        no = pcl[4 * (p + 1)];
+                        npx = pcl[4 * (p + 1) + 1];
+                        npy = pcl[4 * (p + 1) + 2];
+                    }
+                    ng = pcl[4 * (p + 1) + 3];
+                    double t[NB];
+                    uint64_t any = 0;
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) {
+                        t[c] = tau_eval<GEOM, F64, MODE>(P, R[c], d.cK, d.rb2, d.sh.C);
+                        any |= __ballot(t[c] >= g);
+                    }
+                    if (__builtin_expect(any != 0, 0)) {  // rare: keep the scan's path straight
+                        crossings(k, q0, nq, p, t);
+                        double tl = t[0];
+#pragma unroll
+                        for (int c = 1; c < NB; ++c)
+                            if (c_last == c) tl = t[c];
+                        const double gn = next_grid(readlane_double(tl, l_last), nob);
+                        if (d.lane == 0) pcl[4 * p + 3] = gn;
+                    }
+                }
+            }
+        }
+    }
+
+    // One fast-path particle: first and last arrival times per pixel (lanes over pixels), the
+    // culling test (LW_CULL), the scan, and the counters, which follow from the two end points.
+    template <int MODE, bool CULL>
+    __device__ __forceinline__ void particle(int64_t k, const bool *pix_in, unsigned long long &c1,
+                                             unsigned long long &c2, unsigned long long &c3)
+    {
+        using SV = ScanVals<GEOM, F64, MODE>;
+        constexpr int NV = SV::N;
+        const int ns = (int)d.sh.n_samples;
+        const double nob = (double)d.sh.n_obs;
+        const double *rk = d.rec + (size_t)k * d.sh.n_samples * Lay::W + SV::OFF;
+        double tau0[kPPL], taul[kPPL];
+        bool lane_ok[kPPL];
+        {
+            const cdptr a = uniform_ptr(rk), b = uniform_ptr(rk + (size_t)(ns - 1) * Lay::W);
+            double v0[NV], v1[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                v0[v] = a[v];
+                v1[v] = b[v];
+            }
+            // this lane's pixel constants, read again per particle (not held through the scan)
+            const double *ptl = d.pt;
+            asm volatile("" : "+s"(ptl));
+#pragma unroll
+            for (int h = 0; h < kPPL; ++h) {
+                const PixC pc = pixc_row(ptl + (size_t)(d.tile * kTilePix + 64 * h + d.lane) * kPT);
+                lane_ok[h] = (okmask[h] >> d.lane) & 1ull;
+                tau0[h] = tau_eval<GEOM, F64, MODE>(pc, v0, d.cK, d.rb2, d.sh.C);
+                taul[h] = tau_eval<GEOM, F64, MODE>(pc, v1, d.cK, d.rb2, d.sh.C);
+            }
+        }
+        bool skip = false;
+        if (CULL) {
+            bool in = false;
+#pragma unroll
+            for (int h = 0; h < kPPL; ++h) in |= lane_ok[h] && grid_count(taul[h], nob) > grid_count(tau0[h], nob);
+            skip = __ballot(in) == 0;
+        }
+        // the counters (taken before the scan, so that the end points are not held through it)
+#pragma unroll
+        for (int h = 0; h < kPPL; ++h) {
+            if (lane_ok[h]) {
+                const int64_t inside = grid_count(taul[h], nob) - grid_count(tau0[h], nob);
+                c3 += (unsigned long long)inside;
+                c2 += (unsigned long long)((int64_t)(floor(taul[h]) - floor(tau0[h])) - inside);
+            } else if (pix_in[h]) {
+                c1 += (unsigned long long)(ns - 1);
+            }
+        }
+        if (!skip && ns >= 2) {
+#pragma unroll
+            for (int h = 0; h < kPPL; ++h) pcl[4 * (64 * h + d.lane) + 3] = lane_ok[h] ? next_grid(tau0[h], nob) : INFINITY;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            scan<MODE>(k, rk);
+        }
+    }
+};
+
+template <typename T, int GEOM, bool CULL>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_scan(
+    const double *__restrict__ r, const double *__restrict__ beta, const double *__restrict__ beta_dot,
+    const double *__restrict__ charge, const double *__restrict__ x_det, const double *__restrict__ rec,
+    const double *__restrict__ pt, const int *__restrict__ pflag, const unsigned long long *__restrict__ rmax2,
+    const double *__restrict__ rbound2, T *__restrict__ E, unsigned long long *__restrict__ diag, DepShape sh)
+{
+    constexpr bool kF64 = sizeof(T) == 8;
+    constexpr int kRec = kF64 ? kModeRec5 : kModeRec3;
+    __shared__ uint2 q_all[kQCap];
+    __shared__ double2 qt_all[kQCap];
+    __shared__ T wc_all[kTilePix * WcLine<T>::P];
+    __shared__ int wcb_all[kTilePix];
+    __shared__ uint32_t want_all[kTilePix];
+    __shared__ int fpix_all[64];
+    __shared__ double pcl_all[4 * (kTilePix + 1)];
+    __shared__ unsigned long long red[4];
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 4) red[threadIdx.x] = 0ull;
+    __syncthreads();
+
+    // block -> (particle group, tile); consecutive groups on one XCD share trajectory lines in L2
+    const int64_t b = blockIdx.x;
+    const int64_t xcd = b & 7, slot = b >> 3;
+    const int64_t grp = (slot / sh.n_tiles) * 8 + xcd;
+    const int64_t tile = slot % sh.n_tiles;
+    const int64_t k0 = grp * sh.parts_per_group;
+    const int64_t k1 = grp < sh.n_groups ? std::min(k0 + sh.parts_per_group, sh.n_particles) : k0;
+
+    ScanWave<T, GEOM> w;
+    Wave<T, GEOM> &d = w.d;
+    bool pix_in[kPPL];
+    double id2 = 0.0;
+    const double Dref = pix_geo(x_det, 0).D;  // the records' pixel distance
+    bool far_off = false;                     // a pixel of this wavefront at another distance
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h) {
+        const int p = 64 * h + lane;
+        const int64_t m = tile * kTilePix + p;
+        pix_in[h] = m < sh.n_pix;
+        // rows past the pass's last pixel are zero padding (not usable)
+        const PixC pc = pixc_row(pt + m * kPT);
+        const bool ok = pix_in[h] && pc.g.ok;
+        w.okmask[h] = __ballot(ok);
+        pcl_all[4 * p] = pc.o;
+        pcl_all[4 * p + 1] = pc.px;
+        pcl_all[4 * p + 2] = pc.py;
+        pcl_all[4 * p + 3] = INFINITY;
+        if (p < 4) pcl_all[4 * kTilePix + p] = p == 3 ? INFINITY : 0.0;
+        if (ok) {
+            id2 = fmax(id2, pc.g.invD * pc.g.invD);
+            far_off |= !(fabs(pc.g.D - Dref) <= kSameDistance * Dref);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) id2 = fmax(id2, __shfl_xor(id2, off));
+    const double invD2max = uniform_double(id2);
+    const bool rec_ok = GEOM == LW_GEOM_EXACT && __ballot(far_off) == 0;
+    {
+        double c[6];
+        if (kF64)
+            tau_poly<5>(0.0, 0.0, 0.0, 0.0, sh.C, Dref, c);
+        else
+            tau_poly<3>(0.0, 0.0, 0.0, 0.0, sh.C, Dref, c);
+        d.cK = c[kF64 ? 5 : 3];
+    }
+    w.pcl = pcl_all;
+    d.r = r;
+    d.beta = beta;
+    d.beta_dot = beta_dot;
+    d.charge = charge;
+    d.x_det = x_det;
+    d.rec = rec;
+    d.pt = pt;
+    d.E = E;
+    d.sh = sh;
+    d.lane = lane;
+    d.tile = tile;
+    d.k0 = k0;
+    d.q = q_all;
+    d.qt = qt_all;
+    d.wc = wc_all;
+    d.wcb = wcb_all;
+    d.want = want_all;
+    d.fpix = fpix_all;
+    d.qh = 0;
+    d.qn = 0;
+    for (int j = lane; j < kTilePix * WcLine<T>::P; j += 64) d.wc[j] = (T)0;
+    for (int p = lane; p < kTilePix; p += 64) {
+        d.wcb[p] = -1;
+        d.want[p] = kWantNone;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+
+    unsigned long long c1 = 0, c2 = 0, c3 = 0;
+    for (int64_t k = k0; k < k1; ++k) {
+        if (pflag[k] != 0) continue;  // careful path: k_careful
+        // series forms where |r|^2 <= 1e-8 |x_m|^2 over the whole trajectory (the max over the
+        // whole trajectory when given, else over the samples of this call), decided per pixel
+        d.rb2 = rbound2 ? rbound2[k] : __longlong_as_double((long long)rmax2[k]);
+        const bool all_ser = GEOM == LW_GEOM_EXACT && d.rb2 * invD2max <= kSeriesBound;
+        if (GEOM == LW_GEOM_FARFIELD)
+            w.template particle<kModeFar, CULL>(k, pix_in, c1, c2, c3);
+        else if (all_ser && rec_ok)
+            w.template particle<kRec, CULL>(k, pix_in, c1, c2, c3);
+        else
+            w.template particle<kModeMixed, CULL>(k, pix_in, c1, c2, c3);
+    }
+    while (d.qn > 0) d.drain(d.qn < 64 ? d.qn : 64);
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h) d.flush_lines(__ballot(d.wcb[lane + 64 * h] >= 0), h);
+
+    // counters: block reduction in LDS, then one global atomic per counter
     if (c1) atomicAdd(&red[1], c1);
     if (c2) atomicAdd(&red[2], c2);
     if (c3) atomicAdd(&red[3], c3);
@@ -918,64 +1149,84 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
     const double C = 1.0 / (kC * gr->dt_obs);
     const int64_t n_chunks_s = (ns + kPrepassChunk - 1) / kPrepassChunk;
     if (n_chunks_s > 65535) return fail(LW_E_SHAPE, "lw_deposit_td: too many samples");
-    for (int64_t p0 = 0; p0 < n_p; p0 += chunk) {
-        const int64_t np = std::min<int64_t>(chunk, n_p - p0);
-        DepShape sh;
-        sh.n_particles = np;
-        sh.n_samples = ns;
-        sh.n_pix = n_pix;
-        sh.n_obs = n_obs;
-        sh.n_tiles = (n_pix + kTilePix - 1) / kTilePix;
-        int64_t groups = std::max<int64_t>(1, (kTargetWaves + sh.n_tiles - 1) / sh.n_tiles);
-        groups = std::max<int64_t>(1, std::min<int64_t>(groups, np));
-        sh.parts_per_group = std::max<int64_t>(1, (np + groups - 1) / groups);
-        sh.n_groups = (np + sh.parts_per_group - 1) / sh.parts_per_group;
-        sh.fmask = fmask;
-        sh.C = C;
-        const int64_t blocks = (sh.n_groups + 7) / 8 * 8 * sh.n_tiles;
-        if (sh.parts_per_group >= (int64_t(1) << (32 - kPixBits)))
-            return fail(LW_E_SHAPE, "lw_deposit_td: too many particles per pixel tile group");
-        if (np > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: too many particles");
-        if (blocks > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: problem too large for one launch");
-        const DepWs w = carve(ws, np);
-        const double *r = t->r + (size_t)p0 * ns * 3, *b = t->beta + (size_t)p0 * ns * 3,
-                     *bd = t->beta_dot + (size_t)p0 * ns * 3;
-        const double *charge = t->charge ? t->charge + p0 : nullptr;
-        const double *rb2 = rbound2 ? rbound2 + p0 : nullptr;
-        const int fill_blocks = (int)std::min<int64_t>((np + 255) / 256, 65536);
-        k_fill<int><<<fill_blocks, 256, 0, s>>>(w.pflag, np);
-        k_fill<unsigned long long><<<fill_blocks, 256, 0, s>>>(w.rmax2, np);
-        const dim3 pgrid((unsigned)np, (unsigned)n_chunks_s);
-        if (geom == LW_GEOM_EXACT)
-            launch_prepass<LW_GEOM_EXACT>(f64, pgrid, s, r, b, bd, gr->x_det, ns, sample0, t->t_start, t->dt, gr->t0,
-                                          gr->dt_obs, C, w);
-        else
-            launch_prepass<LW_GEOM_FARFIELD>(f64, pgrid, s, r, b, bd, gr->x_det, ns, sample0, t->t_start, t->dt,
-                                             gr->t0, gr->dt_obs, C, w);
-        unsigned long long *dg = (unsigned long long *)diag;
-        const dim3 grid((unsigned)blocks), block(kBlockThreads);
-#define LW_DEPOSIT_LAUNCH(T, G, CU)                                                                                   \
-    k_deposit<T, G, CU><<<grid, block, 0, s>>>(r, b, bd, charge, gr->x_det, w.rec, w.pflag, w.rmax2, rb2, (T *)E, dg, \
-                                               sh)
-        // culling is a separate instantiation: the full evaluation carries none of its code
-        hipEvent_t t_start = timing_begin(LW_KERNEL_DEPOSIT, s);
-        if (f64) {
-            if (geom == LW_GEOM_EXACT) {
-                if (cull) LW_DEPOSIT_LAUNCH(double, LW_GEOM_EXACT, true); else LW_DEPOSIT_LAUNCH(double, LW_GEOM_EXACT, false);
-            } else {
-                if (cull) LW_DEPOSIT_LAUNCH(double, LW_GEOM_FARFIELD, true); else LW_DEPOSIT_LAUNCH(double, LW_GEOM_FARFIELD, false);
+    // pixel passes of at most kPixTabMax pixels (the pixel table's share of the workspace); each
+    // pass is a deposit of its own pixels (records take the pass's first pixel as reference)
+    for (int64_t m0 = 0; m0 < n_pix; m0 += kPixTabMax) {
+        const int64_t npx = std::min<int64_t>(kPixTabMax, n_pix - m0);
+        const double *xd = gr->x_det + 3 * m0;
+        void *Ep = f64 ? (void *)((double *)E + (size_t)m0 * 3 * (size_t)n_obs)
+                       : (void *)((float *)E + (size_t)m0 * 3 * (size_t)n_obs);
+        for (int64_t p0 = 0; p0 < n_p; p0 += chunk) {
+            const int64_t np = std::min<int64_t>(chunk, n_p - p0);
+            DepShape sh;
+            sh.n_particles = np;
+            sh.n_samples = ns;
+            sh.n_pix = npx;
+            sh.n_obs = n_obs;
+            sh.n_tiles = (npx + kTilePix - 1) / kTilePix;
+            int64_t groups = std::max<int64_t>(1, (kTargetWaves + sh.n_tiles - 1) / sh.n_tiles);
+            groups = std::max<int64_t>(1, std::min<int64_t>(groups, np));
+            sh.parts_per_group = std::max<int64_t>(1, (np + groups - 1) / groups);
+            sh.n_groups = (np + sh.parts_per_group - 1) / sh.parts_per_group;
+            sh.fmask = fmask;
+            sh.C = C;
+            const int64_t blocks = (sh.n_groups + 7) / 8 * 8 * sh.n_tiles;
+            if (sh.parts_per_group >= (int64_t(1) << (32 - kPixBits)))
+                return fail(LW_E_SHAPE, "lw_deposit_td: too many particles per pixel tile group");
+            if (np > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: too many particles");
+            if (blocks > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: problem too large for one launch");
+            const DepWs w = carve(ws, np);
+            if (p0 == 0) {
+                const int64_t rows = sh.n_tiles * kTilePix;  // <= kPixTabMax
+                k_pixtab<<<(unsigned)((rows + 255) / 256), 256, 0, s>>>(xd, npx, rows, C, w.pt);
             }
-        } else {
-            if (geom == LW_GEOM_EXACT) {
-                if (cull) LW_DEPOSIT_LAUNCH(float, LW_GEOM_EXACT, true); else LW_DEPOSIT_LAUNCH(float, LW_GEOM_EXACT, false);
+            const double *r = t->r + (size_t)p0 * ns * 3, *b = t->beta + (size_t)p0 * ns * 3,
+                         *bd = t->beta_dot + (size_t)p0 * ns * 3;
+            const double *charge = t->charge ? t->charge + p0 : nullptr;
+            const double *rb2 = rbound2 ? rbound2 + p0 : nullptr;
+            const int fill_blocks = (int)std::min<int64_t>((np + 255) / 256, 65536);
+            k_fill<int><<<fill_blocks, 256, 0, s>>>(w.pflag, np);
+            k_fill<unsigned long long><<<fill_blocks, 256, 0, s>>>(w.rmax2, np);
+            const dim3 pgrid((unsigned)np, (unsigned)n_chunks_s);
+            if (geom == LW_GEOM_EXACT)
+                launch_prepass<LW_GEOM_EXACT>(f64, pgrid, s, r, b, bd, xd, ns, sample0, t->t_start, t->dt, gr->t0,
+                                              gr->dt_obs, C, w);
+            else
+                launch_prepass<LW_GEOM_FARFIELD>(f64, pgrid, s, r, b, bd, xd, ns, sample0, t->t_start, t->dt, gr->t0,
+                                                 gr->dt_obs, C, w);
+            unsigned long long *dg = (unsigned long long *)diag;
+            const dim3 grid((unsigned)blocks), block(kBlockThreads);
+            // the fast path (timed as the deposit kernel), then the careful path; culling is a
+            // separate instantiation of the fast path, so the full evaluation carries none of its code
+#define LW_SCAN_LAUNCH(T, G, CU) \
+    k_scan<T, G, CU><<<grid, block, 0, s>>>(r, b, bd, charge, xd, w.rec, w.pt, w.pflag, w.rmax2, rb2, (T *)Ep, dg, sh)
+#define LW_CAREFUL_LAUNCH(T, G) \
+    k_careful<T, G><<<grid, block, 0, s>>>(r, b, bd, charge, xd, w.rec, w.pt, w.pflag, w.rmax2, rb2, (T *)Ep, dg, sh)
+            hipEvent_t ev = timing_begin(LW_KERNEL_DEPOSIT, s);
+            if (f64) {
+                if (geom == LW_GEOM_EXACT) {
+                    if (cull) LW_SCAN_LAUNCH(double, LW_GEOM_EXACT, true); else LW_SCAN_LAUNCH(double, LW_GEOM_EXACT, false);
+                } else {
+                    if (cull) LW_SCAN_LAUNCH(double, LW_GEOM_FARFIELD, true); else LW_SCAN_LAUNCH(double, LW_GEOM_FARFIELD, false);
+                }
             } else {
-                if (cull) LW_DEPOSIT_LAUNCH(float, LW_GEOM_FARFIELD, true); else LW_DEPOSIT_LAUNCH(float, LW_GEOM_FARFIELD, false);
+                if (geom == LW_GEOM_EXACT) {
+                    if (cull) LW_SCAN_LAUNCH(float, LW_GEOM_EXACT, true); else LW_SCAN_LAUNCH(float, LW_GEOM_EXACT, false);
+                } else {
+                    if (cull) LW_SCAN_LAUNCH(float, LW_GEOM_FARFIELD, true); else LW_SCAN_LAUNCH(float, LW_GEOM_FARFIELD, false);
+                }
             }
+            timing_end(LW_KERNEL_DEPOSIT, ev, s);
+            if (f64) {
+                if (geom == LW_GEOM_EXACT) LW_CAREFUL_LAUNCH(double, LW_GEOM_EXACT); else LW_CAREFUL_LAUNCH(double, LW_GEOM_FARFIELD);
+            } else {
+                if (geom == LW_GEOM_EXACT) LW_CAREFUL_LAUNCH(float, LW_GEOM_EXACT); else LW_CAREFUL_LAUNCH(float, LW_GEOM_FARFIELD);
+            }
+#undef LW_SCAN_LAUNCH
+#undef LW_CAREFUL_LAUNCH
+            const lw_status st = check_launch("lw_deposit_td");
+            if (st != LW_OK) return st;
         }
-#undef LW_DEPOSIT_LAUNCH
-        timing_end(LW_KERNEL_DEPOSIT, t_start, s);
-        const lw_status st = check_launch("lw_deposit_td");
-        if (st != LW_OK) return st;
     }
     return LW_OK;
 }
