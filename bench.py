@@ -67,12 +67,12 @@ DENSE_F32_FLOPS, DENSE_F64_FLOPS = 68, 6
 FD_TERM_FLOPS = 18
 DEPOSIT_SOURCES = ("paper_2206_03015_amd/csrc/deposit.hip", "paper_2206_03015_amd/csrc/lw_internal.h")
 SUMMARIES = {
-    "precision": {"traffic": "profiles/k_deposit_precision_mixed_hbm_traffic.md",
-                  "valu": "profiles/k_deposit_precision_mixed_valu.md",
+    "precision": {"traffic": "profiles/k_scan_precision_mixed_hbm_traffic.md",
+                  "valu": "profiles/k_scan_precision_mixed_valu.md",
                   "types": "profiles/valu_fp32_fp64_precision.md"},
-    "bunch": {"traffic": "profiles/k_deposit_bunch_mixed_exact_hbm_traffic.md",
-              "valu": "profiles/k_deposit_bunch_mixed_exact_valu.md",
-              "types": "profiles/valu_fp32_fp64_bunch_exact.md"},
+    "bunch": {"traffic": "profiles/k_scan_bunch_mixed_exact_hbm_traffic.md",
+              "valu": "profiles/k_scan_bunch_mixed_exact_valu.md",
+              "types": "profiles/valu_fp32_fp64_bunch.md"},
 }
 
 
@@ -133,9 +133,9 @@ def main():
         n = int(args.copy_calibration_gib * (1 << 30)) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)  # one plain elementwise copy kernel: n*4 bytes read, n*4 written
+        torch.mul(src, 1.0, out=dst)  # a plain elementwise copy (torch runs it as kernels of <= 2 GiB): n*4 bytes read, n*4 written
         torch.cuda.synchronize()
-        log(f"[bench] copy calibration: {n * 4} bytes read and written by one elementwise kernel")
+        log(f"[bench] copy calibration: {n * 4} bytes read and written by an elementwise copy")
         del src, dst
     rec = headline(torch, dev, args)
     print(json.dumps(rec), flush=True)
@@ -153,7 +153,7 @@ def deposit_roofline(triples, hits, kernel_s, launches, summaries=None, profiled
     peak = work / t_roof / 1e12
     achieved = work / kernel_s / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None, "kernel": "k_deposit", "launches": launches, "kernel_ms": kernel_s * 1e3,
+            "traffic": None, "kernel": "k_scan", "launches": launches, "kernel_ms": kernel_s * 1e3,
             "work": {"f64_flops": f64, "f32_flops": f32, "triples": triples, "deposited_points": hits,
                      "f64_flops_per_triple": TRIPLE_F64_FLOPS, "f32_flops_per_deposited_point": HIT_F32_FLOPS},
             "roofline_ms": t_roof * 1e3}

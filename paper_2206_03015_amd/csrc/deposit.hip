@@ -70,6 +70,9 @@ constexpr int kLongRun = 8;
 // wavefronts per launch to aim for (particle groups x pixel tiles): ~26 rounds of the 3072
 // resident wavefronts (12 per CU), so that the last, partly filled round is a small share
 constexpr int kTargetWaves = 98304;
+// at most this many particles per group: the wavefronts of a group (one per pixel tile, started
+// together on one XCD) read the same records, and stay close enough to share them in L2
+constexpr int kMaxPartsPerGroup = 4;
 // (|r|/|x|)^2 up to which the series forms of the exact-geometry arrival time are used
 constexpr double kSeriesBound = 1e-8;
 // pixels whose |x_m| is within this relative distance of the records' distance use the records
@@ -1165,6 +1168,7 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
             sh.n_obs = n_obs;
             sh.n_tiles = (npx + kTilePix - 1) / kTilePix;
             int64_t groups = std::max<int64_t>(1, (kTargetWaves + sh.n_tiles - 1) / sh.n_tiles);
+            groups = std::max<int64_t>(groups, (np + kMaxPartsPerGroup - 1) / kMaxPartsPerGroup);
             groups = std::max<int64_t>(1, std::min<int64_t>(groups, np));
             sh.parts_per_group = std::max<int64_t>(1, (np + groups - 1) / groups);
             sh.n_groups = (np + sh.parts_per_group - 1) / sh.parts_per_group;
