@@ -65,6 +65,11 @@ DENSE_F32_FLOPS, DENSE_F64_FLOPS = 68, 6
 # Direct FD: ~18 FP32 flops per (particle, sample, pixel, frequency) term (phase, sin/cos,
 # three complex multiply-accumulates)
 FD_TERM_FLOPS = 18
+# Deposit adjoint (all FP64): the arrival time of every triple (6 flops, as in the forward) and for
+# every deposited grid point, at the interval's two ends, the field (68 flops) and its
+# vector-Jacobian product (twice the field's), plus the interpolation's adjoint (~20 flops)
+ADJ_TRIPLE_F64_FLOPS = 6
+ADJ_POINT_F64_FLOPS = 2 * (FIELD_F32_FLOPS + 2 * FIELD_F32_FLOPS) + 20
 DEPOSIT_SOURCES = ("paper_2206_03015_amd/csrc/deposit.hip", "paper_2206_03015_amd/csrc/lw_internal.h")
 SUMMARIES = {
     "precision": {"traffic": "profiles/k_scan_precision_mixed_hbm_traffic.md",
@@ -126,9 +131,6 @@ def main():
     if args.accuracy:
         print(json.dumps(accuracy(torch, dev)), flush=True)
         return 0
-    if args.workload == "large":
-        print(json.dumps(full_size(torch, dev, "large")), flush=True)
-        return 0
     if args.copy_calibration_gib > 0:
         n = int(args.copy_calibration_gib * (1 << 30)) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -137,6 +139,9 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: {n * 4} bytes read and written by an elementwise copy")
         del src, dst
+    if args.workload == "large":
+        print(json.dumps(full_size(torch, dev, "large")), flush=True)
+        return 0
     rec = headline(torch, dev, args)
     print(json.dumps(rec), flush=True)
     return 0
@@ -700,32 +705,49 @@ def full_size_adjoint(torch, dev, W, init):
     wts = torch.as_tensor(inputs.band_weights(W, xc_np), device=dev)
 
     def objective(a0):
-        E, _ = lw.deposit_td_boris(init, W.n_samples, W.t_start, W.dt, a0, L.lam, L.w0, L.n_cycles, xc, W.t0,
-                                   W.dt_obs, W.n_obs, prec="fp64")
+        E, diag = lw.deposit_td_boris(init, W.n_samples, W.t_start, W.dt, a0, L.lam, L.w0, L.n_cycles, xc, W.t0,
+                                      W.dt_obs, W.n_obs, prec="fp64")
         S = lw.spectrum_fft(E, W.dt_obs, "fp64")
-        return E, float(torch.sum(wts * S))
+        return E, float(torch.sum(wts * S)), diag
 
     torch.cuda.synchronize()
     e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     e[0].record()
-    E, J = objective(L.a0)
+    E, J, diag = objective(L.a0)
     e[1].record()
     dE = lw.spectrum_fft_bwd(E, wts, W.dt_obs, "fp64")
+    lw.timing_enable(True)
     e[2].record()
     g_init, g_a0 = lw.deposit_td_bwd_boris(init, W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles, xc,
                                            W.t0, W.dt_obs, W.n_obs, dE)
     e[3].record()
     torch.cuda.synchronize()
+    bwd_ms, bwd_n = lw.timing_read(lw.KERNEL_DEPOSIT_BWD)
+    tan_ms, tan_n = lw.timing_read(lw.KERNEL_BORIS_TANGENT)
+    lw.timing_enable(False)
     dj_da0 = float(torch.sum(g_a0))
+    points = int(diag.cpu()[3])
     del E, dE
     h = 1e-6 * L.a0
-    _, Jp = objective(L.a0 + h)
-    _, Jm = objective(L.a0 - h)
+    _, Jp, _ = objective(L.a0 + h)
+    _, Jm, _ = objective(L.a0 - h)
     fd = (Jp - Jm) / (2 * h)
+    # the sample-gradient kernel on the work it performs (FP64 only)
+    triples = W.n_p * W.n_samples * len(cen)
+    work = ADJ_TRIPLE_F64_FLOPS * triples + ADJ_POINT_F64_FLOPS * points
+    t_roof = work / (PEAK_F64_TFLOPS * 1e12)
+    roof = {"bound": "alu", "kernel": "k_deposit_bwd", "launches": bwd_n, "kernel_ms": bwd_ms,
+            "achieved": work / (bwd_ms / 1e3) / 1e12, "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
+            "frac": t_roof / (bwd_ms / 1e3),
+            "work": {"f64_flops": work, "triples": triples, "deposited_points": points,
+                     "f64_flops_per_triple": ADJ_TRIPLE_F64_FLOPS, "f64_flops_per_deposited_point": ADJ_POINT_F64_FLOPS}}
     rec = {"pixels": int(len(cen)), "J": J, "dJ_da0": dj_da0, "dJ_da0_central_difference": fd,
            "rel_diff": abs(dj_da0 - fd) / abs(fd), "forward_ms": e[0].elapsed_time(e[1]),
            "fft_bwd_ms": e[1].elapsed_time(e[2]), "deposit_boris_bwd_ms": e[2].elapsed_time(e[3]),
-           "grad_init_norm": float(torch.linalg.vector_norm(g_init))}
+           "deposit_bwd_kernel_ms": bwd_ms, "boris_tangent_kernel_ms": tan_ms, "tangent_launches": tan_n,
+           "deposit_bwd_roofline": roof, "grad_init_norm": float(torch.linalg.vector_norm(g_init))}
+    log(f"[large] adjoint kernels: k_deposit_bwd {bwd_ms:.0f} ms in {bwd_n} launches (roofline fraction "
+        f"{roof['frac']:.3f}), k_boris_tangent_span {tan_ms:.0f} ms in {tan_n} launches")
     log(f"[large] adjoint on {len(cen)} pixels: forward {rec['forward_ms']:.0f} ms, FFT adjoint "
         f"{rec['fft_bwd_ms']:.1f} ms, deposit+pusher adjoint {rec['deposit_boris_bwd_ms']:.0f} ms; dJ/da0 "
         f"{dj_da0:.6e} vs central difference {fd:.6e} (rel {rec['rel_diff']:.1e})")

@@ -360,13 +360,19 @@ lw_status lw_direct_fd_bwd(const lw_traj_t *traj, const lw_grid_t *grid, const d
  * was recorded.  lw_timing_read waits for the recorded events (host
  * synchronisation on them), writes the summed elapsed time in milliseconds and
  * the number of launches, and clears them.  which: LW_KERNEL_DEPOSIT (the
- * evaluate-and-deposit kernel of lw_deposit_td, once per call, or once per
- * pushed span for LW_TRAJ_BORIS).  The events are owned by the library (created
+ * fast-path evaluate-and-deposit kernel of lw_deposit_td, once per launch: per
+ * call, per particle chunk of a small workspace, or per pushed span for
+ * LW_TRAJ_BORIS), LW_KERNEL_DEPOSIT_BWD (the sample-gradient kernel of
+ * lw_deposit_td_bwd and of each span of lw_deposit_td_bwd_boris),
+ * LW_KERNEL_BORIS_TANGENT (the pusher's tangent kernel of each span of
+ * lw_deposit_td_bwd_boris).  The events are owned by the library (created
  * on first use, reused).  Returns LW_E_ARG for an unknown `which` or NULL
  * outputs, LW_E_HIP if an event call fails.  Not meant for concurrent use from
  * several host threads.
  */
 #define LW_KERNEL_DEPOSIT 1
+#define LW_KERNEL_DEPOSIT_BWD 2
+#define LW_KERNEL_BORIS_TANGENT 3
 lw_status lw_timing_enable(int on);
 lw_status lw_timing_read(int which, double *total_ms, int64_t *launches);
 

@@ -534,8 +534,10 @@ lw_status launch_boris_bwd_span(const lw_traj_t *t, int64_t s0, int64_t n_span, 
     const LaserDev L = laser_dev(t->laser);
     const int64_t lanes = t->n_particles * kParams;
     const int64_t blocks = (lanes + 63) / 64;
+    hipEvent_t ev = timing_begin(LW_KERNEL_BORIS_TANGENT, s);
     k_boris_tangent_span<<<(unsigned)blocks, 64, 0, s>>>(t->init, t->n_particles, s0, n_span, t->t_start, t->dt, L,
                                                         tstate, g_r, g_beta, g_beta_dot, grad_init, grad_a0);
+    timing_end(LW_KERNEL_BORIS_TANGENT, ev, s);
     return check_launch("lw_deposit_td_bwd_boris (tangent span)");
 }
 

@@ -234,12 +234,14 @@ lw_status launch_deposit_bwd(const lw_traj_t *t, const lw_grid_t *gr, int fmask,
         k_rmax2<<<(unsigned)t->n_particles, 256, 0, s>>>(t->r, t->beta, t->beta_dot, t->n_samples, (double *)ws);
         rbound2 = (const double *)ws;
     }
+    hipEvent_t ev = timing_begin(LW_KERNEL_DEPOSIT_BWD, s);
     if (geom == LW_GEOM_EXACT)
         k_deposit_bwd<LW_GEOM_EXACT><<<(unsigned)blocks, 64 * kWavesPerBlock, 0, s>>>(
             t->r, t->beta, t->beta_dot, t->charge, gr->x_det, dE, rbound2, d_r, d_beta, d_beta_dot, sh);
     else
         k_deposit_bwd<LW_GEOM_FARFIELD><<<(unsigned)blocks, 64 * kWavesPerBlock, 0, s>>>(
             t->r, t->beta, t->beta_dot, t->charge, gr->x_det, dE, rbound2, d_r, d_beta, d_beta_dot, sh);
+    timing_end(LW_KERNEL_DEPOSIT_BWD, ev, s);
     return check_launch("lw_deposit_td_bwd");
 }
 

@@ -175,7 +175,8 @@ lw_status lw_timing_enable(int on)
 
 lw_status lw_timing_read(int which, double *total_ms, int64_t *launches)
 {
-    if (which != LW_KERNEL_DEPOSIT) return fail(LW_E_ARG, "lw_timing_read: unknown kernel %d", which);
+    if (which != LW_KERNEL_DEPOSIT && which != LW_KERNEL_DEPOSIT_BWD && which != LW_KERNEL_BORIS_TANGENT)
+        return fail(LW_E_ARG, "lw_timing_read: unknown kernel %d", which);
     if (!total_ms || !launches) return fail(LW_E_ARG, "lw_timing_read: NULL output");
     std::lock_guard<std::mutex> lk(g_tm);
     double sum = 0.0;

@@ -27,7 +27,7 @@ TRAJ_SAMPLES = 0
 TRAJ_BORIS = 1
 WS_DEPOSIT, WS_FFT, WS_DIRECT_FD, WS_DEPOSIT_BWD, WS_FFT_BWD, WS_DIRECT_FD_BWD = 1, 2, 3, 4, 5, 6
 WS_DEPOSIT_BORIS, WS_DEPOSIT_BWD_BORIS = 7, 8
-KERNEL_DEPOSIT = 1
+KERNEL_DEPOSIT, KERNEL_DEPOSIT_BWD, KERNEL_BORIS_TANGENT = 1, 2, 3
 
 c_d = ctypes.c_double
 c_i64 = ctypes.c_int64
