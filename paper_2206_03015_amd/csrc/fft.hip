@@ -12,13 +12,15 @@
 // Pass B handles rows k1 and N1 - k1 together, which hold X_j and X_{N-j}, and writes
 // S_j for j <= N/2 directly.
 //
-// Forward path: rows are up to 4096 points (FP32) or 2048 (FP64), so N1 = N / N2 is small
-// (64 for N = 2^18) and pass A reads C = 4096/N1 (2048/N1) adjacent columns: rows of
-// 256 bytes.  Sub-transforms run in place in one LDS buffer as Stockham passes of radix 16
-// (FP32) or 8 (FP64) whose butterflies each thread holds in registers between two
-// barriers; twiddles come from two 64-entry tables (W_4096^b and W_64^a).  For N <= N2 pass
-// B alone reads the traces.  Pass B writes the spectrum at a stride of N1 floats; all its
-// blocks of one pixel pair run on one XCD so that those partial lines merge in its L2.
+// Forward path: rows are L = 4096 points (FP32) or 2048 (FP64), so N1 = N / L is small (64 for
+// N = 2^18) and pass A reads C = 4096/N1 (2048/N1) adjacent columns: rows of 256 bytes.
+// Sub-transforms are Stockham passes of radix 16 (FP32) or 8 (FP64), each butterfly held by one
+// thread in registers between two barriers of an LDS exchange; the first pass takes the loaded
+// registers and the last leaves its outputs in registers (k_fwd_cols_fast, k_fwd_rows_fast, all
+// shapes fixed at compile time).  The trace scale dt_obs / sqrt(2 pi) rides on pass A's twiddles.
+// Pass B writes the spectrum at a stride of N1 elements; all its blocks of one pixel pair run on
+// one XCD so that those partial lines merge in its L2.  For N <= L one kernel reads the traces
+// (k_fwd_row_direct), and columns longer than 256 points take the runtime-shaped k_fwd_cols.
 //
 // Adjoint path: N1 = 2^ceil(lg/2), N2 = 2^floor(lg/2), radix-4 Stockham passes between two
 // LDS buffers.
@@ -472,7 +474,7 @@ struct FwdShape {
 // pass A: C adjacent columns of one packed transform of one pixel pair per block
 template <typename T>
 __global__ __launch_bounds__(kThrA) void k_fwd_cols(const T *__restrict__ E, typename C2<T>::type *__restrict__ Y,
-                                                    FwdShape sh)
+                                                    FwdShape sh, T sc)
 {
     using T2 = typename C2<T>::type;
     using Cfg = FwdCfg<T>;
@@ -480,7 +482,7 @@ __global__ __launch_bounds__(kThrA) void k_fwd_cols(const T *__restrict__ E, typ
     __shared__ T2 buf[EL];
     __shared__ T2 tlo[64], thi[64];
     const int tid = threadIdx.x;
-    const int N2 = 1 << sh.lg2, lgC = sh.lgC, C = 1 << lgC;
+    const int lgC = sh.lgC, C = 1 << lgC;
     const int64_t N = (int64_t)1 << sh.lg;
     const int t = blockIdx.y;
     const int64_t pl = blockIdx.z, p = sh.pair0 + pl;
@@ -518,54 +520,37 @@ __global__ __launch_bounds__(kThrA) void k_fwd_cols(const T *__restrict__ E, typ
         } else {
             w = unit_phasor(-(double)q2 * inv_n);
         }
+        w.x *= sc;
+        w.y *= sc;
         Yt[((int64_t)k1 << sh.lg2) + n2] = cmul(buf[idx], w);
     }
 }
 
-// pass B: rows k1 and N1 - k1 of the three packed transforms of one pixel pair per block
-// (from Y, or for N1 = 1 the one row straight from the traces), then S
-template <typename T, bool FROM_E>
-__global__ __launch_bounds__(kThrB) void k_fwd_rows(const typename C2<T>::type *__restrict__ Y,
-                                                    const T *__restrict__ E, T *__restrict__ S, FwdShape sh, T sc)
+// N <= L: the three packed transforms of one pixel pair per block straight from the traces
+// (one row, N1 = 1), then S
+template <typename T>
+__global__ __launch_bounds__(kThrB) void k_fwd_row_direct(const T *__restrict__ E, T *__restrict__ S, FwdShape sh,
+                                                          T sc)
 {
     using T2 = typename C2<T>::type;
     using Cfg = FwdCfg<T>;
     constexpr int PS = Cfg::kPadShift;
-    constexpr int EL = 2 << Cfg::kLgRow;  // two rows
-    constexpr int LPT = EL / kThrB;       // loaded elements per thread
-    constexpr int QPT = LPT / 2;          // outputs per thread (+1 for j = N/2)
+    constexpr int EL = 1 << Cfg::kLgRow;
+    constexpr int LPT = EL / kThrB;  // loaded elements per thread
+    constexpr int QPT = LPT / 2;     // outputs per thread (+1 for j = N/2)
     __shared__ T2 buf[EL + (EL >> PS)];
     __shared__ T2 tlo[64], thi[64];
     const int tid = threadIdx.x;
-    const int lg2 = sh.lg2, N2 = 1 << lg2, N1 = 1 << sh.lg1;
-    const int64_t N = (int64_t)1 << sh.lg, half = N / 2;
-    // block -> (row pair, pixel pair): all row-pair blocks of one pixel pair run on one XCD
-    // (blocks go to the 8 XCDs round robin), so the partial lines of its spectrum, written
-    // at a stride of N1 floats, merge in that XCD's L2
-    int rp;
-    int64_t pl;
-    if (FROM_E) {
-        rp = 0;
-        pl = blockIdx.y;
-    } else {
-        const int64_t b = blockIdx.x, xcd = b & 7, slot = b >> 3;
-        const int nrp = N1 / 2 + 1;
-        rp = (int)(slot % nrp);
-        pl = (slot / nrp) * 8 + xcd;
-        if (pl >= sh.nbatch) return;  // padding block (whole block)
-    }
-    const int64_t p = sh.pair0 + pl;
+    const int lg = sh.lg;
+    const int64_t N = (int64_t)1 << lg, half = N / 2;
+    const int64_t p = sh.pair0 + blockIdx.y;
     const int64_t m = 2 * p, m1 = 2 * p + 1;
     const bool has1 = m1 < sh.n_pix;
-    const int ka = rp, kb = (N1 - rp) & (N1 - 1);
-    const int nrows = ka == kb ? 1 : 2;
-    const LayRows<PS> lay{lg2};
+    const LayRows<PS> lay{lg};
     build_tables(tlo, thi, tid);
-    // Outputs: per row the N2/2 columns k2 < N2/2 (j = kr + N1 k2 < N/2), plus j = N/2
-    // (row k1 = 0, column N2/2) in the block of row 0, taken by thread 0 as output QPT.
-    const int lgh = lg2 - 1;
-    const int nout = nrows << lgh;
-    const bool extra = ka == 0 && tid == 0;
+    // outputs k < N/2, plus k = N/2 taken by thread 0 as output QPT
+    const int nout = 1 << (lg - 1);
+    const bool extra = tid == 0;
     T accm[QPT + 1], acc1[QPT + 1];
 #pragma unroll
     for (int i = 0; i <= QPT; ++i) accm[i] = acc1[i] = (T)0;
@@ -576,57 +561,31 @@ __global__ __launch_bounds__(kThrB) void k_fwd_rows(const typename C2<T>::type *
         // every per-lane address of the loop body in registers across the three transforms
         int ltid = tid;
         asm volatile("" : "+v"(ltid));
-        if constexpr (FROM_E) {
-            const T *re, *im;
-            pair_pointers(E, sh.n_pix, p, t, N, re, im);
+        const T *re, *im;
+        pair_pointers(E, sh.n_pix, p, t, N, re, im);
 #pragma unroll
-            for (int i = 0; i < LPT; ++i) {
-                const int q = ltid + i * kThrB;
-                if (q >= N2) continue;
-                T2 v;
-                v.x = re[q] * sc;
-                v.y = im ? im[q] * sc : (T)0;
-                buf[lay.addr(0, q)] = v;
-            }
-        } else {
-            const T2 *Yt = Y + (pl * 3 + t) * N;
-#pragma unroll
-            for (int i = 0; i < LPT; ++i) {
-                const int q = ltid + i * kThrB;
-                const int row = q >> lg2, k2 = q & (N2 - 1);
-                if (row >= nrows) continue;
-                T2 v = Yt[((int64_t)(row ? kb : ka) << lg2) + k2];
-                v.x *= sc;
-                v.y *= sc;
-                buf[lay.addr(row, k2)] = v;
-            }
+        for (int i = 0; i < LPT; ++i) {
+            const int q = ltid + i * kThrB;
+            if (q >= N) continue;
+            T2 v;
+            v.x = re[q] * sc;
+            v.y = im ? im[q] * sc : (T)0;
+            buf[lay.addr(0, q)] = v;
         }
         __syncthreads();
-        fft_inplace<Cfg::kET, Cfg::kLgRadix>(buf, lay, lg2, nrows, tlo, thi, ltid, kThrB);
+        fft_inplace<Cfg::kET, Cfg::kLgRadix>(buf, lay, lg, 1, tlo, thi, ltid, kThrB);
 #pragma unroll
         for (int i = 0; i <= QPT; ++i) {
-            int row, k2;
+            int k;
             if (i < QPT) {
-                const int o = ltid + i * kThrB;
-                if (o >= nout) continue;
-                row = o >> lgh;
-                k2 = o & ((1 << lgh) - 1);
+                k = ltid + i * kThrB;
+                if (k >= nout) continue;
             } else {
                 if (!extra) continue;
-                row = 0;
-                k2 = N2 >> 1;
+                k = (int)half;
             }
-            const int kr = row ? kb : ka;
-            // X_{N-j}: row N1 - kr (column N2 - 1 - k2), or row 0 itself (column -k2)
-            int mrow, mk2;
-            if (kr == 0) {
-                mrow = row;
-                mk2 = (N2 - k2) & (N2 - 1);
-            } else {
-                mrow = (N1 - kr == ka) ? 0 : 1;
-                mk2 = N2 - 1 - k2;
-            }
-            const T2 zj = buf[lay.addr(row, k2)], zm = buf[lay.addr(mrow, mk2)];
+            // X_{N-k} at (N - k) mod N
+            const T2 zj = buf[lay.addr(0, k)], zm = buf[lay.addr(0, (int)((N - k) & (N - 1)))];
             if (t < 2) {
                 const T v = (zj.x * zj.x + zj.y * zj.y + zm.x * zm.x + zm.y * zm.y) * (T)0.5;
                 if (t == 0)
@@ -644,20 +603,371 @@ __global__ __launch_bounds__(kThrB) void k_fwd_rows(const typename C2<T>::type *
     const int64_t ldS = half + 1;
 #pragma unroll
     for (int i = 0; i <= QPT; ++i) {
-        int row, k2;
+        int k;
         if (i < QPT) {
-            const int o = tid + i * kThrB;
-            if (o >= nout) continue;
-            row = o >> lgh;
-            k2 = o & ((1 << lgh) - 1);
+            k = tid + i * kThrB;
+            if (k >= nout) continue;
         } else {
             if (!extra) continue;
-            row = 0;
-            k2 = N2 >> 1;
+            k = (int)half;
         }
-        const int64_t j = (row ? kb : ka) + ((int64_t)k2 << sh.lg1);
-        S[m * ldS + j] = accm[i];
-        if (has1) S[m1 * ldS + j] = acc1[i];
+        S[m * ldS + k] = accm[i];
+        if (has1) S[m1 * ldS + k] = acc1[i];
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Forward path for N > L (L = 2^kLgL row points), every index fixed at compile time.
+//
+// Pass A (k_fwd_cols_fast<T, LG1>): thread (column c, group g < TPC = N1/ET) loads the ET
+// column elements g + TPC m.  The first radix pass works on those registers, the middle passes
+// go through LDS, and the last pass (radix ET, Ns = TPC) leaves the outputs k1 = g + TPC r in
+// registers, where sc W_N^{n2 k1} = sc W_N^{n2 g} (W_N^{n2 TPC})^r is applied before the store.
+//
+// Pass B (k_fwd_rows_fast<T>): a block of 256 threads per row pair (k1, N1 - k1) of a pixel
+// pair; the rows of the three packed transforms pass through one LDS row buffer in turn, the
+// next row's loads in flight meanwhile.  Thread u loads elements u + 256 m (m < R) of a row;
+// passes: radix R (Ns = 1), the remainder radix 2^(lg L mod lg R) if any, radix R up to the
+// last one (Ns = L/R = 256), which yields outputs u + 256 m of row k1 and rho + 256 m of row
+// N1 - k1 with rho = 255 - u: the partners N2 - 1 - e of its own outputs e, so X_{N-j} of each
+// S_j it writes is in its registers.  Row 0 pairs with itself at (N2 - e) mod N2 (rho = -u mod
+// 256, and for u = 0 a last pass that yields the outputs rotated by one), row N1/2 with itself
+// at N2 - 1 - e.
+//
+// LDS addresses are one base per pass and thread plus compile-time offsets: the row buffer has
+// one pad element per R elements (R = its period), and every stride a pass steps by is a
+// multiple of R or stays inside one period.
+template <typename T>
+struct FastCfg;
+// kRowWaves: waves per SIMD pass B is compiled for (its registers: a row of the prefetch, one
+// row's outputs held while the partner row runs, and the accumulators of 2 R + 2 outputs).
+// Radix 8 with 512 threads for FP32 measured slower (36.8 against 36.0 ms on 16384 traces of
+// 2^18 points): more passes and LDS traffic for the doubled occupancy.
+template <>
+struct FastCfg<float> {
+    static constexpr int kLgL = 12, kLgR = 4, kRowThreads = 1 << (kLgL - kLgR), kRowWaves = 2;
+};
+template <>
+struct FastCfg<double> {
+    static constexpr int kLgL = 11, kLgR = 3, kRowThreads = 1 << (kLgL - kLgR), kRowWaves = 2;
+};
+// L / R = 256 threads in both: one radix-R butterfly each per row in the first and last passes.
+// In-pass twiddle bases W_{Ns Rp}^k (k < Ns) are entries q < L/Rp of a table of W_L^q.
+// Pass B's table covers its smallest radix (the remainder pass), pass A's radix ET.
+template <typename T>
+constexpr int tab_entries_rows()
+{
+    constexpr int rem = FastCfg<T>::kLgL % FastCfg<T>::kLgR;
+    return 1 << (FastCfg<T>::kLgL - (rem ? rem : FastCfg<T>::kLgR));
+}
+template <typename T>
+constexpr int tab_entries_cols()
+{
+    return 1 << (FastCfg<T>::kLgL - FwdCfg<T>::kLgRadix);
+}
+
+template <int PS>
+struct AtRow {  // element e of the row buffer, one pad element every 2^PS
+    __device__ __forceinline__ int operator()(int e) const { return e + (e >> PS); }
+    static constexpr int far(int d) { return d + (d >> PS); }  // offset of +d, d a multiple of 2^PS
+    static constexpr int near(int d) { return d; }             // offset of +d inside one period
+};
+template <int LGC>
+struct AtCol {  // element e of column c among 2^LGC interleaved columns
+    int c;
+    __device__ __forceinline__ int operator()(int e) const { return (e << LGC) + c; }
+    static constexpr int far(int d) { return d << LGC; }
+    static constexpr int near(int d) { return d << LGC; }
+};
+
+// Twiddle table slot of entry q (one pad slot per 16 entries: the strided reads tab[16 k] of a
+// middle pass fall in distinct banks)
+__device__ __forceinline__ int tabi(int q) { return q + (q >> 4); }
+constexpr int tab_slots(int entries) { return entries + entries / 16; }
+
+// w[r] = w1^r for 1 <= r < RP, each a product chain of depth at most lg RP
+template <int RP, typename T2>
+__device__ __forceinline__ void powers(T2 w1, T2 *w)
+{
+    w[1] = w1;
+#pragma unroll
+    for (int r = 2; r < RP; ++r) {
+        const int hb = 1 << (31 - __builtin_clz(r));
+        w[r] = hb == r ? cmul(w[r / 2], w[r / 2]) : cmul(w[hb], w[r - hb]);
+    }
+}
+
+// First Stockham pass (Ns = 1, no twiddles) from registers: the thread's butterflies are
+// j = j0 + JS s (s < NB), and X[s + NB r] holds element j + r (sequence length / RP).
+// The RP outputs of a butterfly are adjacent (inside one pad period of the row layout).
+template <int RP, int NB, int JS, typename T2, typename At>
+__device__ __forceinline__ void first_pass(const T2 *X, T2 *buf, const At &at, int j0)
+{
+    T2 *pw = buf + at(j0 * RP);
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+        T2 v[RP];
+#pragma unroll
+        for (int r = 0; r < RP; ++r) v[r] = X[s + NB * r];
+        dftR<RP>(v);
+#pragma unroll
+        for (int r = 0; r < RP; ++r) pw[At::far(JS * s * RP) + At::near(r)] = v[r];
+    }
+}
+
+// One middle Stockham pass of radix RP = 2^LGRP at Ns = 2^LGNS over 2^LGN points: butterfly j
+// reads e = j + r 2^LGN/RP, multiplies by W_{Ns RP}^{r k} (k = j mod Ns; W^k = tab entry
+// k 2^(LGTAB - LGNS - LGRP)), transforms and writes (j - k) RP + k + r Ns.  The thread takes
+// butterflies j0 + JS s, s < NB (JS a multiple of Ns).
+template <int LGRP, int LGN, int LGNS, int NB, int JS, int LGTAB, typename T2, typename At>
+__device__ __forceinline__ void mid_pass(T2 *buf, const At &at, int j0, const T2 *tab)
+{
+    constexpr int RP = 1 << LGRP, M = (1 << LGN) / RP, NS = 1 << LGNS;
+    T2 v[NB][RP];
+    const T2 *pr = buf + at(j0);
+#pragma unroll
+    for (int s = 0; s < NB; ++s)
+#pragma unroll
+        for (int r = 0; r < RP; ++r) v[s][r] = pr[At::far(JS * s + r * M)];
+    __syncthreads();
+    const int k = j0 & (NS - 1);
+    T2 w[RP];
+    if constexpr (LGNS > 0) powers<RP>(tab[tabi(k << (LGTAB - LGNS - LGRP))], w);
+    T2 *pw = buf + at((j0 - k) * RP + k);
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+        if constexpr (LGNS > 0) {
+#pragma unroll
+            for (int r = 1; r < RP; ++r) v[s][r] = cmul(v[s][r], w[r]);
+        }
+        dftR<RP>(v[s]);
+#pragma unroll
+        for (int r = 0; r < RP; ++r) pw[At::far(JS * s * RP + r * NS)] = v[s][r];
+    }
+    __syncthreads();
+}
+
+// Middle passes of radix 2^LGRP from Ns = 2^LGNS up to (not including) 2^LGEND, one butterfly
+// j per thread.
+template <int LGRP, int LGN, int LGNS, int LGEND, int LGTAB, typename T2, typename At>
+__device__ __forceinline__ void mid_passes(T2 *buf, const At &at, int j, const T2 *tab)
+{
+    if constexpr (LGNS < LGEND) {
+        mid_pass<LGRP, LGN, LGNS, 1, 1, LGTAB>(buf, at, j, tab);
+        mid_passes<LGRP, LGN, LGNS + LGRP, LGEND, LGTAB>(buf, at, j, tab);
+    }
+}
+
+// Last Stockham pass (Ns = 2^LGN / RP butterflies, k = j) into registers: out[r] = X[j + Ns r]
+// with w1 = W_{2^LGN}^j.  (w1 = W_{2^LGN}^j W_RP instead gives out[r] = X[j + Ns ((r + 1) mod RP)].)
+template <int LGRP, int LGN, typename T2, typename At>
+__device__ __forceinline__ void last_pass_w(const T2 *buf, const At &at, int j, T2 w1, T2 *out)
+{
+    constexpr int RP = 1 << LGRP, NS = (1 << LGN) / RP;
+    const T2 *pr = buf + at(j);
+#pragma unroll
+    for (int r = 0; r < RP; ++r) out[r] = pr[At::far(r * NS)];
+    T2 w[RP];
+    powers<RP>(w1, w);
+#pragma unroll
+    for (int r = 1; r < RP; ++r) out[r] = cmul(out[r], w[r]);
+    dftR<RP>(out);
+}
+template <int LGRP, int LGN, int LGTAB, typename T2, typename At>
+__device__ __forceinline__ void last_pass(const T2 *buf, const At &at, int j, const T2 *tab, T2 *out)
+{
+    constexpr int RP = 1 << LGRP, NS = (1 << LGN) / RP;
+    if constexpr (NS > 1) {
+        last_pass_w<LGRP, LGN>(buf, at, j, tab[tabi(j << (LGTAB - LGN))], out);
+    } else {
+        const T2 *pr = buf + at(j);
+#pragma unroll
+        for (int r = 0; r < RP; ++r) out[r] = pr[At::far(r * NS)];
+        dftR<RP>(out);
+    }
+}
+
+// exp(-2 pi i q / N) for 0 <= q (reduced mod N = 2^lg), argument exact in the working type
+template <typename T2>
+__device__ __forceinline__ T2 phasor_mod(int64_t q, int64_t N, double inv_n);
+template <>
+__device__ __forceinline__ float2 phasor_mod<float2>(int64_t q, int64_t N, double inv_n)
+{
+    int64_t q2 = 2 * (q & (N - 1));
+    if (q2 > N) q2 -= 2 * N;
+    return unit_phasor_f(-(float)q2 * (float)inv_n);
+}
+template <>
+__device__ __forceinline__ double2 phasor_mod<double2>(int64_t q, int64_t N, double inv_n)
+{
+    int64_t q2 = 2 * (q & (N - 1));
+    if (q2 > N) q2 -= 2 * N;
+    return unit_phasor(-(double)q2 * inv_n);
+}
+
+// pass A: C = 2^LGC adjacent columns (of N1 = 2^LG1 points) of one packed transform of one pixel
+// pair per block
+template <typename T, int LG1>
+__global__ __launch_bounds__(256) void k_fwd_cols_fast(const T *__restrict__ E, typename C2<T>::type *__restrict__ Y,
+                                                       FwdShape sh, T sc)
+{
+    using T2 = typename C2<T>::type;
+    constexpr int LGET = FwdCfg<T>::kLgRadix, ET = 1 << LGET;  // elements per thread
+    constexpr int LGTAB = FastCfg<T>::kLgL;
+    constexpr int LGC = 8 + LGET - LG1, C = 1 << LGC, TPC = 1 << (LG1 - LGET);
+    static_assert(LG1 >= LGET && LGC >= 0, "columns of ET to 256 ET points");
+    constexpr int LGR0 = LG1 % LGET ? LG1 % LGET : LGET, NB0 = ET >> LGR0;
+    constexpr bool kLds = LG1 > LGET;
+    __shared__ T2 buf[kLds ? (C << LG1) : 1];
+    __shared__ T2 tab[tab_slots(tab_entries_cols<T>())];
+    const int tid = threadIdx.x, c = tid & (C - 1), g = tid >> LGC;
+    const int t = blockIdx.y;
+    const int64_t pl = blockIdx.z, p = sh.pair0 + pl;
+    const int64_t N = (int64_t)1 << sh.lg;
+    const T *re, *im;
+    pair_pointers(E, sh.n_pix, p, t, N, re, im);
+    if (!re) return;  // transform of a missing pixel: pass B skips it too
+    const int n2 = blockIdx.x * C + c;
+    if constexpr (kLds) {
+        for (int q = tid; q < tab_entries_cols<T>(); q += 256) tab[tabi(q)] = twiddle<T2>(q, 1 << LGTAB);
+    }
+    T2 X[ET];
+#pragma unroll
+    for (int m = 0; m < ET; ++m) {
+        const int n = ((g + TPC * m) << sh.lg2) + n2;
+        X[m].x = re[n];
+        X[m].y = im ? im[n] : (T)0;
+    }
+    T2 O[ET];
+    if constexpr (!kLds) {
+#pragma unroll
+        for (int r = 0; r < ET; ++r) O[r] = X[r];
+        dftR<ET>(O);
+    } else {
+        const AtCol<LGC> at{c};
+        first_pass<1 << LGR0, NB0, TPC>(X, buf, at, g);
+        __syncthreads();
+        mid_passes<LGET, LG1, LGR0, LG1 - LGET, LGTAB>(buf, at, g, tab);
+        last_pass<LGET, LG1, LGTAB>(buf, at, g, tab, O);
+    }
+    // sc W_N^{n2 k1} for k1 = g + TPC r: bw (W_N^{n2 TPC})^r, the power a product chain of depth
+    // <= LGET, bw = sc W_N^{n2 g} (the trace scale sc rides on the twiddle)
+    const double inv_n = ldexp(1.0, -sh.lg);
+    T2 bw = phasor_mod<T2>((int64_t)n2 * g, N, inv_n);
+    bw.x *= sc;
+    bw.y *= sc;
+    T2 sp[ET];
+    powers<ET>(phasor_mod<T2>((int64_t)n2 * TPC, N, inv_n), sp);
+    T2 *Yt = Y + (pl * 3 + t) * N;
+    Yt[(g << sh.lg2) + n2] = cmul(O[0], bw);
+#pragma unroll
+    for (int r = 1; r < ET; ++r) Yt[((g + TPC * r) << sh.lg2) + n2] = cmul(O[r], cmul(bw, sp[r]));
+}
+
+// pass B: row pair (k1, N1 - k1) of the three packed transforms of one pixel pair per block, then S
+template <typename T>
+__global__ __launch_bounds__(FastCfg<T>::kRowThreads) __attribute__((amdgpu_waves_per_eu(FastCfg<T>::kRowWaves))) void k_fwd_rows_fast(
+    const typename C2<T>::type *__restrict__ Y, T *__restrict__ S, FwdShape sh, T scale)
+{
+    using T2 = typename C2<T>::type;
+    using Cfg = FastCfg<T>;
+    constexpr int LGL = Cfg::kLgL, L = 1 << LGL, LGR = Cfg::kLgR, R = 1 << LGR, H = R / 2;
+    constexpr int REM = LGL % LGR;  // remainder pass radix 2^REM (none if 0)
+    constexpr int NT = L / R;  // threads: one butterfly each in the first and last passes
+    static_assert(NT == Cfg::kRowThreads, "block size");
+    __shared__ T2 buf[L + L / R];
+    __shared__ T2 tab[tab_slots(tab_entries_rows<T>())];
+    const int tid = threadIdx.x;
+    const int N1 = 1 << sh.lg1;
+    const int64_t N = (int64_t)1 << sh.lg, ldS = N / 2 + 1;
+    // block -> (row pair, pixel pair): all row-pair blocks of one pixel pair run on one XCD
+    // (blocks go to the 8 XCDs round robin), so the partial lines of its spectrum, written at a
+    // stride of N1 elements, merge in that XCD's L2
+    const int64_t b = blockIdx.x, xcd = b & 7, slot = b >> 3;
+    const int nrp = N1 / 2 + 1;
+    const int rp = (int)(slot % nrp);
+    const int64_t pl = (slot / nrp) * 8 + xcd;
+    if (pl >= sh.nbatch) return;  // padding block (whole block)
+    const int64_t p = sh.pair0 + pl, m0 = 2 * p, m1 = m0 + 1;
+    const bool has1 = m1 < sh.n_pix;
+    const int ka = rp, kb = (N1 - rp) & (N1 - 1);
+    const bool two = ka != kb, row0 = ka == 0;
+    const int rho = row0 ? ((NT - tid) & (NT - 1)) : NT - 1 - tid;
+    for (int q = tid; q < tab_entries_rows<T>(); q += NT) tab[tabi(q)] = twiddle<T2>(q, L);
+    __syncthreads();
+    const T2 wa = tab[tabi(tid)], wb = row0 && tid == 0 ? twiddle<T2>(1, R) : tab[tabi(rho)];
+    const AtRow<LGR> at;
+    // accm/acc1: [0, H) outputs tid + NT q of row ka, [H] j = N/2 (row 0, thread 0),
+    // (H, 2H] outputs rho + NT q of row kb; pixel m0 / m1
+    T accm[R + 1], acc1[R + 1];
+#pragma unroll
+    for (int q = 0; q <= R; ++q) accm[q] = acc1[q] = (T)0;
+    // rows in order: (t, ka) and, with two rows, (t, kb) for t = 0, 1 (second pixel only), 2;
+    // each row's loads are issued while the previous row runs through the buffer
+    const int nt = has1 ? 3 : 2;
+    auto row_ptr = [&](int tt, bool second) {  // the row (uniform), indexed by 32-bit offsets
+        const int t = (!has1 && tt == 1) ? 2 : tt;
+        return Y + (pl * 3 + t) * N + (int64_t)(second ? kb : ka) * L;
+    };
+    T2 X[R];
+    auto load_row = [&](const T2 *src) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) X[m] = src[tid + NT * m];
+    };
+    auto row_passes = [&](const T2 *next) {  // next: the row to load meanwhile, or null
+        __syncthreads();  // the previous row's last pass has read the buffer
+        first_pass<R, 1, 1>(X, buf, at, tid);
+        if (next) load_row(next);
+        __syncthreads();
+        if constexpr (REM > 0) mid_pass<REM, LGL, LGR, (L >> REM) / NT, NT, LGL>(buf, at, tid, tab);
+        mid_passes<LGR, LGL, LGR + REM, LGL - LGR, LGL>(buf, at, tid, tab);
+    };
+    load_row(row_ptr(0, false));
+    for (int tt = 0; tt < nt; ++tt) {
+        const int t = (!has1 && tt == 1) ? 2 : tt;
+        const T2 *after = tt + 1 < nt ? row_ptr(tt + 1, false) : nullptr;
+        T2 A[R], B[R];
+        row_passes(two ? row_ptr(tt, true) : after);
+        last_pass_w<LGR, LGL>(buf, at, tid, wa, A);
+        if (two) row_passes(after);
+        // row 0's thread 0 pairs element NT q with NT (R - q) mod L: B[i] = X[NT ((i + 1) mod R)]
+        last_pass_w<LGR, LGL>(buf, at, rho, wb, B);
+        // t < 2: S += (|Z_j|^2 + |Z_{N-j}|^2) / 2 for pixel m0 (t = 0) or m1 (t = 1); t = 2 (Ez of
+        // both): |A_j|^2 and |B_j|^2 of the two real parts, (s +- c) / 4 with s = |Z_j|^2 +
+        // |Z_{N-j}|^2, c = 2 Re(Z_j Z_{N-j}); all four times larger here (scale = 1/4; pass A has
+        // applied the trace scale)
+        const T fs0 = t == 0 ? (T)2 : t == 2 ? (T)1 : (T)0, fs1 = t == 1 ? (T)2 : t == 2 ? (T)1 : (T)0;
+        const T fc = t == 2 ? (T)1 : (T)0;
+#pragma unroll
+        for (int q = 0; q <= R; ++q) {
+            // q <= H: output tid + NT q of row ka, partner B[R-1-q]; q > H: output
+            // rho + NT (q-H-1) of row kb, partner A[R-1-(q-H-1)]
+            const T2 zj = q <= H ? A[q] : B[q - H - 1];
+            const T2 zm = q <= H ? B[R - 1 - q] : A[R - 1 - (q - H - 1)];
+            const T sq = zj.x * zj.x + zj.y * zj.y + zm.x * zm.x + zm.y * zm.y;
+            const T c = (T)2 * fc * (zj.x * zm.x - zj.y * zm.y);
+            accm[q] += fs0 * sq + c;
+            acc1[q] += fs1 * sq - c;
+        }
+    }
+    T *S0 = S + m0 * ldS, *S1 = S + m1 * ldS;
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+        const int j = ka + ((tid + NT * q) << sh.lg1);
+        S0[j] = accm[q] * scale;
+        if (has1) S1[j] = acc1[q] * scale;
+    }
+    if (row0 && tid == 0) {
+        S0[N / 2] = accm[H] * scale;
+        if (has1) S1[N / 2] = acc1[H] * scale;
+    }
+    if (two) {
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            const int j = kb + ((rho + NT * q) << sh.lg1);
+            S0[j] = accm[H + 1 + q] * scale;
+            if (has1) S1[j] = acc1[H + 1 + q] * scale;
+        }
     }
 }
 
@@ -851,6 +1161,19 @@ size_t per_pair_bytes(int64_t n_obs)
 
 constexpr int64_t kMaxGridYZ = 65535;
 
+// columns of up to 2^kFastColsMaxLg1 points take the compile-time pass A
+constexpr int kFastColsMaxLg1 = 8;
+template <typename T>
+using ColsKernel = void (*)(const T *, typename C2<T>::type *, FwdShape, T);
+template <typename T, int LG1>
+ColsKernel<T> pick_cols_fast(int lg1)
+{
+    if constexpr (LG1 > kFastColsMaxLg1)
+        return nullptr;
+    else
+        return lg1 == LG1 ? k_fwd_cols_fast<T, LG1> : pick_cols_fast<T, LG1 + 1>(lg1);
+}
+
 template <typename T>
 lw_status run_fft(const T *E, int64_t n_pix, int64_t n_obs, double dt_obs, T *S, void *ws, size_t ws_bytes,
                   hipStream_t s)
@@ -872,19 +1195,26 @@ lw_status run_fft(const T *E, int64_t n_pix, int64_t n_obs, double dt_obs, T *S,
         for (int64_t p0 = 0; p0 < pairs; p0 += kMaxGridYZ) {
             sh.pair0 = p0;
             const int64_t nb = std::min(kMaxGridYZ, pairs - p0);
-            k_fwd_rows<T, true><<<dim3(1, (unsigned)nb, 1), kThrB, 0, s>>>(nullptr, E, S, sh, sc);
+            k_fwd_row_direct<T><<<dim3(1, (unsigned)nb, 1), kThrB, 0, s>>>(E, S, sh, sc);
         }
         return check_launch("lw_spectrum_fft");
     }
     const int64_t batch = std::min<int64_t>({pairs, (int64_t)(ws_bytes / per_pair_bytes<T>(n_obs)), kMaxGridYZ});
     T2 *Y = (T2 *)ws;
-    const unsigned gx_a = (unsigned)(1u << (sh.lg2 - sh.lgC)), gx_b = (unsigned)((1 << sh.lg1) / 2 + 1);
+    // N > L: the compile-time passes (pass A for columns of ET to 2^kFastColsMaxLg1 points)
+    const ColsKernel<T> cols = pick_cols_fast<T, Cfg::kLgRadix>(sh.lg1);
+    const int lgC_fast = 8 + Cfg::kLgRadix - sh.lg1;
+    const unsigned gx_a = (unsigned)(1u << (sh.lg2 - (cols ? lgC_fast : sh.lgC))), gx_b = (unsigned)((1 << sh.lg1) / 2 + 1);
     for (int64_t p0 = 0; p0 < pairs; p0 += batch) {
         const int64_t nb = std::min(batch, pairs - p0);
         sh.pair0 = p0;
-        k_fwd_cols<T><<<dim3(gx_a, 3, (unsigned)nb), kThrA, 0, s>>>(E, Y, sh);
+        if (cols)
+            cols<<<dim3(gx_a, 3, (unsigned)nb), 256, 0, s>>>(E, Y, sh, sc);
+        else
+            k_fwd_cols<T><<<dim3(gx_a, 3, (unsigned)nb), kThrA, 0, s>>>(E, Y, sh, sc);
         sh.nbatch = nb;
-        k_fwd_rows<T, false><<<dim3((unsigned)((nb + 7) / 8 * 8 * gx_b), 1, 1), kThrB, 0, s>>>(Y, nullptr, S, sh, sc);
+        k_fwd_rows_fast<T><<<dim3((unsigned)((nb + 7) / 8 * 8 * gx_b), 1, 1), FastCfg<T>::kRowThreads, 0, s>>>(
+            Y, S, sh, (T)0.25);
     }
     return check_launch("lw_spectrum_fft");
 }

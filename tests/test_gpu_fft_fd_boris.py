@@ -11,7 +11,8 @@ DEV = torch.device("cuda:0")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("n_obs", [4, 8, 32, 256, 2048, 1 << 12, 1 << 13, 1 << 16, 1 << 18, 1 << 22])
+@pytest.mark.parametrize("n_obs", [4, 8, 32, 256, 2048, 1 << 12, 1 << 13, 1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18,
+                                   1 << 19, 1 << 20, 1 << 22])
 @pytest.mark.parametrize("n_pix", [1, 2, 5])
 def test_spectrum_random_traces(prec, n_obs, n_pix):
     from paper_2206_03015_amd import lw
