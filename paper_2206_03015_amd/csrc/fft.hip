@@ -641,8 +641,10 @@ template <typename T>
 struct FastCfg;
 // kRowWaves: waves per SIMD pass B is compiled for (its registers: a row of the prefetch, one
 // row's outputs held while the partner row runs, and the accumulators of 2 R + 2 outputs).
-// Radix 8 with 512 threads for FP32 measured slower (36.8 against 36.0 ms on 16384 traces of
-// 2^18 points): more passes and LDS traffic for the doubled occupancy.
+// Measured alternatives on 16384 traces of 2^18 points: FP32 radix 8 with 512 threads, 36.8
+// against 36.0 ms (more passes and LDS traffic for the doubled occupancy); a block of two
+// 256-thread halves, one row each, swapping partner outputs through LDS, 34.8 ms in FP32 but
+// 19.1 against 16.8 ms on 4096 FP64 traces (its two FP64 row buffers leave one block per CU).
 template <>
 struct FastCfg<float> {
     static constexpr int kLgL = 12, kLgR = 4, kRowThreads = 1 << (kLgL - kLgR), kRowWaves = 2;
@@ -697,6 +699,32 @@ __device__ __forceinline__ void powers(T2 w1, T2 *w)
     }
 }
 
+// v[r] *= w1^r for 1 <= r < RP: w1^r = w1^(4 b) w1^a (r = 4 b + a) from w1, w1^2, w1^3 and a
+// running w1^(4 b), product chains of depth <= 5 with 10 registers of powers live
+template <int RP, typename T2>
+__device__ __forceinline__ void twiddle_apply(T2 *v, T2 w1)
+{
+    v[1] = cmul(v[1], w1);
+    if constexpr (RP > 2) {
+        const T2 w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+        v[2] = cmul(v[2], w2);
+        v[3] = cmul(v[3], w3);
+        if constexpr (RP > 4) {
+            const T2 w4 = cmul(w2, w2);
+            T2 h = w4;
+#pragma unroll
+            for (int b = 1; b < RP / 4; ++b) {
+                if (b == 2) h = cmul(w4, w4);
+                if (b > 2) h = cmul(h, w4);
+                v[4 * b] = cmul(v[4 * b], h);
+                v[4 * b + 1] = cmul(v[4 * b + 1], cmul(h, w1));
+                v[4 * b + 2] = cmul(v[4 * b + 2], cmul(h, w2));
+                v[4 * b + 3] = cmul(v[4 * b + 3], cmul(h, w3));
+            }
+        }
+    }
+}
+
 // First Stockham pass (Ns = 1, no twiddles) from registers: the thread's butterflies are
 // j = j0 + JS s (s < NB), and X[s + NB r] holds element j + r (sequence length / RP).
 // The RP outputs of a butterfly are adjacent (inside one pad period of the row layout).
@@ -731,15 +759,12 @@ __device__ __forceinline__ void mid_pass(T2 *buf, const At &at, int j0, const T2
         for (int r = 0; r < RP; ++r) v[s][r] = pr[At::far(JS * s + r * M)];
     __syncthreads();
     const int k = j0 & (NS - 1);
-    T2 w[RP];
-    if constexpr (LGNS > 0) powers<RP>(tab[tabi(k << (LGTAB - LGNS - LGRP))], w);
+    T2 w1;
+    if constexpr (LGNS > 0) w1 = tab[tabi(k << (LGTAB - LGNS - LGRP))];
     T2 *pw = buf + at((j0 - k) * RP + k);
 #pragma unroll
     for (int s = 0; s < NB; ++s) {
-        if constexpr (LGNS > 0) {
-#pragma unroll
-            for (int r = 1; r < RP; ++r) v[s][r] = cmul(v[s][r], w[r]);
-        }
+        if constexpr (LGNS > 0) twiddle_apply<RP>(v[s], w1);
         dftR<RP>(v[s]);
 #pragma unroll
         for (int r = 0; r < RP; ++r) pw[At::far(JS * s * RP + r * NS)] = v[s][r];
@@ -767,10 +792,7 @@ __device__ __forceinline__ void last_pass_w(const T2 *buf, const At &at, int j, 
     const T2 *pr = buf + at(j);
 #pragma unroll
     for (int r = 0; r < RP; ++r) out[r] = pr[At::far(r * NS)];
-    T2 w[RP];
-    powers<RP>(w1, w);
-#pragma unroll
-    for (int r = 1; r < RP; ++r) out[r] = cmul(out[r], w[r]);
+    twiddle_apply<RP>(out, w1);
     dftR<RP>(out);
 }
 template <int LGRP, int LGN, int LGTAB, typename T2, typename At>
@@ -864,6 +886,23 @@ __global__ __launch_bounds__(256) void k_fwd_cols_fast(const T *__restrict__ E, 
     for (int r = 1; r < ET; ++r) Yt[((g + TPC * r) << sh.lg2) + n2] = cmul(O[r], cmul(bw, sp[r]));
 }
 
+// Elements u + NT m (m < R) of a row of L complex values, by buffer loads: a scalar resource for
+// the row, one lane offset, and the NT m steps as scalar offsets
+template <int R, int NT, typename T2>
+__device__ __forceinline__ void load_row_lanes(T2 *X, const T2 *row, int u)
+{
+    constexpr int L = R * NT;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)row, (short)0, (int)(L * sizeof(T2)), 0x00020000);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        if constexpr (sizeof(T2) == 8)
+            X[m] = __builtin_bit_cast(T2, __builtin_amdgcn_raw_buffer_load_b64(rs, u * 8, m * NT * 8, 0));
+        else
+            X[m] = __builtin_bit_cast(T2, __builtin_amdgcn_raw_buffer_load_b128(rs, u * 16, m * NT * 16, 0));
+    }
+}
+
 // pass B: row pair (k1, N1 - k1) of the three packed transforms of one pixel pair per block, then S
 template <typename T>
 __global__ __launch_bounds__(FastCfg<T>::kRowThreads) __attribute__((amdgpu_waves_per_eu(FastCfg<T>::kRowWaves))) void k_fwd_rows_fast(
@@ -910,10 +949,7 @@ __global__ __launch_bounds__(FastCfg<T>::kRowThreads) __attribute__((amdgpu_wave
         return Y + (pl * 3 + t) * N + (int64_t)(second ? kb : ka) * L;
     };
     T2 X[R];
-    auto load_row = [&](const T2 *src) {
-#pragma unroll
-        for (int m = 0; m < R; ++m) X[m] = src[tid + NT * m];
-    };
+    auto load_row = [&](const T2 *src) { load_row_lanes<R, NT>(X, src, tid); };
     auto row_passes = [&](const T2 *next) {  // next: the row to load meanwhile, or null
         __syncthreads();  // the previous row's last pass has read the buffer
         first_pass<R, 1, 1>(X, buf, at, tid);
