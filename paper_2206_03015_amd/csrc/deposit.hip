@@ -61,7 +61,11 @@ constexpr uint32_t kQCap = 128;
 // write-combining line per pixel: 16-byte segments of the trace (4 floats or 2 doubles)
 template <typename T>
 struct WcLine {
-    static constexpr int N = 16 / sizeof(T);   // grid points per line
+    // grid points per line: 2 (FP32) or 1 (FP64); 4 and 2 flushed half as often but took the
+    // LDS of two of the 12 wavefronts per CU the registers allow (13.3 KB per wavefront), and
+    // were slower: 629 against 545 ms on the bunch workload, 941 against 889 ms on 1e4 electrons
+    // of the precision workload
+    static constexpr int N = 8 / sizeof(T);
     static constexpr int P = 3 * N + 1;        // LDS stride per pixel (odd: no bank conflicts)
 };
 constexpr uint32_t kWantNone = 0u;  // below every request (segment + 1)
@@ -150,6 +154,15 @@ __device__ __forceinline__ float readlane_t(float v, int src)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 __device__ __forceinline__ double readlane_t(double v, int src) { return readlane_double(v, src); }
+
+// The previous lane's value (lane l gets lane l - 1's; lane 0 gets 0): a DPP shift of the
+// wavefront by one lane, no LDS round trip
+__device__ __forceinline__ double lane_shift_up(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
 
 __device__ __forceinline__ double uniform_double(double v)
 {
@@ -831,7 +844,7 @@ struct ScanWave {
     __device__ __forceinline__ void crossings(int64_t k, int q0, int nq, int p, const double *t)
     {
         const int ns = (int)d.sh.n_samples;
-        const double nob = (double)d.sh.n_obs;
+        const double nob2 = (double)d.sh.n_obs - 2.0;
         const uint32_t tag = ((uint32_t)(k - d.k0) << kPixBits) | (uint32_t)p;
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
@@ -839,10 +852,13 @@ struct ScanWave {
             const int s = 63 * (q0 + c) + d.lane;
             const bool iv = d.lane >= 1 && s < ns;  // this lane ends an interval
             const double tb = t[c];
-            const double ta = __shfl_up(tb, 1);
+            const double ta = lane_shift_up(tb);
             // arrival times increase on the fast path: the interval holds grid points iff the
-            // count of window grid points up to its end exceeds that up to its start
-            const bool hit = iv && (int)fmin(fmax(floor(tb) + 1.0, 0.0), nob) > (int)fmin(fmax(floor(ta) + 1.0, 0.0), nob);
+            // count of window grid points up to its end, clamp(floor(t) + 1, 0, n_obs), exceeds
+            // that up to its start; with ta <= tb that is floor(tb) > floor(ta), floor(tb) >= 0
+            // and floor(ta) <= n_obs - 2
+            const double fb = floor(tb), fa = lane_shift_up(fb);
+            const bool hit = iv && fb > fa && fb >= 0.0 && fa <= nob2;
             const uint64_t mask = __ballot(hit);
             if (mask) {
                 d.push(hit, mask, (uint32_t)s, tag, ta, tb);
