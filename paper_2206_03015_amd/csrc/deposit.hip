@@ -77,10 +77,6 @@ constexpr int kTargetWaves = 98304;
 // at most this many particles per group: the wavefronts of a group (one per pixel tile, started
 // together on one XCD) read the same records, and stay close enough to share them in L2
 constexpr int kMaxPartsPerGroup = 4;
-// (|r|/|x|)^2 up to which the series forms of the exact-geometry arrival time are used
-constexpr double kSeriesBound = 1e-8;
-// pixels whose |x_m| is within this relative distance of the records' distance use the records
-constexpr double kSameDistance = 4.0 * 2.220446049250313e-16;
 constexpr int kPrepassChunk = 8192;
 // pixel table: kPT doubles per pixel (o, px, py, ok, nx, ny, nz, D, invD, padding), at most
 // kPixTabMax pixels per pass (its share of the workspace); larger grids take several passes
@@ -135,11 +131,6 @@ __device__ __forceinline__ void lds_add(T *p, T v)
 
 // |r|^2 with the operation order of the pre-pass
 __device__ __forceinline__ double sq3(double x, double y, double z) { return fma(z, z, fma(y, y, x * x)); }
-
-__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
-{
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
 
 // value of lane src (wavefront-uniform src) of a double / float / double register
 __device__ __forceinline__ double readlane_double(double v, int src)

@@ -144,6 +144,17 @@ __device__ __forceinline__ double pix_b(const PixC &p, double x, double y, doubl
 //               <= 1.25e-8 of the correction under the bound (used with single-precision fields).
 // Written with explicit fma so that every evaluation of the same (pixel, sample) gives the same bits.
 constexpr int kTauSqrt = 0, kTauSeries = 1, kTauShort = 2;
+// number of set bits of a wavefront mask below this lane
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// (|r|/|x|)^2 up to which the series forms of the exact-geometry arrival time are used
+constexpr double kSeriesBound = 1e-8;
+// pixels whose |x_m| is within this relative distance of the records' distance use the records
+// (tau_poly at that distance)
+constexpr double kSameDistance = 4.0 * 2.220446049250313e-16;
 template <int GEOM, int FORM>
 __device__ __forceinline__ double arrival_tau(const PixC &p, double d, double rx, double ry, double rz, double rr,
                                               double C)
