@@ -309,9 +309,11 @@ lw_status lw_spectrum_fft_bwd(const void *E, const void *dS, int64_t n_pix, int6
  * (MIXED returns LW_E_UNSUPPORTED).  traj: kind LW_TRAJ_SAMPLES.  dE: double
  * [n_pix][3][n_obs].  ws: >= lw_workspace_bytes(LW_WS_DEPOSIT_BWD, n_particles,
  * n_samples, prec) bytes (each particle's max |r_i|^2).  Arrival times take the
- * forward deposit's forms: the compensated arrival base, and in the exact
- * geometry the third-order series of the path correction for particles with
- * max_i |r_i|^2 <= 1e-8 |x_m|^2 (exact to rounding), else the square-root form.
+ * forward FP64 deposit's forms: for pixels at the distance of pixel 0 and
+ * particles with max_i |r_i|^2 <= 1e-8 |x_m|^2 the polynomial in the pixel term
+ * b of the deposit's records (the same coefficients), else from the compensated
+ * arrival base with the third-order series of the path correction in that range
+ * (exact to rounding) or the square-root form.
  */
 lw_status lw_deposit_td_bwd(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom,
                             const void *dE, double *d_r, double *d_beta, double *d_beta_dot, void *ws,
