@@ -420,14 +420,23 @@ __global__ __launch_bounds__(64) void k_boris_tangent(const double *__restrict__
         grad_a0[k] = acc;
 }
 
-// The tangents over samples s0 .. s0 + n_span - 1 only: each lane starts from its seeded
+// The tangents over samples s0 .. s0 + n_span - 1 only, kTanND of the seven per lane: lane l
+// takes particle k = l / G and parameters p = kTanND (l % G) + j (j < kTanND, p < 7), G =
+// ceil(7 / kTanND) lanes per particle, so each lane runs the pusher's values once for kTanND
+// tangents (the laser's sin, cos and exp serve them all).  Each lane starts from its seeded
 // initial state (s0 = 0) or from the dual-number state the previous span left at sample s0
-// ([lane][18]: the 9 state values, then their derivatives), contracts the span's gradients
-// g_* [n_particles][n_span][3], saves its state at the span's last sample, and writes (s0 = 0)
-// or adds its sum.  Spans share their boundary sample; the gradients of a boundary sample are
-// split between the two spans' deposit adjoints (each gathers its own intervals), so the two
-// contractions add up to the whole.
-constexpr int kTanStateDoubles = 18;
+// ([lane][9 (1 + kTanND)]: the 9 state values, then their derivatives), contracts the span's
+// gradients g_* [n_particles][n_span][3], saves its state at the span's last sample, and writes
+// (s0 = 0) or adds its sums.  Spans share their boundary sample; the gradients of a boundary
+// sample are split between the two spans' deposit adjoints (each gathers its own intervals), so
+// the two contractions add up to the whole.
+// One tangent per lane: two or four per lane (values computed once for them) measured slower on
+// the large workload's adjoint (444 and 448 against 326 ms): their registers (221, 324) leave
+// fewer wavefronts to hide the pusher's serial chain of steps.
+constexpr int kTanND = 1;
+constexpr int kTanLanes = (kParams + kTanND - 1) / kTanND;          // lanes per particle
+constexpr int kTanStateDoubles = 9 * (1 + kTanND);                  // per lane
+static_assert(kTanLanes * kTanStateDoubles <= 7 * 18, "the workspace holds 126 doubles of state per particle");
 
 __global__ __launch_bounds__(64) void k_boris_tangent_span(const double *__restrict__ init, int64_t n_particles,
                                                            int64_t s0, int64_t n_span, double t_start, double dt,
@@ -438,49 +447,64 @@ __global__ __launch_bounds__(64) void k_boris_tangent_span(const double *__restr
                                                            double *__restrict__ grad_init,
                                                            double *__restrict__ grad_a0)
 {
-    using D = Dual<1>;
+    using D = Dual<kTanND>;
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= n_particles * kParams) return;
-    const int64_t k = l / kParams;
-    const int p = (int)(l - k * kParams);
+    if (l >= n_particles * kTanLanes) return;
+    const int64_t k = l / kTanLanes;
+    const int p0 = (int)(l - k * kTanLanes) * kTanND;  // parameters p0 .. p0 + kTanND - 1
     D a0(L.a0);
-    a0.d[0] = (p == 6) ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = 0; j < kTanND; ++j) a0.d[j] = (p0 + j == 6) ? 1.0 : 0.0;
     PushState<D> S;
     double *st = tstate + kTanStateDoubles * l;
     if (s0 == 0) {
         D in[6];
         for (int c = 0; c < 6; ++c) {
             in[c] = D(init[6 * k + c]);
-            in[c].d[0] = (c == p) ? 1.0 : 0.0;
+#pragma unroll
+            for (int j = 0; j < kTanND; ++j) in[c].d[j] = (c == p0 + j) ? 1.0 : 0.0;
         }
         push_start(L, a0, in, t_start, dt, S);
     } else {
         D *f[9] = {&S.x, &S.y, &S.z, &S.usx, &S.usy, &S.usz, &S.uhx, &S.uhy, &S.uhz};
         for (int c = 0; c < 9; ++c) {
             f[c]->v = st[c];
-            f[c]->d[0] = st[9 + c];
+#pragma unroll
+            for (int j = 0; j < kTanND; ++j) f[c]->d[j] = st[9 + 9 * j + c];
         }
         // the same arguments as the step that reached sample s0: the same field and derivative
         laser_eb(L, a0, S.x, S.y, S.z, t_start + (double)s0 * dt, S.Ex, S.By);
     }
-    double acc = 0.0;
-    for (int64_t j = 0; j < n_span; ++j) {
+    double acc[kTanND];
+#pragma unroll
+    for (int j = 0; j < kTanND; ++j) acc[j] = 0.0;
+    for (int64_t i = 0; i < n_span; ++i) {
         D rr[3], bb[3], aa[3];
         push_sample(S, rr, bb, aa);
-        const size_t o = (size_t)(k * n_span + j) * 3;
-        for (int c = 0; c < 3; ++c) acc += g_r[o + c] * rr[c].d[0] + g_b[o + c] * bb[c].d[0] + g_a[o + c] * aa[c].d[0];
-        if (j + 1 == n_span) break;
-        push_step(L, a0, t_start + (double)(s0 + j + 1) * dt, dt, S);
+        const size_t o = (size_t)(k * n_span + i) * 3;
+        for (int c = 0; c < 3; ++c) {
+            const double gr = g_r[o + c], gb = g_b[o + c], ga = g_a[o + c];
+#pragma unroll
+            for (int j = 0; j < kTanND; ++j) acc[j] += gr * rr[c].d[j] + gb * bb[c].d[j] + ga * aa[c].d[j];
+        }
+        if (i + 1 == n_span) break;
+        push_step(L, a0, t_start + (double)(s0 + i + 1) * dt, dt, S);
     }
     {
         const D *f[9] = {&S.x, &S.y, &S.z, &S.usx, &S.usy, &S.usz, &S.uhx, &S.uhy, &S.uhz};
         for (int c = 0; c < 9; ++c) {
             st[c] = f[c]->v;
-            st[9 + c] = f[c]->d[0];
+#pragma unroll
+            for (int j = 0; j < kTanND; ++j) st[9 + 9 * j + c] = f[c]->d[j];
         }
     }
-    double *out = p < 6 ? grad_init + 6 * k + p : grad_a0 + k;
-    *out = s0 == 0 ? acc : *out + acc;
+#pragma unroll
+    for (int j = 0; j < kTanND; ++j) {
+        const int p = p0 + j;
+        if (p >= kParams) break;
+        double *out = p < 6 ? grad_init + 6 * k + p : grad_a0 + k;
+        *out = s0 == 0 ? acc[j] : *out + acc[j];
+    }
 }
 
 LaserDev laser_dev(const lw_laser_t &l)
@@ -532,7 +556,7 @@ lw_status launch_boris_bwd_span(const lw_traj_t *t, int64_t s0, int64_t n_span, 
 {
     if (t->n_particles == 0 || n_span == 0) return LW_OK;
     const LaserDev L = laser_dev(t->laser);
-    const int64_t lanes = t->n_particles * kParams;
+    const int64_t lanes = t->n_particles * kTanLanes;
     const int64_t blocks = (lanes + 63) / 64;
     hipEvent_t ev = timing_begin(LW_KERNEL_BORIS_TANGENT, s);
     k_boris_tangent_span<<<(unsigned)blocks, 64, 0, s>>>(t->init, t->n_particles, s0, n_span, t->t_start, t->dt, L,
