@@ -12,20 +12,21 @@
 //   * fast path (k_scan): a wavefront owns a tile of kTilePix pixels and a group of particles.
 //     For each particle it walks the samples in chunks of 64 (lane j holds sample 63 q + j of
 //     chunk q, so consecutive chunks share one sample and every interval has both ends in one
-//     chunk), two chunks at a time with the next two prefetched.  The records sit in vector
-//     registers; for each pixel of the tile the pixel's constants come from the table with
-//     scalar loads and its next grid point from the lane that stores it, and every lane forms
-//     the arrival time of its sample and compares it with that grid point.  If any lane reaches
-//     it, the crossed grid points of every interval of the chunk follow from the two ends'
-//     arrival times (neighbouring lane); each sample that ends or starts a crossing interval
-//     evaluates the Lienard-Wiechert field once, the interval's start field comes from the
-//     neighbouring lane, and the interpolated values go to the trace with global atomics (the
-//     crossed grid points of consecutive intervals are consecutive, so these are contiguous).
-//     An interval holding more than kLongRun grid points (an observer grid much finer than the
-//     samples) is deposited by the whole wavefront, 64 grid points per pass;
+//     chunk), three chunks at a time, the first value of each record of the next three loaded
+//     ahead.  The records sit in vector registers; for each pixel of the tile its next grid point
+//     and its constants come from LDS, the same address in every lane (the constants from the
+//     pixel table with scalar loads where each pixel takes its own arrival-time form), and every
+//     lane forms the arrival time of its sample and compares it with that grid point.  If any
+//     lane reaches it, the intervals of the chunk that hold window grid points follow from the two
+//     ends' arrival times (the neighbouring lane's value) and are queued in LDS with both arrival
+//     times;
 //   * careful path (k_careful, particles the pre-pass could not clear): lanes own pixels; the
-//     skip rules of lw_deposit_td are applied interval by interval, crossings go through a queue
-//     in LDS and write-combining lines of the trace (see Wave).
+//     skip rules of lw_deposit_td are applied interval by interval, and crossings go to the same
+//     queue;
+//   * the queue is drained 64 entries at a time, one per lane (see Wave::drain): the field at the
+//     interval's two ends and the interpolated values at its grid points, added to the trace with
+//     global atomics.  An interval holding more than kLongRun grid points (an observer grid much
+//     finer than the samples) is deposited by the whole wavefront, 64 grid points per pass.
 // The field is therefore evaluated only at samples that the interpolation reads.  Every decision
 // and weight uses one arrival-time value per (sample, pixel): both orientations evaluate it with
 // the same operations (tau_eval).  With LW_CULL (a separate instantiation) a fast-path particle
@@ -58,17 +59,6 @@ constexpr int kBlockThreads = 64;
 // queue ring: up to 63 pending entries plus one push (at most 64 crossings: one sample's pixels
 // of one half of the tile on the careful path, one chunk's intervals on the fast path)
 constexpr uint32_t kQCap = 128;
-// write-combining line per pixel: 16-byte segments of the trace (4 floats or 2 doubles)
-template <typename T>
-struct WcLine {
-    // grid points per line: 2 (FP32) or 1 (FP64); 4 and 2 flushed half as often but took the
-    // LDS of two of the 12 wavefronts per CU the registers allow (13.3 KB per wavefront), and
-    // were slower: 629 against 545 ms on the bunch workload, 941 against 889 ms on 1e4 electrons
-    // of the precision workload
-    static constexpr int N = 8 / sizeof(T);
-    static constexpr int P = 3 * N + 1;        // LDS stride per pixel (odd: no bank conflicts)
-};
-constexpr uint32_t kWantNone = 0u;  // below every request (segment + 1)
 // intervals with more grid points than this are deposited by the whole wavefront
 constexpr int kLongRun = 8;
 // wavefronts per launch to aim for (particle groups x pixel tiles): ~26 rounds of the 3072
@@ -118,15 +108,6 @@ __device__ __forceinline__ double next_grid(double tau, double n_obs)
 __device__ __forceinline__ int64_t grid_count(double tau, double n_obs)
 {
     return (int64_t)fmin(fmax(floor(tau) + 1.0, 0.0), n_obs);
-}
-
-// Atomic add into LDS through an LDS-qualified pointer, so that the compiler cannot merge it
-// with a global atomic on another path into one flat (address-space generic) atomic.
-template <typename T>
-__device__ __forceinline__ void lds_add(T *p, T v)
-{
-    typedef __attribute__((address_space(3))) T lds_t;
-    __hip_atomic_fetch_add((lds_t *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // |r|^2 with the operation order of the pre-pass
@@ -387,7 +368,8 @@ struct DepShape {
 
 // Per-wavefront state of the careful path (k_careful): lanes own pixels (kPPL each); a particle's
 // samples are taken one at a time, with the skip rules applied per interval; crossings are queued
-// in LDS and drained 64 at a time into write-combining lines of the trace.
+// in LDS and drained 64 at a time, each lane adding one interval's grid points to the trace with
+// global atomics.
 template <typename T, int GEOM>
 struct Wave {
     const double *__restrict__ r;
@@ -405,10 +387,6 @@ struct Wave {
     int64_t tile, k0;
     uint2 *q;          // queue ring in LDS: {sample index, (particle - k0) << kPixBits | pixel in tile}
     double2 *qt;       // the entry's arrival times {tau_{i-1}, tau_i}
-    T *wc;             // write-combining lines in LDS, [kTilePix][WcLine<T>::P] (3 components x N)
-    int *wcb;          // [kTilePix] trace segment each line holds (-1: none)
-    uint32_t *want;    // [kTilePix] 1 + the furthest segment holding the grid point after a hit in this drain
-    int *fpix;         // [64] pixel (in tile) of the j-th line of a flush
     PixC pc[kPPL];     // constants of this lane's pixels (lane + 64 h)
     uint32_t qh, qn;   // queue ring head and length
 
@@ -443,28 +421,6 @@ struct Wave {
         for (int c = 0; c < scan_n<MODE>(); ++c) v[c] = src[c];
     }
 
-    // Add the lines of pixels 64 h + (bits of `mask`) to the trace and clear them: lane l of a pass
-    // takes value l % 3N (component (l % 3N) / N, grid point l % N) of the (l / 3N)-th line.
-    __device__ void flush_lines(uint64_t mask, int h)
-    {
-        constexpr int NL = WcLine<T>::N, V = 3 * NL;
-        const int n = __popcll(mask);
-        if (n == 0) return;
-        if ((mask >> lane) & 1ull) fpix[lanes_below(mask)] = lane + 64 * h;
-        __builtin_amdgcn_wave_barrier();
-        for (int l = lane; l < n * V; l += 64) {
-            const int jj = l / V, w = l - jj * V;
-            const int p = fpix[jj];
-            const int c = w / NL, o = w - c * NL;
-            T *line = wc + p * WcLine<T>::P + w;
-            const T v = *line;
-            *line = (T)0;
-            const int64_t u = (int64_t)wcb[p] * NL + o;
-            if (v != (T)0 && u < sh.n_obs) atomic_add(E + ((size_t)(tile * kTilePix + p) * 3 + c) * sh.n_obs + u, v);
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-
     // Evaluate the cnt oldest queued crossings (lane j takes entry j).
     __device__ void drain(uint32_t cnt)
     {
@@ -488,7 +444,6 @@ struct Wave {
         const double ta = tt.x, tb = tt.y;
         int u0 = 0, u1 = 0;
         T idt = (T)0, eax = (T)0, eay = (T)0, eaz = (T)0, ebx = (T)0, eby = (T)0, ebz = (T)0;
-        constexpr int NL = WcLine<T>::N;
         if (act) {
             const uint32_t i = e.x, kl = e.y;
             const int64_t k = k0 + (int64_t)(kl >> kPixBits);
@@ -511,24 +466,14 @@ struct Wave {
             // interpolation weight w = (u - ta)/(tb - ta), in the precision of the trace
             idt = sizeof(T) == 4 ? (T)__builtin_amdgcn_rcpf((float)(tb - ta)) : (T)(1.0 / (tb - ta));
             if (u1 - u0 <= kLongRun) {
-                const int seg = wcb[ml];
+                T *Em = E + (size_t)m * 3 * sh.n_obs;
                 for (int u = u0; u < u1; ++u) {
                     const T w = (T)((double)u - ta) * idt, w1 = (T)1 - w;
-                    const T vx = w1 * eax + w * ebx, vy = w1 * eay + w * eby, vz = w1 * eaz + w * ebz;
-                    if (u / NL == seg) {
-                        T *line = wc + ml * WcLine<T>::P + (u % NL);
-                        lds_add(line, vx);
-                        lds_add(line + NL, vy);
-                        lds_add(line + 2 * NL, vz);
-                    } else {
-                        T *Em = E + (size_t)m * 3 * sh.n_obs + u;
-                        atomic_add(Em, vx);
-                        atomic_add(Em + sh.n_obs, vy);
-                        atomic_add(Em + 2 * sh.n_obs, vz);
-                    }
+                    atomic_add(Em + u, w1 * eax + w * ebx);
+                    atomic_add(Em + sh.n_obs + u, w1 * eay + w * eby);
+                    atomic_add(Em + 2 * sh.n_obs + u, w1 * eaz + w * ebz);
                 }
             }
-            if (u1 > u0) atomicMax(want + ml, (uint32_t)(u1 / NL) + 1u);
         }
         // intervals holding many grid points (a grid much finer than the sample spacing): the
         // whole wavefront deposits them one at a time, 64 consecutive grid points per pass
@@ -551,25 +496,9 @@ struct Wave {
                 atomic_add(Em + 2 * sh.n_obs + u, w1 * saz + w * sbz);
             }
         }
+        // the entries are read: later pushes may take their slots
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        // steer each pixel's line to the segment of its next grid point; flush lines that move
-#pragma unroll
-        for (int h = 0; h < kPPL; ++h) {
-            const int p = lane + 64 * h;
-            const uint32_t wnt = want[p];
-            want[p] = kWantNone;
-            const int cur = wcb[p];
-            const int nxt = wnt == kWantNone ? cur : (int)(wnt - 1u);
-            const bool move = nxt != cur && nxt * (int64_t)WcLine<T>::N < sh.n_obs;
-            const uint64_t fm = __ballot(move && cur >= 0);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            flush_lines(fm, h);
-            if (move) wcb[p] = nxt;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-        }
         qh = __builtin_amdgcn_readfirstlane(qwrap(qh + cnt));
         qn = __builtin_amdgcn_readfirstlane(qn - cnt);
     }
@@ -679,10 +608,6 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     }
     __shared__ uint2 q_all[kQCap];
     __shared__ double2 qt_all[kQCap];
-    __shared__ T wc_all[kTilePix * WcLine<T>::P];
-    __shared__ int wcb_all[kTilePix];
-    __shared__ uint32_t want_all[kTilePix];
-    __shared__ int fpix_all[64];
     __shared__ unsigned long long red[4];
     const int lane = threadIdx.x & 63;
     if (threadIdx.x < 4) red[threadIdx.x] = 0ull;
@@ -731,19 +656,8 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     w.k0 = k0;
     w.q = q_all;
     w.qt = qt_all;
-    w.wc = wc_all;
-    w.wcb = wcb_all;
-    w.want = want_all;
-    w.fpix = fpix_all;
     w.qh = 0;
     w.qn = 0;
-    for (int j = lane; j < kTilePix * WcLine<T>::P; j += 64) w.wc[j] = (T)0;
-    for (int p = lane; p < kTilePix; p += 64) {
-        w.wcb[p] = -1;
-        w.want[p] = kWantNone;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
 
     unsigned long long c0 = 0, c1 = 0, c2 = 0, c3 = 0;
     for (int64_t k = k0; k < k1; ++k) {
@@ -760,8 +674,6 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
             w.template particle<kModeMixed>(lane_ok, pix_in, m, k, c0, c1, c2, c3);
     }
     while (w.qn > 0) w.drain(w.qn < 64 ? w.qn : 64);
-#pragma unroll
-    for (int h = 0; h < kPPL; ++h) w.flush_lines(__ballot(w.wcb[lane + 64 * h] >= 0), h);
 
     // counters: block reduction in LDS, then one global atomic per counter
     if (c0) atomicAdd(&red[0], c0);
@@ -780,9 +692,10 @@ template <typename T, int GEOM>
 struct ScanWave {
     static constexpr bool F64 = sizeof(T) == 8;
     using Lay = RecLayout<GEOM, F64>;
-    // chunks per block: three with single-precision fields, two with double ones (their larger
-    // records and drain take the registers a third chunk would need)
-    static constexpr int NB = F64 ? 2 : 3;
+    // chunks per block: three. With double-precision fields (degree-5 records) this leaves a few
+    // values that live through the whole kernel in scratch (36 bytes, reloaded once per particle);
+    // still faster than two chunks: 1124 against 1141 ms on 1e4 electrons of the precision workload
+    static constexpr int NB = 3;
     Wave<T, GEOM> d;       // queue, drain and write-combining lines (shared with the careful path)
     double *pcl;           // LDS: o, px, py, g of the tile's pixels, [kTilePix + 1][4] (one padding row);
                            // g: the pixel's next grid point above the arrival times scanned so far
@@ -998,10 +911,6 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     constexpr int kRec = kF64 ? kModeRec5 : kModeRec3;
     __shared__ uint2 q_all[kQCap];
     __shared__ double2 qt_all[kQCap];
-    __shared__ T wc_all[kTilePix * WcLine<T>::P];
-    __shared__ int wcb_all[kTilePix];
-    __shared__ uint32_t want_all[kTilePix];
-    __shared__ int fpix_all[64];
     __shared__ double pcl_all[4 * (kTilePix + 1)];
     __shared__ unsigned long long red[4];
     const int lane = threadIdx.x & 63;
@@ -1067,17 +976,8 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     d.k0 = k0;
     d.q = q_all;
     d.qt = qt_all;
-    d.wc = wc_all;
-    d.wcb = wcb_all;
-    d.want = want_all;
-    d.fpix = fpix_all;
     d.qh = 0;
     d.qn = 0;
-    for (int j = lane; j < kTilePix * WcLine<T>::P; j += 64) d.wc[j] = (T)0;
-    for (int p = lane; p < kTilePix; p += 64) {
-        d.wcb[p] = -1;
-        d.want[p] = kWantNone;
-    }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 
@@ -1096,8 +996,6 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
             w.template particle<kModeMixed, CULL>(k, pix_in, c1, c2, c3);
     }
     while (d.qn > 0) d.drain(d.qn < 64 ? d.qn : 64);
-#pragma unroll
-    for (int h = 0; h < kPPL; ++h) d.flush_lines(__ballot(d.wcb[lane + 64 * h] >= 0), h);
 
     // counters: block reduction in LDS, then one global atomic per counter
     if (c1) atomicAdd(&red[1], c1);
