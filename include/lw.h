@@ -136,7 +136,7 @@ typedef struct {
  * default: min(n_particles, 65536) particles over the longest spans that fit);
  * any workspace that holds a two-sample span of one particle is accepted and
  * sets batch and span.  LW_WS_DEPOSIT_BWD_BORIS does the same for the adjoint
- * (min(n_particles, 16384) particles, seven tangents each).  Returns 0 for
+ * (min(n_particles, 28086) particles, seven tangents each).  Returns 0 for
  * an unknown `which`.  Larger workspaces are accepted; for the FFT a larger
  * workspace lets more pixels be transformed per pass.
  */

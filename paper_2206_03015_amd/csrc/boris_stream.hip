@@ -27,8 +27,11 @@ constexpr int64_t kMinSpan = 1024;
 // longest span one deposit launch takes (its pre-pass grid covers 8192 samples per block row)
 constexpr int64_t kMaxSpan = int64_t(1) << 28;
 constexpr int kStateBytes = 9 * sizeof(double);
-// the adjoint runs seven tangent lanes per particle: batches of up to ~1.75 wavefronts per SIMD
-constexpr int64_t kFillParticlesBwd = 16384;
+// the adjoint runs seven tangent lanes per particle: batches of up to three wavefronts of them per
+// SIMD (3 x 1024 x 64 / 7 particles).  Larger batches also push each trajectory's first pass
+// (max |r|^2) fewer times.  Deposit-and-pusher adjoint of the large workload: 16384 particles
+// 787 ms, 28086 633-640 ms, 40960 654 ms, 65536 648 ms
+constexpr int64_t kFillParticlesBwd = 28086;
 constexpr int kTanStateBytes = 7 * 18 * sizeof(double);
 
 inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
