@@ -241,6 +241,34 @@ __device__ __forceinline__ double tau_eval(const PixC &P, const double *v, doubl
     }
 }
 
+// tau_eval of NB records at one pixel: with polynomial records the operations of each record are
+// tau_eval's, in its order, interleaved across the records, so that a wavefront has NB
+// independent chains to issue from instead of one dependent chain at a time (same bits)
+template <int GEOM, bool F64, int MODE, int NB, int N>
+__device__ __forceinline__ void tau_eval_block(const PixC &P, const double (*R)[N], double cK, double rb2, double C,
+                                               double *t)
+{
+    if constexpr (MODE == kModeRec3 || MODE == kModeRec5) {
+        constexpr int DEG = RecLayout<GEOM, F64>::DEG;
+        double b[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) b[c] = P.o * R[c][DEG + 2];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) b[c] = fma(P.px, R[c][DEG], b[c]);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) b[c] = fma(P.py, R[c][DEG + 1], b[c]);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) t[c] = fma(b[c], cK, R[c][DEG - 1]);
+#pragma unroll
+        for (int j = DEG - 2; j >= 0; --j)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) t[c] = fma(b[c], t[c], R[c][j]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) t[c] = tau_eval<GEOM, F64, MODE>(P, R[c], cK, rb2, C);
+    }
+}
+
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct DepWs {
@@ -820,12 +848,10 @@ struct ScanWave {
                     }
                     ng = pcl[4 * (p + 1) + 3];
                     double t[NB];
+                    tau_eval_block<GEOM, F64, MODE, NB>(P, R, d.cK, d.rb2, d.sh.C, t);
                     uint64_t any = 0;
 #pragma unroll
-                    for (int c = 0; c < NB; ++c) {
-                        t[c] = tau_eval<GEOM, F64, MODE>(P, R[c], d.cK, d.rb2, d.sh.C);
-                        any |= __ballot(t[c] >= g);
-                    }
+                    for (int c = 0; c < NB; ++c) any |= __ballot(t[c] >= g);
                     if (__builtin_expect(any != 0, 0)) {  // rare: keep the scan's path straight
                         crossings(k, q0, nq, p, t);
                         double tl = t[0];
