@@ -79,6 +79,12 @@ static_assert(kPixTabMax % kTilePix == 0, "whole tiles per pixel pass");
 constexpr int kModeRec3 = 0, kModeRec5 = 1, kModeFar = 2, kModeSqrt = 3, kModeSeries = 4, kModeShort = 5;
 // arrival_tau per pixel with the form of each pixel (series where rb2 |x_m|^-2 <= kSeriesBound)
 constexpr int kModeMixed = 6;
+// degree-3 records (single-precision fields) evaluated without their cubic term K e b^3, where
+// its bound over the particle's trajectory and the tile's pixels is at most kCubicBound grid
+// units (a tenth of a ten-millionth of a grid step: below the single-precision interpolation
+// weights' own rounding)
+constexpr int kModeRec2 = 7;
+constexpr double kCubicBound = 1e-7;
 
 // Record of one sample (doubles), read by the scan with scalar loads:
 //   far field:          d, x, y, z
@@ -209,7 +215,7 @@ __device__ __forceinline__ PixC pixc_row(P row)
 template <int GEOM, bool F64, int MODE>
 struct ScanVals {
     using L = RecLayout<GEOM, F64>;
-    static constexpr bool kRecMode = MODE == kModeRec3 || MODE == kModeRec5;
+    static constexpr bool kRecMode = MODE == kModeRec3 || MODE == kModeRec5 || MODE == kModeRec2;
     static constexpr int OFF = MODE == kModeMixed ? L::X : 0;
     static constexpr int N = (MODE == kModeFar || MODE == kModeMixed) ? 4 : L::DEG + 3;
     static constexpr int X = MODE == kModeFar ? 1 : (MODE == kModeMixed ? 0 : L::DEG);
@@ -217,7 +223,8 @@ struct ScanVals {
 };
 
 // Arrival time of one (sample, pixel) in scan mode MODE from the record values v and the pixel
-// constants P: far field tau = d + b; polynomial records tau = sum_j c_j b^j (c_DEG = cK); else
+// constants P: far field tau = d + b; polynomial records tau = sum_j c_j b^j (c_DEG = cK; without
+// that term in kModeRec2); else
 // arrival_tau in the pixel's form (series where rb2 |x_m|^-2 <= kSeriesBound).  Both orientations
 // (lanes over pixels, v uniform; lanes over samples, P uniform) run these same operations, so a
 // (sample, pixel) gets the same bits wherever it is evaluated.
@@ -226,12 +233,19 @@ __device__ __forceinline__ double tau_eval(const PixC &P, const double *v, doubl
 {
     if constexpr (MODE == kModeFar) {
         return pix_b(P, v[1], v[2], v[3]) + v[0];
-    } else if constexpr (MODE == kModeRec3 || MODE == kModeRec5) {
+    } else if constexpr (MODE == kModeRec3 || MODE == kModeRec5 || MODE == kModeRec2) {
         constexpr int DEG = RecLayout<GEOM, F64>::DEG;
         const double b = pix_b(P, v[DEG], v[DEG + 1], v[DEG + 2]);
-        double u = fma(b, cK, v[DEG - 1]);
+        double u;
+        if constexpr (MODE == kModeRec2) {
+            u = fma(b, v[DEG - 1], v[DEG - 2]);
 #pragma unroll
-        for (int j = DEG - 2; j >= 0; --j) u = fma(b, u, v[j]);
+            for (int j = DEG - 3; j >= 0; --j) u = fma(b, u, v[j]);
+        } else {
+            u = fma(b, cK, v[DEG - 1]);
+#pragma unroll
+            for (int j = DEG - 2; j >= 0; --j) u = fma(b, u, v[j]);
+        }
         return u;
     } else {
         constexpr int FORM = F64 ? kTauSeries : kTauShort;
@@ -248,7 +262,7 @@ template <int GEOM, bool F64, int MODE, int NB, int N>
 __device__ __forceinline__ void tau_eval_block(const PixC &P, const double (*R)[N], double cK, double rb2, double C,
                                                double *t)
 {
-    if constexpr (MODE == kModeRec3 || MODE == kModeRec5) {
+    if constexpr (MODE == kModeRec3 || MODE == kModeRec5 || MODE == kModeRec2) {
         constexpr int DEG = RecLayout<GEOM, F64>::DEG;
         double b[NB];
 #pragma unroll
@@ -257,16 +271,28 @@ __device__ __forceinline__ void tau_eval_block(const PixC &P, const double (*R)[
         for (int c = 0; c < NB; ++c) b[c] = fma(P.px, R[c][DEG], b[c]);
 #pragma unroll
         for (int c = 0; c < NB; ++c) b[c] = fma(P.py, R[c][DEG + 1], b[c]);
+        // the highest power: cK (or, without it, c_{DEG-1})
+        constexpr int TOP = MODE == kModeRec2 ? DEG - 2 : DEG - 1;
 #pragma unroll
-        for (int c = 0; c < NB; ++c) t[c] = fma(b[c], cK, R[c][DEG - 1]);
+        for (int c = 0; c < NB; ++c) t[c] = MODE == kModeRec2 ? fma(b[c], R[c][DEG - 1], R[c][DEG - 2])
+                                                             : fma(b[c], cK, R[c][DEG - 1]);
 #pragma unroll
-        for (int j = DEG - 2; j >= 0; --j)
+        for (int j = TOP - 1; j >= 0; --j)
 #pragma unroll
             for (int c = 0; c < NB; ++c) t[c] = fma(b[c], t[c], R[c][j]);
     } else {
 #pragma unroll
         for (int c = 0; c < NB; ++c) t[c] = tau_eval<GEOM, F64, MODE>(P, R[c], cK, rb2, C);
     }
+}
+
+// Whether the degree-3 records' cubic term K e b^3 (cK = K e) stays within kCubicBound grid units
+// for a particle with |r|^2 <= rb2 over its trajectory and pixels with 2 (1 - n_z) <= s2:
+// b = C (e_z - n) . r, so |b| <= C |e_z - n| |r| = C sqrt(2 (1 - n_z)) |r|
+__device__ __forceinline__ bool cubic_negligible(double rb2, double s2, double C, double cK)
+{
+    const double bmax = C * sqrt(rb2 * s2);
+    return cK * bmax * bmax * bmax <= kCubicBound;
 }
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -644,7 +670,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     Wave<T, GEOM> w;
     int64_t m[kPPL];
     bool pix_in[kPPL], lane_ok[kPPL];
-    double id2 = 0.0;
+    double id2 = 0.0, s2 = 0.0;
     const double Dref = pix_geo(x_det, 0).D;  // the records' pixel distance
     bool far_off = false;                     // a pixel of this wavefront at another distance
 #pragma unroll
@@ -655,11 +681,15 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
         lane_ok[h] = pix_in[h] && w.pc[h].g.ok;
         if (lane_ok[h]) {
             id2 = fmax(id2, w.pc[h].g.invD * w.pc[h].g.invD);
+            s2 = fmax(s2, 2.0 * (1.0 - w.pc[h].g.nz));
             far_off |= !(fabs(w.pc[h].g.D - Dref) <= kSameDistance * Dref);
         }
     }
-    for (int off = 32; off > 0; off >>= 1) id2 = fmax(id2, __shfl_xor(id2, off));
-    const double invD2max = uniform_double(id2);
+    for (int off = 32; off > 0; off >>= 1) {
+        id2 = fmax(id2, __shfl_xor(id2, off));
+        s2 = fmax(s2, __shfl_xor(s2, off));
+    }
+    const double invD2max = uniform_double(id2), s2max = uniform_double(s2);
     const bool rec_ok = GEOM == LW_GEOM_EXACT && __ballot(far_off) == 0;
     {
         double c[6];
@@ -696,9 +726,15 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
         const bool all_ser = GEOM == LW_GEOM_EXACT && w.rb2 * invD2max <= kSeriesBound;
         if (GEOM == LW_GEOM_FARFIELD)
             w.template particle<kModeFar>(lane_ok, pix_in, m, k, c0, c1, c2, c3);
-        else if (all_ser && rec_ok)
+        else if (all_ser && rec_ok) {
+            if constexpr (!kF64) {
+                if (cubic_negligible(w.rb2, s2max, sh.C, w.cK)) {
+                    w.template particle<kModeRec2>(lane_ok, pix_in, m, k, c0, c1, c2, c3);
+                    continue;
+                }
+            }
             w.template particle<kRec>(lane_ok, pix_in, m, k, c0, c1, c2, c3);
-        else
+        } else
             w.template particle<kModeMixed>(lane_ok, pix_in, m, k, c0, c1, c2, c3);
     }
     while (w.qn > 0) w.drain(w.qn < 64 ? w.qn : 64);
@@ -954,7 +990,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     ScanWave<T, GEOM> w;
     Wave<T, GEOM> &d = w.d;
     bool pix_in[kPPL];
-    double id2 = 0.0;
+    double id2 = 0.0, s2 = 0.0;
     const double Dref = pix_geo(x_det, 0).D;  // the records' pixel distance
     bool far_off = false;                     // a pixel of this wavefront at another distance
 #pragma unroll
@@ -973,11 +1009,15 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
         if (p < 4) pcl_all[4 * kTilePix + p] = p == 3 ? INFINITY : 0.0;
         if (ok) {
             id2 = fmax(id2, pc.g.invD * pc.g.invD);
+            s2 = fmax(s2, 2.0 * (1.0 - pc.g.nz));
             far_off |= !(fabs(pc.g.D - Dref) <= kSameDistance * Dref);
         }
     }
-    for (int off = 32; off > 0; off >>= 1) id2 = fmax(id2, __shfl_xor(id2, off));
-    const double invD2max = uniform_double(id2);
+    for (int off = 32; off > 0; off >>= 1) {
+        id2 = fmax(id2, __shfl_xor(id2, off));
+        s2 = fmax(s2, __shfl_xor(s2, off));
+    }
+    const double invD2max = uniform_double(id2), s2max = uniform_double(s2);
     const bool rec_ok = GEOM == LW_GEOM_EXACT && __ballot(far_off) == 0;
     {
         double c[6];
@@ -1016,9 +1056,15 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
         const bool all_ser = GEOM == LW_GEOM_EXACT && d.rb2 * invD2max <= kSeriesBound;
         if (GEOM == LW_GEOM_FARFIELD)
             w.template particle<kModeFar, CULL>(k, pix_in, c1, c2, c3);
-        else if (all_ser && rec_ok)
+        else if (all_ser && rec_ok) {
+            if constexpr (!kF64) {
+                if (cubic_negligible(d.rb2, s2max, sh.C, d.cK)) {
+                    w.template particle<kModeRec2, CULL>(k, pix_in, c1, c2, c3);
+                    continue;
+                }
+            }
             w.template particle<kRec, CULL>(k, pix_in, c1, c2, c3);
-        else
+        } else
             w.template particle<kModeMixed, CULL>(k, pix_in, c1, c2, c3);
     }
     while (d.qn > 0) d.drain(d.qn < 64 ? d.qn : 64);
