@@ -176,7 +176,11 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec);
  *             by a first pass of the pusher) has its path correction expanded in
  *             |r|/|x_m|: to third order in FP64 mode (exact to rounding), to first
  *             order in MIXED mode (relative error of the correction <= 1.25e-8);
- *             other particles use the square-root form.  The arrival base
+ *             where every pixel of a 128-pixel tile is at the first pixel's
+ *             distance, the series is evaluated as a polynomial in the pixel
+ *             variable, leaving out its highest terms where their bound over the
+ *             particle and the tile is at most 1e-12 (FP64) or 1e-7 (MIXED) grid
+ *             units; other particles use the square-root form.  The arrival base
  *             (t_i - t0 - z_i/c)/dt_obs is summed in double-double and rounded once.
  * field_mask: LW_FIELD_ACCEL and/or LW_FIELD_VELOCITY (non-zero).
  * geom:       LW_GEOM_EXACT or LW_GEOM_FARFIELD, optionally | LW_ACCUMULATE, | LW_CULL.

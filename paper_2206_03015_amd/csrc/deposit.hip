@@ -6,9 +6,10 @@
 //     (the two large, cancelling terms of the arrival time, carried in double-double and
 //     rounded once) and, for the exact geometry with the path term in series form, the
 //     coefficients of the arrival time as a polynomial in the pixel variable b
-//     (tau = sum_j c_j b^j, b = C((1 - n_z) z - n_x x - n_y y): three fused multiply-adds per
-//     pixel); it also flags particles whose arrival times are provably increasing and finds
-//     each particle's max |r|^2; a pixel table holds each pixel's constants;
+//     (tau = sum_j c_j b^j, b = C((1 - n_z) z - n_x x - n_y y): one fused multiply-add per
+//     degree and pixel, at a lower degree where kModeRecLow applies); it also flags particles
+//     whose arrival times are provably increasing and finds each particle's max |r|^2; a pixel
+//     table holds each pixel's constants;
 //   * fast path (k_scan): a wavefront owns a tile of kTilePix pixels and a group of particles.
 //     For each particle it walks the samples in chunks of 64 (lane j holds sample 63 q + j of
 //     chunk q, so consecutive chunks share one sample and every interval has both ends in one
@@ -36,9 +37,10 @@
 // Arrival-time forms (exact geometry): the polynomial records hold the path term's series
 // (first order with single-precision fields, third order with double ones; valid where
 // |r|^2 <= 1e-8 |x_m|^2 over the whole trajectory) for pixels at the records' distance
-// (|x_m| of the first pixel); a wavefront whose pixels sit at another distance, or a particle
-// outside the series bound, evaluates arrival_tau per pixel instead (series or square-root
-// form), from the same d.
+// (|x_m| of the first pixel), evaluated to a lower degree where the terms above it are provably
+// negligible for the particle and the wavefront's pixels (kModeRecLow); a wavefront whose pixels
+// sit at another distance, or a particle outside the series bound, evaluates arrival_tau per
+// pixel instead (series or square-root form), from the same d.
 //
 // Fast path condition (checked per particle by the pre-pass): every sample usable and
 // every step shorter than c*dt by a margin well above the rounding of tau, which makes
@@ -79,12 +81,14 @@ static_assert(kPixTabMax % kTilePix == 0, "whole tiles per pixel pass");
 constexpr int kModeRec3 = 0, kModeRec5 = 1, kModeFar = 2, kModeSqrt = 3, kModeSeries = 4, kModeShort = 5;
 // arrival_tau per pixel with the form of each pixel (series where rb2 |x_m|^-2 <= kSeriesBound)
 constexpr int kModeMixed = 6;
-// degree-3 records (single-precision fields) evaluated without their cubic term K e b^3, where
-// its bound over the particle's trajectory and the tile's pixels is at most kCubicBound grid
-// units (a tenth of a ten-millionth of a grid step: below the single-precision interpolation
-// weights' own rounding)
-constexpr int kModeRec2 = 7;
-constexpr double kCubicBound = 1e-7;
+// polynomial records evaluated to a lower degree (RecLayout::LOW: 2 of 3 with single-precision
+// fields, 3 of 5 with double ones) where the terms left out stay within kTailBound grid units
+// for the particle's whole trajectory and the tile's pixels: 1e-7 (about the rounding of the
+// single-precision interpolation weights), resp. 1e-12 (far below the rounding of a double
+// arrival time of up to ~1e7 grid units)
+constexpr int kModeRecLow = 7;
+template <bool F64>
+constexpr double kTailBound = F64 ? 1e-12 : 1e-7;
 
 // Record of one sample (doubles), read by the scan with scalar loads:
 //   far field:          d, x, y, z
@@ -94,6 +98,7 @@ constexpr double kCubicBound = 1e-7;
 template <int GEOM, bool F64>
 struct RecLayout {
     static constexpr int DEG = GEOM == LW_GEOM_FARFIELD ? 0 : (F64 ? 5 : 3);
+    static constexpr int LOW = GEOM == LW_GEOM_FARFIELD ? 0 : (F64 ? 3 : 2);  // degree of kModeRecLow
     static constexpr int X = GEOM == LW_GEOM_FARFIELD ? 1 : DEG;      // x, y, z at X, X + 1, X + 2
     static constexpr int D = GEOM == LW_GEOM_FARFIELD ? 0 : DEG + 3;  // d
     static constexpr int W = GEOM == LW_GEOM_FARFIELD ? 4 : DEG + 5;  // width
@@ -215,7 +220,7 @@ __device__ __forceinline__ PixC pixc_row(P row)
 template <int GEOM, bool F64, int MODE>
 struct ScanVals {
     using L = RecLayout<GEOM, F64>;
-    static constexpr bool kRecMode = MODE == kModeRec3 || MODE == kModeRec5 || MODE == kModeRec2;
+    static constexpr bool kRecMode = MODE == kModeRec3 || MODE == kModeRec5 || MODE == kModeRecLow;
     static constexpr int OFF = MODE == kModeMixed ? L::X : 0;
     static constexpr int N = (MODE == kModeFar || MODE == kModeMixed) ? 4 : L::DEG + 3;
     static constexpr int X = MODE == kModeFar ? 1 : (MODE == kModeMixed ? 0 : L::DEG);
@@ -223,8 +228,8 @@ struct ScanVals {
 };
 
 // Arrival time of one (sample, pixel) in scan mode MODE from the record values v and the pixel
-// constants P: far field tau = d + b; polynomial records tau = sum_j c_j b^j (c_DEG = cK; without
-// that term in kModeRec2); else
+// constants P: far field tau = d + b; polynomial records tau = sum_j c_j b^j (c_DEG = cK; up to
+// j = LOW in kModeRecLow); else
 // arrival_tau in the pixel's form (series where rb2 |x_m|^-2 <= kSeriesBound).  Both orientations
 // (lanes over pixels, v uniform; lanes over samples, P uniform) run these same operations, so a
 // (sample, pixel) gets the same bits wherever it is evaluated.
@@ -233,14 +238,14 @@ __device__ __forceinline__ double tau_eval(const PixC &P, const double *v, doubl
 {
     if constexpr (MODE == kModeFar) {
         return pix_b(P, v[1], v[2], v[3]) + v[0];
-    } else if constexpr (MODE == kModeRec3 || MODE == kModeRec5 || MODE == kModeRec2) {
-        constexpr int DEG = RecLayout<GEOM, F64>::DEG;
+    } else if constexpr (MODE == kModeRec3 || MODE == kModeRec5 || MODE == kModeRecLow) {
+        constexpr int DEG = RecLayout<GEOM, F64>::DEG, LOW = RecLayout<GEOM, F64>::LOW;
         const double b = pix_b(P, v[DEG], v[DEG + 1], v[DEG + 2]);
         double u;
-        if constexpr (MODE == kModeRec2) {
-            u = fma(b, v[DEG - 1], v[DEG - 2]);
+        if constexpr (MODE == kModeRecLow) {
+            u = fma(b, v[LOW], v[LOW - 1]);
 #pragma unroll
-            for (int j = DEG - 3; j >= 0; --j) u = fma(b, u, v[j]);
+            for (int j = LOW - 2; j >= 0; --j) u = fma(b, u, v[j]);
         } else {
             u = fma(b, cK, v[DEG - 1]);
 #pragma unroll
@@ -262,8 +267,8 @@ template <int GEOM, bool F64, int MODE, int NB, int N>
 __device__ __forceinline__ void tau_eval_block(const PixC &P, const double (*R)[N], double cK, double rb2, double C,
                                                double *t)
 {
-    if constexpr (MODE == kModeRec3 || MODE == kModeRec5 || MODE == kModeRec2) {
-        constexpr int DEG = RecLayout<GEOM, F64>::DEG;
+    if constexpr (MODE == kModeRec3 || MODE == kModeRec5 || MODE == kModeRecLow) {
+        constexpr int DEG = RecLayout<GEOM, F64>::DEG, LOW = RecLayout<GEOM, F64>::LOW;
         double b[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) b[c] = P.o * R[c][DEG + 2];
@@ -271,11 +276,11 @@ __device__ __forceinline__ void tau_eval_block(const PixC &P, const double (*R)[
         for (int c = 0; c < NB; ++c) b[c] = fma(P.px, R[c][DEG], b[c]);
 #pragma unroll
         for (int c = 0; c < NB; ++c) b[c] = fma(P.py, R[c][DEG + 1], b[c]);
-        // the highest power: cK (or, without it, c_{DEG-1})
-        constexpr int TOP = MODE == kModeRec2 ? DEG - 2 : DEG - 1;
+        // the highest power: cK, or c_LOW in kModeRecLow
+        constexpr int TOP = MODE == kModeRecLow ? LOW - 1 : DEG - 1;
 #pragma unroll
-        for (int c = 0; c < NB; ++c) t[c] = MODE == kModeRec2 ? fma(b[c], R[c][DEG - 1], R[c][DEG - 2])
-                                                             : fma(b[c], cK, R[c][DEG - 1]);
+        for (int c = 0; c < NB; ++c) t[c] = MODE == kModeRecLow ? fma(b[c], R[c][LOW], R[c][LOW - 1])
+                                                               : fma(b[c], cK, R[c][DEG - 1]);
 #pragma unroll
         for (int j = TOP - 1; j >= 0; --j)
 #pragma unroll
@@ -286,13 +291,21 @@ __device__ __forceinline__ void tau_eval_block(const PixC &P, const double (*R)[
     }
 }
 
-// Whether the degree-3 records' cubic term K e b^3 (cK = K e) stays within kCubicBound grid units
-// for a particle with |r|^2 <= rb2 over its trajectory and pixels with 2 (1 - n_z) <= s2:
-// b = C (e_z - n) . r, so |b| <= C |e_z - n| |r| = C sqrt(2 (1 - n_z)) |r|
-__device__ __forceinline__ bool cubic_negligible(double rb2, double s2, double C, double cK)
+// Whether the records' terms above degree LOW stay within kTailBound grid units for a particle
+// with |r|^2 <= rb2 over its trajectory and pixels with 2 (1 - n_z) <= s2 at the records'
+// distance D: b = C (e_z - n) . r, so |b| <= C |e_z - n| |r| = C sqrt(2 (1 - n_z)) |r|.  Degree 3
+// (cK = K e): the cubic term K e b^3.  Degree 5 (cK = 7 K e^3 / 4): |c_4| <= 1.3 K e^2 within the
+// series range (|r| <= 1e-4 D; 1.251 K e^2 is its maximum there), and K e^2 = (4/7) cK C D, so
+// |c_4 b^4 + cK b^5| <= cK b^4 (0.75 C D + |b|).
+template <bool F64>
+__device__ __forceinline__ bool tail_negligible(double rb2, double s2, double C, double cK, double D)
 {
     const double bmax = C * sqrt(rb2 * s2);
-    return cK * bmax * bmax * bmax <= kCubicBound;
+    const double b3 = bmax * bmax * bmax;
+    if constexpr (F64)
+        return cK * b3 * bmax * (0.75 * C * D + bmax) <= kTailBound<true>;
+    else
+        return cK * b3 <= kTailBound<false>;
 }
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -727,13 +740,10 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
         if (GEOM == LW_GEOM_FARFIELD)
             w.template particle<kModeFar>(lane_ok, pix_in, m, k, c0, c1, c2, c3);
         else if (all_ser && rec_ok) {
-            if constexpr (!kF64) {
-                if (cubic_negligible(w.rb2, s2max, sh.C, w.cK)) {
-                    w.template particle<kModeRec2>(lane_ok, pix_in, m, k, c0, c1, c2, c3);
-                    continue;
-                }
-            }
-            w.template particle<kRec>(lane_ok, pix_in, m, k, c0, c1, c2, c3);
+            if (tail_negligible<kF64>(w.rb2, s2max, sh.C, w.cK, Dref))
+                w.template particle<kModeRecLow>(lane_ok, pix_in, m, k, c0, c1, c2, c3);
+            else
+                w.template particle<kRec>(lane_ok, pix_in, m, k, c0, c1, c2, c3);
         } else
             w.template particle<kModeMixed>(lane_ok, pix_in, m, k, c0, c1, c2, c3);
     }
@@ -1057,13 +1067,10 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
         if (GEOM == LW_GEOM_FARFIELD)
             w.template particle<kModeFar, CULL>(k, pix_in, c1, c2, c3);
         else if (all_ser && rec_ok) {
-            if constexpr (!kF64) {
-                if (cubic_negligible(d.rb2, s2max, sh.C, d.cK)) {
-                    w.template particle<kModeRec2, CULL>(k, pix_in, c1, c2, c3);
-                    continue;
-                }
-            }
-            w.template particle<kRec, CULL>(k, pix_in, c1, c2, c3);
+            if (tail_negligible<kF64>(d.rb2, s2max, sh.C, d.cK, Dref))
+                w.template particle<kModeRecLow, CULL>(k, pix_in, c1, c2, c3);
+            else
+                w.template particle<kRec, CULL>(k, pix_in, c1, c2, c3);
         } else
             w.template particle<kModeMixed, CULL>(k, pix_in, c1, c2, c3);
     }
