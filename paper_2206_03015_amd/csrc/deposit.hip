@@ -82,13 +82,8 @@ constexpr int kModeRec3 = 0, kModeRec5 = 1, kModeFar = 2, kModeSqrt = 3, kModeSe
 // arrival_tau per pixel with the form of each pixel (series where rb2 |x_m|^-2 <= kSeriesBound)
 constexpr int kModeMixed = 6;
 // polynomial records evaluated to a lower degree (RecLayout::LOW: 2 of 3 with single-precision
-// fields, 3 of 5 with double ones) where the terms left out stay within kTailBound grid units
-// for the particle's whole trajectory and the tile's pixels: 1e-7 (about the rounding of the
-// single-precision interpolation weights), resp. 1e-12 (far below the rounding of a double
-// arrival time of up to ~1e7 grid units)
+// fields, 3 of 5 with double ones) where tail_negligible holds for the particle and the tile
 constexpr int kModeRecLow = 7;
-template <bool F64>
-constexpr double kTailBound = F64 ? 1e-12 : 1e-7;
 
 // Record of one sample (doubles), read by the scan with scalar loads:
 //   far field:          d, x, y, z
@@ -289,23 +284,6 @@ __device__ __forceinline__ void tau_eval_block(const PixC &P, const double (*R)[
 #pragma unroll
         for (int c = 0; c < NB; ++c) t[c] = tau_eval<GEOM, F64, MODE>(P, R[c], cK, rb2, C);
     }
-}
-
-// Whether the records' terms above degree LOW stay within kTailBound grid units for a particle
-// with |r|^2 <= rb2 over its trajectory and pixels with 2 (1 - n_z) <= s2 at the records'
-// distance D: b = C (e_z - n) . r, so |b| <= C |e_z - n| |r| = C sqrt(2 (1 - n_z)) |r|.  Degree 3
-// (cK = K e): the cubic term K e b^3.  Degree 5 (cK = 7 K e^3 / 4): |c_4| <= 1.3 K e^2 within the
-// series range (|r| <= 1e-4 D; 1.251 K e^2 is its maximum there), and K e^2 = (4/7) cK C D, so
-// |c_4 b^4 + cK b^5| <= cK b^4 (0.75 C D + |b|).
-template <bool F64>
-__device__ __forceinline__ bool tail_negligible(double rb2, double s2, double C, double cK, double D)
-{
-    const double bmax = C * sqrt(rb2 * s2);
-    const double b3 = bmax * bmax * bmax;
-    if constexpr (F64)
-        return cK * b3 * bmax * (0.75 * C * D + bmax) <= kTailBound<true>;
-    else
-        return cK * b3 <= kTailBound<false>;
 }
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }

@@ -235,12 +235,23 @@ __global__ __launch_bounds__(64) void k_deposit_bwd(const double *__restrict__ r
         const int cnt = (int)std::min<int64_t>(64, sh.n_pix - m0);
         // the records apply to this chunk of pixels if every pixel is at the reference distance
         // and in the series range of this particle (the deposit's rule for its tiles)
-        bool rec_chunk = false;
+        bool rec_chunk = false, rec_low = false;
         if (GEOM == LW_GEOM_EXACT) {
             const PixGeo &gl = geo[lane];
             const bool fits = lane >= cnt || (gl.ok && fabs(gl.D - Dref) <= kSameDistance * Dref &&
                                               rb2 * (gl.invD * gl.invD) <= kSeriesBound);
             rec_chunk = __ballot(!fits) == 0;
+            // the forward deposit's lower-degree rule, decided over the same 128-pixel tile (its
+            // usable pixels' largest 2 (1 - n_z)), so that both evaluate the same polynomial
+            double s2 = lane < cnt && gl.ok ? 2.0 * (1.0 - gl.nz) : 0.0;  // this chunk: half the tile
+            const int64_t mo = (m0 ^ 64) + lane;                               // the other half
+            if (mo < sh.n_pix) {
+                const PixGeo go = pix_geo(x_det, mo);
+                if (go.ok) s2 = fmax(s2, 2.0 * (1.0 - go.nz));
+            }
+            for (int off = 32; off > 0; off >>= 1) s2 = fmax(s2, __shfl_xor(s2, off));
+            const bool low = rec_chunk && tail_negligible<true>(rb2, s2, sh.inv_cdt, cp[5], Dref);
+            rec_low = __builtin_amdgcn_readfirstlane(low ? 1 : 0) != 0;  // the same in every lane
         }
         for (int j = 0; j < cnt; ++j) {
             // interval (tau_{lane-1}, tau_lane]: both samples usable (and the pixel), increasing,
@@ -249,9 +260,16 @@ __global__ __launch_bounds__(64) void k_deposit_bwd(const double *__restrict__ r
             bool ok2;  // this lane's interval has both ends
             if (rec_chunk) {  // every pixel of the chunk usable: the lanes' flags alone
                 const double b = fma(pcs[2][j], rs[1], fma(pcs[1][j], rs[0], pcs[0][j] * rs[2]));
-                double u = fma(b, cp[5], cp[4]);
+                double u;
+                if (rec_low) {  // degree 3 of 5, as the forward where its terms above are negligible
+                    u = fma(b, cp[3], cp[2]);
+                    u = fma(b, u, cp[1]);
+                    u = fma(b, u, cp[0]);
+                } else {
+                    u = fma(b, cp[5], cp[4]);
 #pragma unroll
-                for (int c = 3; c >= 0; --c) u = fma(b, u, cp[c]);
+                    for (int c = 3; c >= 0; --c) u = fma(b, u, cp[c]);
+                }
                 tau = u;
                 ok2 = pair_ok;
             } else {

@@ -155,6 +155,29 @@ constexpr double kSeriesBound = 1e-8;
 // pixels whose |x_m| is within this relative distance of the records' distance use the records
 // (tau_poly at that distance)
 constexpr double kSameDistance = 4.0 * 2.220446049250313e-16;
+// The polynomial records (tau_poly) are evaluated to a lower degree -- 2 of 3 with
+// single-precision fields, 3 of 5 with double ones -- where the terms left out stay within
+// kTailBound grid units for the particle's whole trajectory and the pixels of a 128-pixel tile:
+// 1e-7 (about the rounding of the single-precision interpolation weights), resp. 1e-12 (far
+// below the rounding of a double arrival time of up to ~1e7 grid units).
+template <bool F64>
+constexpr double kTailBound = F64 ? 1e-12 : 1e-7;
+// Whether that holds for a particle with |r|^2 <= rb2 over its trajectory and pixels with
+// 2 (1 - n_z) <= s2 at the records' distance D: b = C (e_z - n) . r, so
+// |b| <= C |e_z - n| |r| = C sqrt(2 (1 - n_z)) |r|.  Degree 3 (cK = K e): the cubic term K e b^3.
+// Degree 5 (cK = 7 K e^3 / 4): |c_4| <= 1.3 K e^2 within the series range (|r| <= 1e-4 D;
+// 1.251 K e^2 is its maximum there), and K e^2 = (4/7) cK C D, so
+// |c_4 b^4 + cK b^5| <= cK b^4 (0.75 C D + |b|).
+template <bool F64>
+__device__ __forceinline__ bool tail_negligible(double rb2, double s2, double C, double cK, double D)
+{
+    const double bmax = C * sqrt(rb2 * s2);
+    const double b3 = bmax * bmax * bmax;
+    if constexpr (F64)
+        return cK * b3 * bmax * (0.75 * C * D + bmax) <= kTailBound<true>;
+    else
+        return cK * b3 <= kTailBound<false>;
+}
 template <int GEOM, int FORM>
 __device__ __forceinline__ double arrival_tau(const PixC &p, double d, double rx, double ry, double rz, double rr,
                                               double C)
