@@ -748,7 +748,7 @@ struct ScanWave {
     // values that live through the whole kernel in scratch (36 bytes, reloaded once per particle);
     // still faster than two chunks: 1124 against 1141 ms on 1e4 electrons of the precision workload
     static constexpr int NB = 3;
-    Wave<T, GEOM> d;       // queue, drain and write-combining lines (shared with the careful path)
+    Wave<T, GEOM> d;       // queue and drain (shared with the careful path)
     double *pcl;           // LDS: o, px, py, g of the tile's pixels, [kTilePix + 1][4] (one padding row);
                            // g: the pixel's next grid point above the arrival times scanned so far
     uint64_t okmask[kPPL]; // pixels 64 h + l of the tile that take part (in the pass, geometry ok)
