@@ -126,6 +126,7 @@ typedef struct {
 #define LW_WS_DIRECT_FD_BWD 6
 #define LW_WS_DEPOSIT_BORIS 7
 #define LW_WS_DEPOSIT_BWD_BORIS 8
+#define LW_WS_DEPOSIT_DET_ACC 9
 
 /*
  * Workspace (scratch device memory) that the call `which` needs, in bytes:
@@ -136,7 +137,9 @@ typedef struct {
  * default: min(n_particles, 65536) particles over the longest spans that fit);
  * any workspace that holds a two-sample span of one particle is accepted and
  * sets batch and span.  LW_WS_DEPOSIT_BWD_BORIS does the same for the adjoint
- * (min(n_particles, 28086) particles, seven tangents each).  Returns 0 for
+ * (min(n_particles, 28086) particles, seven tangents each).
+ * LW_WS_DEPOSIT_DET_ACC (n_a = n_pix, n_b = n_obs) is the accumulator buffer of
+ * lw_deposit_td_det: 8 bytes per trace element and 8 per trace row.  Returns 0 for
  * an unknown `which`.  Larger workspaces are accepted; for the FFT a larger
  * workspace lets more pixels be transformed per pass.
  */
@@ -199,10 +202,36 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec);
  *             prec)) is accepted, and the particles are then deposited in as many
  *             launches as needed.
  * Contributions are summed with device atomics: results are reproducible to
- * rounding, not bit-for-bit, across runs.
+ * rounding, not bit-for-bit, across runs (lw_deposit_td_det is).
  */
 lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom, void *E,
                         int64_t *diag, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * lw_deposit_td_det -- the deposit of lw_deposit_td (same Algorithm 2 with the
+ * interpolation of Sec. "Interpolation"), FP64, with a result that does not depend on
+ * the order in which the contributions reach a trace element: the same inputs give the
+ * same E bit for bit on every run, and so does any permutation of the particles.
+ * Two deposits compute the same contributions v: the first keeps max |v| per element
+ * (an order-free maximum), which sets a power-of-two scale s per trace row (pixel and
+ * component) with |v| s < 2^62; the second adds round(v s) to a 128-bit fixed-point
+ * integer per element, whose sum no ordering changes; each sum is then divided by s
+ * (one rounding).  The rounding of a contribution is at most 2^-62 of its row's largest
+ * contribution, so the result agrees with lw_deposit_td's FP64 sum to rounding.  About
+ * twice the time of the FP64 call.  A row that receives a non-finite contribution is
+ * NaN throughout.
+ *
+ * traj, grid, field_mask, diag, ws, ws_bytes: as for lw_deposit_td with LW_PREC_FP64
+ *             (LW_TRAJ_BORIS pushes the trajectories twice).
+ * geom:       LW_GEOM_EXACT or LW_GEOM_FARFIELD; LW_ACCUMULATE and LW_CULL are
+ *             refused (LW_E_ARG).
+ * E:          [n_pix][3][n_obs] double, overwritten.
+ * acc:        device buffer of acc_bytes >= lw_workspace_bytes(LW_WS_DEPOSIT_DET_ACC,
+ *             n_pix, n_obs, LW_PREC_FP64), 256-byte aligned, owned by the caller; its
+ *             contents on entry are ignored (LW_E_WORKSPACE if smaller or NULL).
+ */
+lw_status lw_deposit_td_det(const lw_traj_t *traj, const lw_grid_t *grid, int field_mask, int geom, double *E,
+                            int64_t *diag, void *acc, size_t acc_bytes, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * lw_spectrum_fft -- |E(w)|^2 of every pixel's trace on the FFT bins

@@ -116,7 +116,8 @@ size_t boris_plan_ws_bytes(const BorisPlan &p, int prec, bool bwd)
 }
 
 lw_status launch_deposit_boris(const lw_traj_t *t, const lw_grid_t *gr, int prec, int fmask, int geom,
-                               bool accumulate, void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s)
+                               bool accumulate, void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s,
+                               int acc_mode, DetAcc det)
 {
     const int64_t n_p = t->n_particles, ns = t->n_samples;
     if (n_p == 0 || gr->n_pix == 0) {  // nothing to push: only the trace and diag reset of the plain call
@@ -125,7 +126,8 @@ lw_status launch_deposit_boris(const lw_traj_t *t, const lw_grid_t *gr, int prec
         sub.span = 0;
         sub.n_particles = 0;
         sub.r = sub.beta = sub.beta_dot = nullptr;
-        return launch_deposit(&sub, gr, prec, fmask, geom, accumulate, E, diag, ws, ws_bytes, s);
+        return launch_deposit(&sub, gr, prec, fmask, geom, accumulate, E, diag, ws, ws_bytes, s, 0, nullptr, acc_mode,
+                              det);
     }
     const BorisPlan P = boris_plan_fit(n_p, ns, t->span, ws_bytes, prec);
     if (P.batch < 1 || (ns > 1 && P.span < 2)) return fail(LW_E_WORKSPACE, "lw_deposit_td: workspace holds no span");
@@ -160,7 +162,7 @@ lw_status launch_deposit_boris(const lw_traj_t *t, const lw_grid_t *gr, int prec
             sub.init = nullptr;
             sub.charge = t->charge ? t->charge + b0 : nullptr;
             st = launch_deposit(&sub, gr, prec, fmask, geom, accumulate || b0 > 0 || s0 > 0, E, diag, ws, dep_bytes,
-                                s, s0, rb2);
+                                s, s0, rb2, acc_mode, det);
             if (st != LW_OK) return st;
             if (s0 + n_span >= ns) break;
             s0 += n_span - 1;  // the next span starts at this span's last sample

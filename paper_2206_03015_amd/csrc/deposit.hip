@@ -274,7 +274,7 @@ __device__ __forceinline__ void tau_eval_block(const PixC &P, const double (*R)[
         // the highest power: cK, or c_LOW in kModeRecLow
         constexpr int TOP = MODE == kModeRecLow ? LOW - 1 : DEG - 1;
 #pragma unroll
-        for (int c = 0; c < NB; ++c) t[c] = MODE == kModeRecLow ? fma(b[c], R[c][LOW], R[c][LOW - 1])
+        for (int c = 0; c < NB; ++c) t[c] = MODE == kModeRecLow ? fma(b[c], R[c][LOW], R[c][LOW > 0 ? LOW - 1 : 0])
                                                                : fma(b[c], cK, R[c][DEG - 1]);
 #pragma unroll
         for (int j = TOP - 1; j >= 0; --j)
@@ -414,8 +414,8 @@ struct DepShape {
 // Per-wavefront state of the careful path (k_careful): lanes own pixels (kPPL each); a particle's
 // samples are taken one at a time, with the skip rules applied per interval; crossings are queued
 // in LDS and drained 64 at a time, each lane adding one interval's grid points to the trace with
-// global atomics.
-template <typename T, int GEOM>
+// global atomics (ACC: how a contribution is added to the trace).
+template <typename T, int GEOM, int ACC = kAccFloat>
 struct Wave {
     const double *__restrict__ r;
     const double *__restrict__ beta;
@@ -434,8 +434,29 @@ struct Wave {
     double2 *qt;       // the entry's arrival times {tau_{i-1}, tau_i}
     PixC pc[kPPL];     // constants of this lane's pixels (lane + 64 h)
     uint32_t qh, qn;   // queue ring head and length
+    DetAcc det;        // high words and row scales (ACC == kAccFixed)
 
     __device__ __forceinline__ static uint32_t qwrap(uint32_t v) { return v >= kQCap ? v - kQCap : v; }
+
+    // contribution v to element j of the trace, in the order-independent modes (FP64 only)
+    __device__ __forceinline__ void put_det(size_t j, size_t row, double v) const
+    {
+        unsigned long long *lo = (unsigned long long *)E + j;
+        if (ACC == kAccMaxAbs) {
+            atomicMax(lo, (unsigned long long)__double_as_longlong(fabs(v)));
+        } else {
+            // |v * scale| < 2^62 wherever scale is finite; the sign-extended term is added to the
+            // 128-bit sum as its low word and, with the carry out of the low word, its high word
+            const double t = v * det.scale[row];
+            const long long n = fabs(t) < 0x1p62 ? (long long)__builtin_rint(t) : 0ll;
+            if (n != 0) {
+                const unsigned long long un = (unsigned long long)n;
+                const unsigned long long old = atomicAdd(lo, un);
+                const long long dh = (n < 0 ? -1ll : 0ll) + (old + un < old ? 1ll : 0ll);
+                if (dh != 0) atomicAdd(det.hi + j, (unsigned long long)dh);
+            }
+        }
+    }
 
     using Lay = RecLayout<GEOM, sizeof(T) == 8>;
     // the part of a record a scan mode reads: offset and count of doubles
@@ -514,9 +535,16 @@ struct Wave {
                 T *Em = E + (size_t)m * 3 * sh.n_obs;
                 for (int u = u0; u < u1; ++u) {
                     const T w = (T)((double)u - ta) * idt, w1 = (T)1 - w;
-                    atomic_add(Em + u, w1 * eax + w * ebx);
-                    atomic_add(Em + sh.n_obs + u, w1 * eay + w * eby);
-                    atomic_add(Em + 2 * sh.n_obs + u, w1 * eaz + w * ebz);
+                    if constexpr (ACC == kAccFloat) {
+                        atomic_add(Em + u, w1 * eax + w * ebx);
+                        atomic_add(Em + sh.n_obs + u, w1 * eay + w * eby);
+                        atomic_add(Em + 2 * sh.n_obs + u, w1 * eaz + w * ebz);
+                    } else {
+                        const size_t row = (size_t)m * 3, j = row * sh.n_obs + u;
+                        put_det(j, row, w1 * eax + w * ebx);
+                        put_det(j + sh.n_obs, row + 1, w1 * eay + w * eby);
+                        put_det(j + 2 * sh.n_obs, row + 2, w1 * eaz + w * ebz);
+                    }
                 }
             }
         }
@@ -536,9 +564,16 @@ struct Wave {
             // 64-bit index: su1 may sit within 64 of the largest int (n_obs up to 2^31 - 1)
             for (int64_t u = (int64_t)su0 + lane; u < su1; u += 64) {
                 const T w = (T)((double)u - sta) * sidt, w1 = (T)1 - w;
-                atomic_add(Em + u, w1 * sax + w * sbx);
-                atomic_add(Em + sh.n_obs + u, w1 * say + w * sby);
-                atomic_add(Em + 2 * sh.n_obs + u, w1 * saz + w * sbz);
+                if constexpr (ACC == kAccFloat) {
+                    atomic_add(Em + u, w1 * sax + w * sbx);
+                    atomic_add(Em + sh.n_obs + u, w1 * say + w * sby);
+                    atomic_add(Em + 2 * sh.n_obs + u, w1 * saz + w * sbz);
+                } else {
+                    const size_t row = (size_t)(tile * kTilePix + sml) * 3, j = row * sh.n_obs + u;
+                    put_det(j, row, w1 * sax + w * sbx);
+                    put_det(j + sh.n_obs, row + 1, w1 * say + w * sby);
+                    put_det(j + 2 * sh.n_obs, row + 2, w1 * saz + w * sbz);
+                }
             }
         }
         // the entries are read: later pushes may take their slots
@@ -630,12 +665,12 @@ struct Wave {
 };
 
 // careful path: the particles the pre-pass flagged (a wavefront whose group holds none exits)
-template <typename T, int GEOM>
+template <typename T, int GEOM, int ACC>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_careful(
     const double *__restrict__ r, const double *__restrict__ beta, const double *__restrict__ beta_dot,
     const double *__restrict__ charge, const double *__restrict__ x_det, const double *__restrict__ rec,
     const double *__restrict__ pt, const int *__restrict__ pflag, const unsigned long long *__restrict__ rmax2,
-    const double *__restrict__ rbound2, T *__restrict__ E, unsigned long long *__restrict__ diag, DepShape sh)
+    const double *__restrict__ rbound2, T *__restrict__ E, unsigned long long *__restrict__ diag, DepShape sh, DetAcc det)
 {
     constexpr bool kF64 = sizeof(T) == 8;
     constexpr int kRec = kF64 ? kModeRec5 : kModeRec3;
@@ -658,7 +693,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     if (threadIdx.x < 4) red[threadIdx.x] = 0ull;
     __syncthreads();
 
-    Wave<T, GEOM> w;
+    Wave<T, GEOM, ACC> w;
     int64_t m[kPPL];
     bool pix_in[kPPL], lane_ok[kPPL];
     double id2 = 0.0, s2 = 0.0;
@@ -699,6 +734,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     w.rec = rec;
     w.pt = pt;
     w.E = E;
+    if constexpr (ACC != kAccFloat) w.det = det;
     w.sh = sh;
     w.lane = lane;
     w.tile = tile;
@@ -740,7 +776,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
 // Fast path.  Lanes over samples: lane j of chunk q holds sample 63 q + j (chunks share their
 // boundary sample, so interval (63 q + j - 1, 63 q + j] has both ends in chunk q for j >= 1).
 
-template <typename T, int GEOM>
+template <typename T, int GEOM, int ACC = kAccFloat>
 struct ScanWave {
     static constexpr bool F64 = sizeof(T) == 8;
     using Lay = RecLayout<GEOM, F64>;
@@ -748,7 +784,7 @@ struct ScanWave {
     // values that live through the whole kernel in scratch (36 bytes, reloaded once per particle);
     // still faster than two chunks: 1124 against 1141 ms on 1e4 electrons of the precision workload
     static constexpr int NB = 3;
-    Wave<T, GEOM> d;       // queue and drain (shared with the careful path)
+    Wave<T, GEOM, ACC> d;  // queue and drain (shared with the careful path)
     double *pcl;           // LDS: o, px, py, g of the tile's pixels, [kTilePix + 1][4] (one padding row);
                            // g: the pixel's next grid point above the arrival times scanned so far
     uint64_t okmask[kPPL]; // pixels 64 h + l of the tile that take part (in the pass, geometry ok)
@@ -950,12 +986,12 @@ struct ScanWave {
     }
 };
 
-template <typename T, int GEOM, bool CULL>
+template <typename T, int GEOM, bool CULL, int ACC>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_scan(
     const double *__restrict__ r, const double *__restrict__ beta, const double *__restrict__ beta_dot,
     const double *__restrict__ charge, const double *__restrict__ x_det, const double *__restrict__ rec,
     const double *__restrict__ pt, const int *__restrict__ pflag, const unsigned long long *__restrict__ rmax2,
-    const double *__restrict__ rbound2, T *__restrict__ E, unsigned long long *__restrict__ diag, DepShape sh)
+    const double *__restrict__ rbound2, T *__restrict__ E, unsigned long long *__restrict__ diag, DepShape sh, DetAcc det)
 {
     constexpr bool kF64 = sizeof(T) == 8;
     constexpr int kRec = kF64 ? kModeRec5 : kModeRec3;
@@ -975,8 +1011,8 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     const int64_t k0 = grp * sh.parts_per_group;
     const int64_t k1 = grp < sh.n_groups ? std::min(k0 + sh.parts_per_group, sh.n_particles) : k0;
 
-    ScanWave<T, GEOM> w;
-    Wave<T, GEOM> &d = w.d;
+    ScanWave<T, GEOM, ACC> w;
+    Wave<T, GEOM, ACC> &d = w.d;
     bool pix_in[kPPL];
     double id2 = 0.0, s2 = 0.0;
     const double Dref = pix_geo(x_det, 0).D;  // the records' pixel distance
@@ -1024,6 +1060,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     d.rec = rec;
     d.pt = pt;
     d.E = E;
+    if constexpr (ACC != kAccFloat) d.det = det;
     d.sh = sh;
     d.lane = lane;
     d.tile = tile;
@@ -1062,6 +1099,57 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     if (diag && threadIdx.x < 4 && red[threadIdx.x]) atomicAdd(diag + threadIdx.x, red[threadIdx.x]);
 }
 
+// Row scales of the fixed-point pass from the first pass's max |v| per element (bits of a
+// non-negative double): scale = 2^(62 - e) where max < 2^e, so every |v| * scale < 2^62.  A row
+// that received nothing takes 1; a row with a non-finite contribution takes NaN and is NaN in the
+// result.
+__global__ __launch_bounds__(256) void k_det_scale(const unsigned long long *__restrict__ mx, int64_t n_rows,
+                                                   int64_t n_obs, double *__restrict__ scale)
+{
+    __shared__ unsigned long long red[256];
+    for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
+        const unsigned long long *p = mx + (size_t)row * (size_t)n_obs;
+        unsigned long long v = 0;
+        for (int64_t u = threadIdx.x; u < n_obs; u += 256) v = p[u] > v ? p[u] : v;
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h && red[threadIdx.x + h] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const double M = __longlong_as_double((long long)red[0]);
+            double sc = 1.0;
+            if (!isfinite(M)) {
+                sc = NAN;
+            } else if (M > 0.0) {
+                int e;
+                frexp(M, &e);
+                sc = ldexp(1.0, 62 - e < 1023 ? 62 - e : 1023);
+            }
+            scale[row] = sc;
+        }
+        __syncthreads();
+    }
+}
+
+// The 128-bit sums (low words in E, high words in hi) to doubles, in place, then divided by the
+// row's power of two.  A sum that fits in 64 bits converts with one rounding; a larger one is
+// hi 2^64 + lo through the fma, where the rounding of lo (at most 2^10) is at most half an ulp of
+// the result (|result| >= 2^63): at most one ulp in all.
+__global__ __launch_bounds__(256) void k_det_finish(double *__restrict__ E, const unsigned long long *__restrict__ hi,
+                                                    const double *__restrict__ scale, int64_t n_rows, int64_t n_obs)
+{
+    const size_t n = (size_t)n_rows * (size_t)n_obs;
+    for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (size_t)gridDim.x * blockDim.x) {
+        const double sc = scale[j / (size_t)n_obs];
+        const unsigned long long lo = (unsigned long long)__double_as_longlong(E[j]);
+        const long long h = (long long)hi[j], sl = (long long)lo;
+        const double v = h == (sl < 0 ? -1ll : 0ll) ? (double)sl : fma((double)h, 0x1p64, (double)lo);
+        E[j] = isnan(sc) ? NAN : v * (1.0 / sc);
+    }
+}
+
 template <int GEOM>
 void launch_prepass(bool f64, dim3 grid, hipStream_t s, const double *r, const double *b, const double *bd,
                     const double *x_det, int64_t ns, int64_t sample0, double t_start, double dt, double t0,
@@ -1077,6 +1165,40 @@ void launch_prepass(bool f64, dim3 grid, hipStream_t s, const double *r, const d
 
 }  // namespace
 
+size_t det_acc_bytes(int64_t n_pix, int64_t n_obs)
+{
+    return align_up((size_t)n_pix * 3 * (size_t)n_obs * 8, 256) + align_up((size_t)n_pix * 3 * 8, 256);
+}
+
+// Two deposits with the same per-contribution values: the first finds max |v| per trace element,
+// the second adds the contributions as 128-bit fixed-point integers scaled per row by the first's
+// maximum; the integer sums do not depend on the order in which the atomics land.
+lw_status launch_deposit_det(const lw_traj_t *t, const lw_grid_t *gr, int fmask, int geom, double *E, int64_t *diag,
+                             void *acc, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    const int64_t rows = gr->n_pix * 3, n_obs = gr->n_obs;
+    const size_t n_el = (size_t)rows * (size_t)n_obs;
+    double *scale = (double *)((char *)acc + align_up(n_el * 8, 256));
+    const DetAcc det{(unsigned long long *)acc, scale};
+    const bool boris = t->kind == LW_TRAJ_BORIS;
+    auto pass = [&](int mode, int64_t *dg) {
+        return boris ? launch_deposit_boris(t, gr, LW_PREC_FP64, fmask, geom, false, E, dg, ws, ws_bytes, s, mode, det)
+                     : launch_deposit(t, gr, LW_PREC_FP64, fmask, geom, false, E, dg, ws, ws_bytes, s, 0, nullptr, mode,
+                                      det);
+    };
+    if (n_el == 0) return pass(kAccFixed, diag);  // nothing to deposit: the diag reset only
+    lw_status st = pass(kAccMaxAbs, nullptr);
+    if (st != LW_OK) return st;
+    k_det_scale<<<(unsigned)std::min<int64_t>(rows, 65536), 256, 0, s>>>((const unsigned long long *)E, rows, n_obs,
+                                                                        scale);
+    const unsigned blocks = (unsigned)std::min<size_t>((n_el + 255) / 256, 65536);
+    k_fill<unsigned long long><<<blocks, 256, 0, s>>>(det.hi, (int64_t)n_el);
+    if ((st = check_launch("lw_deposit_td_det")) != LW_OK) return st;
+    if ((st = pass(kAccFixed, diag)) != LW_OK) return st;
+    k_det_finish<<<blocks, 256, 0, s>>>(E, det.hi, scale, rows, n_obs);
+    return check_launch("lw_deposit_td_det");
+}
+
 size_t deposit_ws_bytes(int64_t n_particles, int64_t n_samples, int prec)
 {
     return ws_bytes_for(n_particles, n_samples, rec_width(LW_GEOM_EXACT, prec == LW_PREC_FP64));
@@ -1084,13 +1206,15 @@ size_t deposit_ws_bytes(int64_t n_particles, int64_t n_samples, int prec)
 
 lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int fmask, int geom, bool accumulate,
                          void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s, int64_t sample0,
-                         const double *rbound2)
+                         const double *rbound2, int acc_mode, DetAcc det)
 {
     const int64_t n_p = t->n_particles, ns = t->n_samples, n_pix = gr->n_pix, n_obs = gr->n_obs;
     const bool cull = (geom & LW_CULL) != 0;
     geom &= ~LW_CULL;
     const size_t trace_elems = (size_t)n_pix * 3 * (size_t)n_obs;
     const bool f64 = prec == LW_PREC_FP64;
+    if (acc_mode != kAccFloat && (!f64 || cull))
+        return fail(LW_E_UNSUPPORTED, "lw_deposit_td_det: FP64 without culling only");
     if (n_obs > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: n_obs must be below 2^31");
     if (ns > 0x7fffffff) return fail(LW_E_SHAPE, "lw_deposit_td: too many samples");
     if (!accumulate) {
@@ -1121,6 +1245,9 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
         const double *xd = gr->x_det + 3 * m0;
         void *Ep = f64 ? (void *)((double *)E + (size_t)m0 * 3 * (size_t)n_obs)
                        : (void *)((float *)E + (size_t)m0 * 3 * (size_t)n_obs);
+        // the pass's rows of the order-independent accumulators
+        const DetAcc dp{det.hi ? det.hi + (size_t)m0 * 3 * (size_t)n_obs : nullptr,
+                        det.scale ? det.scale + (size_t)m0 * 3 : nullptr};
         for (int64_t p0 = 0; p0 < n_p; p0 += chunk) {
             const int64_t np = std::min<int64_t>(chunk, n_p - p0);
             DepShape sh;
@@ -1162,12 +1289,32 @@ lw_status launch_deposit(const lw_traj_t *t, const lw_grid_t *gr, int prec, int 
                                                  gr->dt_obs, C, w);
             unsigned long long *dg = (unsigned long long *)diag;
             const dim3 grid((unsigned)blocks), block(kBlockThreads);
+            if (acc_mode != kAccFloat) {
+#define LW_DET_LAUNCH(G, A)                                                                                          \
+    do {                                                                                                             \
+        k_scan<double, G, false, A><<<grid, block, 0, s>>>(r, b, bd, charge, xd, w.rec, w.pt, w.pflag, w.rmax2, rb2,  \
+                                                           (double *)Ep, dg, sh, dp);                                \
+        k_careful<double, G, A><<<grid, block, 0, s>>>(r, b, bd, charge, xd, w.rec, w.pt, w.pflag, w.rmax2, rb2,      \
+                                                       (double *)Ep, dg, sh, dp);                                    \
+    } while (0)
+                if (geom == LW_GEOM_EXACT) {
+                    if (acc_mode == kAccMaxAbs) LW_DET_LAUNCH(LW_GEOM_EXACT, kAccMaxAbs); else LW_DET_LAUNCH(LW_GEOM_EXACT, kAccFixed);
+                } else {
+                    if (acc_mode == kAccMaxAbs) LW_DET_LAUNCH(LW_GEOM_FARFIELD, kAccMaxAbs); else LW_DET_LAUNCH(LW_GEOM_FARFIELD, kAccFixed);
+                }
+#undef LW_DET_LAUNCH
+                const lw_status st = check_launch("lw_deposit_td_det");
+                if (st != LW_OK) return st;
+                continue;
+            }
             // the fast path (timed as the deposit kernel), then the careful path; culling is a
             // separate instantiation of the fast path, so the full evaluation carries none of its code
-#define LW_SCAN_LAUNCH(T, G, CU) \
-    k_scan<T, G, CU><<<grid, block, 0, s>>>(r, b, bd, charge, xd, w.rec, w.pt, w.pflag, w.rmax2, rb2, (T *)Ep, dg, sh)
-#define LW_CAREFUL_LAUNCH(T, G) \
-    k_careful<T, G><<<grid, block, 0, s>>>(r, b, bd, charge, xd, w.rec, w.pt, w.pflag, w.rmax2, rb2, (T *)Ep, dg, sh)
+#define LW_SCAN_LAUNCH(T, G, CU)                                                                                  \
+    k_scan<T, G, CU, kAccFloat><<<grid, block, 0, s>>>(r, b, bd, charge, xd, w.rec, w.pt, w.pflag, w.rmax2, rb2,      \
+                                                       (T *)Ep, dg, sh, DetAcc{nullptr, nullptr})
+#define LW_CAREFUL_LAUNCH(T, G)                                                                                   \
+    k_careful<T, G, kAccFloat><<<grid, block, 0, s>>>(r, b, bd, charge, xd, w.rec, w.pt, w.pflag, w.rmax2, rb2,       \
+                                                      (T *)Ep, dg, sh, DetAcc{nullptr, nullptr})
             hipEvent_t ev = timing_begin(LW_KERNEL_DEPOSIT, s);
             if (f64) {
                 if (geom == LW_GEOM_EXACT) {

@@ -222,15 +222,18 @@ size_t lw_workspace_bytes(int which, int64_t n_a, int64_t n_b, int prec)
     case LW_WS_DEPOSIT_BWD_BORIS:
         return n_b >= 1 ? boris_plan_ws_bytes(boris_plan_default(n_a, n_b, LW_PREC_FP64, true), LW_PREC_FP64, true)
                         : 0;
+    case LW_WS_DEPOSIT_DET_ACC:
+        return n_a >= 0 && n_b >= 0 ? det_acc_bytes(n_a, n_b) : 0;
     default:
         return 0;
     }
 }
 
-lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom, void *E,
-                        int64_t *diag, void *ws, size_t ws_bytes, hipStream_t stream)
+// lw_deposit_td and lw_deposit_td_det (acc != nullptr: the order-independent FP64 deposit)
+static lw_status deposit_entry(const char *fn, const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask,
+                               int geom, void *E, int64_t *diag, void *acc, size_t acc_bytes, void *ws,
+                               size_t ws_bytes, hipStream_t stream)
 {
-    const char *fn = "lw_deposit_td";
     const bool boris = traj && traj->kind == LW_TRAJ_BORIS;
     lw_status st = boris ? check_traj_boris(traj, fn, true) : check_traj_samples(traj, fn);
     if (st != LW_OK) return st;
@@ -238,7 +241,7 @@ lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, 
     if (prec != LW_PREC_FP64 && prec != LW_PREC_MIXED) return fail(LW_E_ARG, "%s: unknown prec %d", fn, prec);
     if (field_mask <= 0 || (field_mask & ~(LW_FIELD_ACCEL | LW_FIELD_VELOCITY)))
         return fail(LW_E_ARG, "%s: field_mask must be a non-empty combination of LW_FIELD_*", fn);
-    const bool acc = (geom & LW_ACCUMULATE) != 0;
+    const bool accum = (geom & LW_ACCUMULATE) != 0;
     const int g = geom & ~(LW_ACCUMULATE | LW_CULL);
     if (g != LW_GEOM_EXACT && g != LW_GEOM_FARFIELD) return fail(LW_E_ARG, "%s: unknown geometry %d", fn, g);
     const int gc = g | (geom & LW_CULL);  // geometry and culling for the launchers
@@ -248,6 +251,14 @@ lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, 
     if (grid->n_pix > (int64_t(1) << 31) || traj->n_particles > (int64_t(1) << 40))
         return fail(LW_E_SHAPE, "%s: too many pixels or particles", fn);
     if (ws && !aligned(ws, 256)) return fail(LW_E_ALIGN, "%s: workspace must be 256-byte aligned", fn);
+    const bool det = acc_bytes > 0 || acc;
+    if (det) {
+        if (geom & (LW_ACCUMULATE | LW_CULL)) return fail(LW_E_ARG, "%s: LW_ACCUMULATE and LW_CULL are not taken", fn);
+        const size_t need = det_acc_bytes(grid->n_pix, grid->n_obs);
+        if (!acc || acc_bytes < need)
+            return fail(LW_E_WORKSPACE, "%s: accumulator buffer of %zu bytes < %zu needed", fn, acc_bytes, need);
+        if (!aligned(acc, 256)) return fail(LW_E_ALIGN, "%s: accumulator buffer must be 256-byte aligned", fn);
+    }
     if (boris) {
         const bool work = traj->n_particles > 0 && grid->n_pix > 0;
         const BorisPlan plan = boris_plan_fit(traj->n_particles, traj->n_samples, traj->span, ws_bytes, prec);
@@ -255,14 +266,31 @@ lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, 
         if (work && (!ws || plan.batch < 1 || plan.span < lmin))
             return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes holds no span (one particle needs %zu)", fn,
                         ws_bytes, boris_plan_ws_bytes(BorisPlan{1, traj->span > 0 ? traj->span : lmin}, prec));
-        return launch_deposit_boris(traj, grid, prec, field_mask, gc, acc, E, diag, ws, ws_bytes, stream);
+        if (det) return launch_deposit_det(traj, grid, field_mask, g, (double *)E, diag, acc, ws, ws_bytes, stream);
+        return launch_deposit_boris(traj, grid, prec, field_mask, gc, accum, E, diag, ws, ws_bytes, stream);
     }
     // any workspace that holds one particle's records is accepted (the particles are then taken
     // in chunks); lw_workspace_bytes gives the size that takes them all at once
     const size_t need = deposit_ws_bytes(1, traj->n_samples, prec);
     if (traj->n_particles > 0 && grid->n_pix > 0 && (!ws || ws_bytes < need))
         return fail(LW_E_WORKSPACE, "%s: workspace of %zu bytes < %zu needed", fn, ws_bytes, need);
-    return launch_deposit(traj, grid, prec, field_mask, gc, acc, E, diag, ws, ws_bytes, stream);
+    if (det) return launch_deposit_det(traj, grid, field_mask, g, (double *)E, diag, acc, ws, ws_bytes, stream);
+    return launch_deposit(traj, grid, prec, field_mask, gc, accum, E, diag, ws, ws_bytes, stream);
+}
+
+lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom, void *E,
+                        int64_t *diag, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    return deposit_entry("lw_deposit_td", traj, grid, prec, field_mask, geom, E, diag, nullptr, 0, ws, ws_bytes,
+                         stream);
+}
+
+lw_status lw_deposit_td_det(const lw_traj_t *traj, const lw_grid_t *grid, int field_mask, int geom, double *E,
+                            int64_t *diag, void *acc, size_t acc_bytes, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!acc && acc_bytes == 0) return fail(LW_E_WORKSPACE, "lw_deposit_td_det: no accumulator buffer");
+    return deposit_entry("lw_deposit_td_det", traj, grid, LW_PREC_FP64, field_mask, geom, E, diag, acc, acc_bytes, ws,
+                         ws_bytes, stream);
 }
 
 lw_status lw_spectrum_fft(const void *E, int64_t n_pix, int64_t n_obs, double dt_obs, int prec, void *S, void *ws,

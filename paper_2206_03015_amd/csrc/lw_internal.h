@@ -405,6 +405,18 @@ __device__ __forceinline__ bool sample_usable(const double *r, const double *b, 
 __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
+// How the deposit adds a contribution v to trace element j.  kAccFloat: a floating-point atomic
+// add (the result depends on the order of arrival in its last bits).  The two modes of the
+// order-independent FP64 deposit: kAccMaxAbs keeps max |v| per element (as the bits of a
+// non-negative double, which order like unsigned integers); kAccFixed adds round(v * scale[row])
+// to a 128-bit two's-complement fixed-point sum per element, low words in the trace, high words
+// in DetAcc::hi.  Integer sums do not depend on the order of their terms.
+enum { kAccFloat = 0, kAccMaxAbs = 1, kAccFixed = 2 };
+struct DetAcc {
+    unsigned long long *hi;  // [n_pix][3][n_obs] high words (kAccFixed)
+    const double *scale;     // [n_pix][3] power of two per trace row (kAccFixed)
+};
+
 // host-side launch helpers (defined in the kernel files)
 // sample0: index of the first sample of traj within a longer trajectory (its arrival times use
 // t_start + (sample0 + i) dt); 0 for whole trajectories.  rbound2: per particle, max |r|^2 over
@@ -412,7 +424,13 @@ __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAd
 // of the arrival time per particle and pixel.
 lw_status launch_deposit(const lw_traj_t *traj, const lw_grid_t *grid, int prec, int field_mask, int geom,
                          bool accumulate, void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s,
-                         int64_t sample0 = 0, const double *rbound2 = nullptr);
+                         int64_t sample0 = 0, const double *rbound2 = nullptr, int acc_mode = kAccFloat,
+                         DetAcc det = DetAcc{nullptr, nullptr});
+// lw_deposit_td_det: FP64 deposit whose result does not depend on the order of the contributions
+// (acc: the high words and row scales, det_acc_bytes(n_pix, n_obs) bytes)
+lw_status launch_deposit_det(const lw_traj_t *traj, const lw_grid_t *grid, int field_mask, int geom, double *E,
+                             int64_t *diag, void *acc, void *ws, size_t ws_bytes, hipStream_t s);
+size_t det_acc_bytes(int64_t n_pix, int64_t n_obs);
 // workspace of a deposit launch that holds the records of all its particles (a smaller one makes
 // it process the particles in chunks)
 size_t deposit_ws_bytes(int64_t n_particles, int64_t n_samples, int prec);
@@ -462,7 +480,8 @@ BorisPlan boris_plan_default(int64_t n_p, int64_t ns, int prec, bool bwd = false
 BorisPlan boris_plan_fit(int64_t n_p, int64_t ns, int64_t span_req, size_t ws_bytes, int prec, bool bwd = false);
 size_t boris_plan_ws_bytes(const BorisPlan &p, int prec, bool bwd = false);
 lw_status launch_deposit_boris(const lw_traj_t *t, const lw_grid_t *gr, int prec, int fmask, int geom,
-                               bool accumulate, void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s);
+                               bool accumulate, void *E, int64_t *diag, void *ws, size_t ws_bytes, hipStream_t s,
+                               int acc_mode = kAccFloat, DetAcc det = DetAcc{nullptr, nullptr});
 lw_status launch_deposit_bwd_boris(const lw_traj_t *t, const lw_grid_t *gr, int fmask, int geom, const double *dE,
                                    double *grad_init, double *grad_a0, void *ws, size_t ws_bytes, hipStream_t s);
 

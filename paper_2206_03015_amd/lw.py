@@ -26,7 +26,7 @@ CULL = 1 << 9
 TRAJ_SAMPLES = 0
 TRAJ_BORIS = 1
 WS_DEPOSIT, WS_FFT, WS_DIRECT_FD, WS_DEPOSIT_BWD, WS_FFT_BWD, WS_DIRECT_FD_BWD = 1, 2, 3, 4, 5, 6
-WS_DEPOSIT_BORIS, WS_DEPOSIT_BWD_BORIS = 7, 8
+WS_DEPOSIT_BORIS, WS_DEPOSIT_BWD_BORIS, WS_DEPOSIT_DET_ACC = 7, 8, 9
 KERNEL_DEPOSIT, KERNEL_DEPOSIT_BWD, KERNEL_BORIS_TANGENT = 1, 2, 3
 
 c_d = ctypes.c_double
@@ -70,6 +70,8 @@ _SIGS = {
                                            ctypes.c_size_t, c_vp]),
     "lw_deposit_td_bwd": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "lw_deposit_td_det": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_int,
+                                         c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp, ctypes.c_size_t, c_vp]),
     "lw_deposit_td_bwd_boris": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_int,
                                                ctypes.c_int, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "lw_direct_fd_bwd": (ctypes.c_int, [ctypes.POINTER(Traj), ctypes.POINTER(Grid), c_vp, c_i64, ctypes.c_int,
@@ -194,6 +196,46 @@ def deposit_td(r, beta, beta_dot, t_start, dt, x_det, t0, dt_obs, n_obs, prec="m
     _check(lib.lw_deposit_td(ctypes.byref(tr), ctypes.byref(gr), PREC[prec], int(field_mask), flags, _ptr(out),
                              _ptr(diag), _ptr(ws), ws.numel(), _stream()))
     return out, diag
+
+
+def _deposit_det(tr, gr, device, ws_need, field_mask, geom, out, diag, ws, acc):
+    lib = load()
+    if out is None:
+        out = torch.empty((gr.n_pix, 3, gr.n_obs), dtype=torch.float64, device=device)
+    _need(out, torch.float64, (gr.n_pix, 3, gr.n_obs), "E")
+    if diag is None:
+        diag = torch.zeros(4, dtype=torch.int64, device=device)
+    if ws is None:
+        ws = _workspace(ws_need, device)
+    if acc is None:
+        acc = _workspace(workspace_bytes(WS_DEPOSIT_DET_ACC, gr.n_pix, gr.n_obs, "fp64"), device)
+    _check(lib.lw_deposit_td_det(ctypes.byref(tr), ctypes.byref(gr), int(field_mask), GEOM[geom], _ptr(out),
+                                 _ptr(diag), _ptr(acc), acc.numel(), _ptr(ws), ws.numel(), _stream()))
+    return out, diag
+
+
+def deposit_td_det(r, beta, beta_dot, t_start, dt, x_det, t0, dt_obs, n_obs, field_mask=FIELD_ACCEL, geom="exact",
+                   charge=None, out=None, diag=None, ws=None, acc=None):
+    """lw_deposit_td_det: the FP64 deposit, the same bits on every run and for any particle order.
+    Returns (E [n_pix][3][n_obs] float64, diag int64[4])."""
+    tr = make_traj(r, beta, beta_dot, t_start, dt, charge)
+    gr = make_grid(x_det, t0, dt_obs, n_obs)
+    need = workspace_bytes(WS_DEPOSIT, tr.n_particles, tr.n_samples, "fp64")
+    return _deposit_det(tr, gr, r.device, need, field_mask, geom, out, diag, ws, acc)
+
+
+def deposit_td_det_boris(init, n_samples, t_start, dt, a0, lam, w0, n_cycles, x_det, t0, dt_obs, n_obs,
+                         field_mask=FIELD_ACCEL, geom="exact", charge=None, out=None, diag=None, ws=None, acc=None,
+                         span=0):
+    """lw_deposit_td_det with LW_TRAJ_BORIS (trajectories pushed inside the call, twice)."""
+    tr = make_boris_traj(init, n_samples, t_start, dt, a0, lam, w0, n_cycles)
+    tr.span = int(span)
+    if charge is not None:
+        _need(charge, torch.float64, (int(init.shape[0]),), "charge")
+        tr.charge = c_vp(charge.data_ptr())
+    gr = make_grid(x_det, t0, dt_obs, n_obs)
+    need = workspace_bytes(WS_DEPOSIT_BORIS, tr.n_particles, tr.n_samples, "fp64")
+    return _deposit_det(tr, gr, init.device, need, field_mask, geom, out, diag, ws, acc)
 
 
 def spectrum_fft(E, dt_obs, prec=None, out=None, ws=None):

@@ -62,6 +62,9 @@ def test_workspace_sizes(lib):
     assert lw.workspace_bytes(lw.WS_DEPOSIT_BWD_BORIS, 10, 1000) >= 10 * 1000 * 144
     assert 15.5 * 2**30 < lw.workspace_bytes(lw.WS_DEPOSIT_BWD_BORIS, 100000, 20001) < 16.5 * 2**30
     assert lib.lw_workspace_bytes(999, 1, 1, 0) == 0
+    # order-independent deposit: a high word per trace element and a scale per trace row
+    assert lw.workspace_bytes(lw.WS_DEPOSIT_DET_ACC, 7, 64, "fp64") >= 7 * 3 * 64 * 8 + 7 * 3 * 8
+    assert lw.workspace_bytes(lw.WS_DEPOSIT_DET_ACC, -1, 64, "fp64") == 0
 
 
 def test_host_validation_rejects_bad_arguments(lib):
@@ -138,6 +141,17 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert b"span" in lib.lw_last_error()
     # the deposit adjoint takes spans too: span 2 passes, the missing workspace is reported
     assert lib.lw_deposit_td_bwd_boris(ctypes.byref(tb), ctypes.byref(gr), 0, 1, 0, p, p, p, None, 0, None) == -4
+    # lw_deposit_td_det: an accumulator buffer of the documented size, no accumulate or cull flag
+    need = lw.workspace_bytes(lw.WS_DEPOSIT_DET_ACC, gr.n_pix, gr.n_obs, "fp64")
+    det = lib.lw_deposit_td_det
+    assert det(ctypes.byref(tr), ctypes.byref(gr), 1, 0, p, None, None, 0, p, 1 << 20, None) == -4
+    assert b"no accumulator" in lib.lw_last_error()
+    assert det(ctypes.byref(tr), ctypes.byref(gr), 1, 0, p, None, p, need - 8, p, 1 << 20, None) == -4
+    assert det(ctypes.byref(tr), ctypes.byref(gr), 1, 0, p, None, ctypes.c_void_p(264), need, p, 1 << 20, None) == -3
+    for flags in (lw.ACCUMULATE, lw.CULL):
+        assert det(ctypes.byref(tr), ctypes.byref(gr), 1, flags, p, None, p, need, p, 1 << 20, None) == -1
+        assert b"not taken" in lib.lw_last_error()
+    assert det(None, ctypes.byref(gr), 1, 0, p, None, p, need, p, 1 << 20, None) == -1
     tb.span = 1
     assert lib.lw_deposit_td_bwd_boris(ctypes.byref(tb), ctypes.byref(gr), 0, 1, 0, p, p, p, None, 0, None) == -1
     assert lib.lw_version().startswith(b"liblw")

@@ -1,0 +1,120 @@
+"""lw_deposit_td_det, the FP64 deposit whose sum does not depend on the order of its terms.
+
+Bit for bit: repeated calls, reversed and shuffled particle orders, garbage left in the
+accumulator buffer, and (trajectories pushed inside the call) any span length give the same E.
+Against the FP64 oracle at the FP64 deposit's tolerance (max |E - E_oracle| <= 1e-9
+max |E_oracle|), with identical counters; against lw_deposit_td in FP64 to 1e-13 of max |E| (the
+two differ by the rounding of the sums: float additions in arrival order against one rounding
+of an exact fixed-point sum whose terms are rounded to 2^-62 of their row's largest term)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from cases import small_bunch, synthetic
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def T(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV)
+
+
+def bits(E):
+    return E.cpu().numpy().view(np.uint64)
+
+
+def det_samples(c, geom="exact", field_mask=1, charge=None, perm=None, acc=None):
+    from paper_2206_03015_amd import lw
+    idx = np.arange(c["r"].shape[0]) if perm is None else perm
+    ch = None if charge is None else T(charge[idx])
+    E, diag = lw.deposit_td_det(T(c["r"][idx]), T(c["beta"][idx]), T(c["beta_dot"][idx]), c["t_start"], c["dt"],
+                                T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], field_mask=field_mask, geom=geom,
+                                charge=ch, acc=acc)
+    torch.cuda.synchronize()
+    return E, diag.cpu().numpy()
+
+
+@pytest.mark.parametrize("geom", ["exact", "farfield"])
+@pytest.mark.parametrize("field_mask", [1, 3])
+def test_det_matches_oracle_and_fp64_deposit(geom, field_mask):
+    """24 Boris-pushed electrons, 10x10 pixels (two tiles, ragged), 2^12 grid points."""
+    from paper_2206_03015_amd import lw
+    c = small_bunch()
+    E, d = det_samples(c, geom, field_mask)
+    Eo, do = oracle.deposit_td(c["t_start"], c["dt"], c["r"], c["beta"], c["beta_dot"], c["x_det"], c["t0"],
+                               c["dt_obs"], c["n_obs"], field_mask=field_mask,
+                               geom=oracle.GEOM_EXACT if geom == "exact" else oracle.GEOM_FARFIELD)
+    En = E.cpu().numpy()
+    scale = np.max(np.abs(Eo))
+    err = np.max(np.abs(En - Eo)) / scale
+    print(f"det vs oracle: max rel err {err:.3e}")
+    assert err <= 1e-9
+    assert d.tolist() == list(do)
+    Ef, df = lw.deposit_td(T(c["r"]), T(c["beta"]), T(c["beta_dot"]), c["t_start"], c["dt"], T(c["x_det"]), c["t0"],
+                           c["dt_obs"], c["n_obs"], prec="fp64", field_mask=field_mask, geom=geom)
+    torch.cuda.synchronize()
+    dev = np.max(np.abs(En - Ef.cpu().numpy())) / scale
+    print(f"det vs FP64 deposit: {dev:.3e}")
+    assert dev <= 1e-13
+    assert df.cpu().numpy().tolist() == d.tolist()
+
+
+@pytest.mark.parametrize("case", ["bunch", "synthetic_charges"])
+def test_det_same_bits_for_any_order(case):
+    """Three calls, the particles reversed and shuffled, and an accumulator buffer full of 0xff
+    bytes on entry: every E has the same bits."""
+    from paper_2206_03015_amd import lw
+    if case == "bunch":
+        c, fm, ch = small_bunch(n_p=48, n_steps=2000), 1, None
+    else:
+        c = synthetic(n_p=40, n_pix=70, n_obs=600)
+        fm, ch = 3, c["charge"]
+    n_p = c["r"].shape[0]
+    ref, dref = det_samples(c, field_mask=fm, charge=ch)
+    ref = bits(ref)
+    assert np.any(ref != 0)
+    rng = np.random.default_rng(11)
+    junk = torch.full((lw.workspace_bytes(lw.WS_DEPOSIT_DET_ACC, c["x_det"].shape[0], c["n_obs"], "fp64"),), 255,
+                      dtype=torch.uint8, device=DEV)
+    for perm, acc in ((None, None), (np.arange(n_p)[::-1].copy(), None), (rng.permutation(n_p), junk)):
+        E, d = det_samples(c, field_mask=fm, charge=ch, perm=perm, acc=acc)
+        assert np.array_equal(bits(E), ref)
+        assert d.tolist() == dref.tolist()
+
+
+@pytest.mark.parametrize("span", [0, 2, 97])
+def test_det_boris_same_bits_for_any_span(span):
+    """Trajectories pushed inside the call: every span length (and several batches) gives the
+    bits of span 0 with one batch, and the result matches the oracle on the stored samples."""
+    from paper_2206_03015_amd import lw
+    c = small_bunch(n_p=24, n_steps=3000, n_side=10, n_obs=1 << 12)
+    W, L = c["W"], c["W"].laser
+    init = T(c["init"])
+    args = (W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
+    E0, d0 = lw.deposit_td_det_boris(init, *args, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"])
+    ws = None
+    if span:
+        need = lw.workspace_bytes(lw.WS_DEPOSIT_BORIS, 7, W.n_samples, "fp64")  # batches of at most 7
+        ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+    E1, d1 = lw.deposit_td_det_boris(init, *args, T(c["x_det"]), c["t0"], c["dt_obs"], c["n_obs"], ws=ws, span=span)
+    torch.cuda.synchronize()
+    assert np.array_equal(bits(E1), bits(E0))
+    assert d1.cpu().numpy().tolist() == d0.cpu().numpy().tolist()
+    Eo, do = oracle.deposit_td(W.t_start, W.dt, c["r"], c["beta"], c["beta_dot"], c["x_det"], c["t0"], c["dt_obs"],
+                               c["n_obs"])
+    assert np.max(np.abs(E0.cpu().numpy() - Eo)) <= 1e-9 * np.max(np.abs(Eo))
+    assert d0.cpu().numpy().tolist() == list(do)
+
+
+def test_det_degenerate_sizes():
+    """No particles: E is zero and diag is reset.  An observer window after every arrival:
+    nothing is deposited and every row (scale 1) is zero."""
+    c = synthetic(n_p=5, n_pix=70, n_obs=600)
+    empty = dict(c, r=c["r"][:0], beta=c["beta"][:0], beta_dot=c["beta_dot"][:0])
+    E, d = det_samples(empty)
+    assert not np.any(bits(E)) and d.tolist() == [0, 0, 0, 0]
+    far = dict(c, t0=c["t0"] + 1e-9)
+    E, d = det_samples(far)
+    assert not np.any(bits(E)) and d[3] == 0
