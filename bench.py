@@ -28,8 +28,9 @@ on the differentiation workload; and the FP64 CPU oracle on a bounded sample (``
 Other modes (one JSON line each, not the headline): ``--workload bunch`` (the bunch workload as
 the headline), ``--workload large`` (one full-size pass of that configuration, mixed against
 FP64, with the full-size adjoint), ``--cost-model`` (refit of the wall-clock model constants and
-the TD/FD crossover) and ``--accuracy`` (the single-electron accuracy experiment against a
-converged reference and the oracle).
+the TD/FD crossover), ``--accuracy`` (the single-electron accuracy experiment against a
+converged reference and the oracle) and ``--det`` (the order-independent FP64 deposit against the
+atomics-order one on the bunch workload).
 """
 from __future__ import annotations
 
@@ -105,6 +106,9 @@ def parse():
     p.add_argument("--accuracy", action="store_true",
                    help="instead of the headline step: the single-electron accuracy experiment (Eq. "
                         "spectra_error of TD and FD against a converged FP64 FD reference and the oracle)")
+    p.add_argument("--det", action="store_true",
+                   help="instead of the headline step: the bunch workload in FP64 through lw_deposit_td and "
+                        "lw_deposit_td_det (times, run-to-run bit equality of each, their difference)")
     p.add_argument("--copy-calibration-gib", type=float, default=0.0,
                    help="run a plain device copy of this many GiB first (scale for HBM byte counters)")
     return p.parse_args()
@@ -130,6 +134,9 @@ def main():
         return 0
     if args.accuracy:
         print(json.dumps(accuracy(torch, dev)), flush=True)
+        return 0
+    if args.det:
+        print(json.dumps(det_leg(torch, dev)), flush=True)
         return 0
     if args.copy_calibration_gib > 0:
         n = int(args.copy_calibration_gib * (1 << 30)) // 4
@@ -443,6 +450,52 @@ def bunch_leg(torch, dev, args):
     del r, b, bd
     torch.cuda.empty_cache()
     return out
+
+
+def det_leg(torch, dev, reps=2):
+    """The bunch workload (1e4 e-, 2e4 stored Boris steps, 64 x 64 px, 2^18 grid), FP64: the
+    atomics-order deposit against the order-independent one.  Each is run `reps` times after a
+    warm-up; reported: mean wall time of a call, whether its outputs are bit-identical across the
+    runs (and how many elements differ), and max |E_det - E_fp64| / max |E_fp64|."""
+    from paper_2206_03015_amd import inputs, lw
+    W = inputs.workload("bunch")
+    L = W.laser
+    init = torch.as_tensor(inputs.bunch_init(W), device=dev)
+    r, b, bd = lw.trajectory_boris(init, W.n_samples, W.t_start, W.dt, L.a0, L.lam, L.w0, L.n_cycles)
+    x_det = torch.as_tensor(inputs.pixel_positions(W.n_side, W.theta_max, W.D), device=dev)
+    n_pix, n_obs = W.n_pix, W.n_obs
+    ws = torch.empty(lw.workspace_bytes(lw.WS_DEPOSIT, W.n_p, W.n_samples, "fp64"), dtype=torch.uint8, device=dev)
+    acc = torch.empty(lw.workspace_bytes(lw.WS_DEPOSIT_DET_ACC, n_pix, n_obs, "fp64"), dtype=torch.uint8,
+                      device=dev)
+    E = [torch.empty((n_pix, 3, n_obs), dtype=torch.float64, device=dev) for _ in range(2)]
+    calls = {
+        "fp64": lambda o: lw.deposit_td(r, b, bd, W.t_start, W.dt, x_det, W.t0, W.dt_obs, n_obs, prec="fp64", out=o,
+                                        ws=ws),
+        "det": lambda o: lw.deposit_td_det(r, b, bd, W.t_start, W.dt, x_det, W.t0, W.dt_obs, n_obs, out=o, ws=ws,
+                                           acc=acc),
+    }
+    res = {"workload": "bunch", "n_particles": W.n_p, "n_samples": W.n_samples, "n_pix": n_pix, "n_obs": n_obs}
+    ref = None
+    for name, fn in calls.items():
+        fn(E[0])
+        ms = []
+        for i in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            fn(E[i % 2])
+            torch.cuda.synchronize()
+            ms.append((time.time() - t0) * 1e3)
+        a, c = E[0].view(torch.int64), E[1].view(torch.int64)
+        res[name] = {"ms": float(np.mean(ms)), "bit_identical": bool(torch.equal(a, c)),
+                     "elements_differing": int((a != c).sum())}
+        log(f"[bench] det leg, {name}: {res[name]['ms']:.1f} ms per call, runs bit-identical "
+            f"{res[name]['bit_identical']} ({res[name]['elements_differing']} of {a.numel()} elements differ)")
+        if ref is None:
+            ref = E[0].clone()
+        else:
+            res["max_rel_diff_det_vs_fp64"] = float((E[0] - ref).abs().max() / ref.abs().max())
+    res["det_over_fp64"] = res["det"]["ms"] / res["fp64"]["ms"]
+    return res
 
 
 def fd_leg(torch, dev, W, r, b, bd, x_det, td_ms_per_step, geom, n_fd_pix=64, n_w=4096):
