@@ -118,3 +118,25 @@ def test_det_degenerate_sizes():
     far = dict(c, t0=c["t0"] + 1e-9)
     E, d = det_samples(far)
     assert not np.any(bits(E)) and d[3] == 0
+
+
+def test_det_careful_path():
+    """Unusable samples (NaN, |beta| = 1), swapped samples (non-monotone arrival times) and a
+    pixel at the origin send particles down the careful path: the oracle's trace and counters,
+    and the same bits with the particles reversed."""
+    c = synthetic(n_p=4, seed=3)
+    c["r"] = c["r"].copy()
+    c["beta"] = c["beta"].copy()
+    c["beta"][1, 100, 0] = np.nan
+    c["beta"][2, 50] = [0.0, 0.0, 1.0]
+    c["r"][3, 300:303] = c["r"][3, 300:303][::-1]
+    c["x_det"] = c["x_det"].copy()
+    c["x_det"][5] = 0.0
+    Eo, do = oracle.deposit_td(c["t_start"], c["dt"], c["r"], c["beta"], c["beta_dot"], c["x_det"], c["t0"],
+                               c["dt_obs"], c["n_obs"])
+    assert do[0] > 0 and do[1] > 0
+    E, d = det_samples(c)
+    assert d.tolist() == list(do)
+    assert np.max(np.abs(E.cpu().numpy() - Eo)) <= 1e-9 * np.max(np.abs(Eo))
+    Er, dr = det_samples(c, perm=np.arange(4)[::-1].copy())
+    assert np.array_equal(bits(Er), bits(E)) and dr.tolist() == d.tolist()
