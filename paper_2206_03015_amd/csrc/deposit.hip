@@ -445,10 +445,12 @@ struct Wave {
         if (ACC == kAccMaxAbs) {
             atomicMax(lo, (unsigned long long)__double_as_longlong(fabs(v)));
         } else {
-            // |v * scale| < 2^62 wherever scale is finite; the sign-extended term is added to the
-            // 128-bit sum as its low word and, with the carry out of the low word, its high word
+            // |v * scale| < 2^62 by the choice of scale, and any term below 2^63 is taken, so a
+            // last-bit difference between the two passes' v cannot drop one (a NaN scale drops
+            // all: the row is NaN in the result).  The sign-extended term is added to the 128-bit
+            // sum as its low word and, with the carry out of the low word, its high word.
             const double t = v * det.scale[row];
-            const long long n = fabs(t) < 0x1p62 ? (long long)__builtin_rint(t) : 0ll;
+            const long long n = fabs(t) < 0x1p63 ? (long long)__builtin_rint(t) : 0ll;
             if (n != 0) {
                 const unsigned long long un = (unsigned long long)n;
                 const unsigned long long old = atomicAdd(lo, un);
