@@ -215,8 +215,8 @@ lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, 
  * Two deposits compute the same contributions v: the first keeps max |v| per element
  * (an order-free maximum), which sets a power-of-two scale s per trace row (pixel and
  * component) with |v| s < 2^62; the second adds round(v s) to a 128-bit fixed-point
- * integer per element, whose sum no ordering changes; each sum is then divided by s
- * (one rounding).  The rounding of a contribution is at most 2^-62 of its row's largest
+ * integer per element, whose sum no ordering changes; each sum is then converted and
+ * divided by s (within one ulp).  The rounding of a contribution is at most 2^-62 of its row's largest
  * contribution, so the result agrees with lw_deposit_td's FP64 sum to rounding.  About
  * twice the time of the FP64 call.  A row that receives a non-finite contribution is
  * NaN throughout.
@@ -228,7 +228,8 @@ lw_status lw_deposit_td(const lw_traj_t *traj, const lw_grid_t *grid, int prec, 
  * E:          [n_pix][3][n_obs] double, overwritten.
  * acc:        device buffer of acc_bytes >= lw_workspace_bytes(LW_WS_DEPOSIT_DET_ACC,
  *             n_pix, n_obs, LW_PREC_FP64), 256-byte aligned, owned by the caller; its
- *             contents on entry are ignored (LW_E_WORKSPACE if smaller or NULL).
+ *             contents on entry are ignored (LW_E_WORKSPACE if smaller or NULL,
+ *             LW_E_ALIGN if misaligned).
  */
 lw_status lw_deposit_td_det(const lw_traj_t *traj, const lw_grid_t *grid, int field_mask, int geom, double *E,
                             int64_t *diag, void *acc, size_t acc_bytes, void *ws, size_t ws_bytes, hipStream_t stream);
